@@ -1,0 +1,178 @@
+/*
+ * ah.h -- C ABI of the MI355X Abelian-Higgs lattice library (libah.so).
+ *
+ * One handle evolves one periodic comoving N^3 lattice of the U(1)
+ * Abelian-Higgs model in a flat FRW background, in temporal gauge, with the
+ * staggered leapfrog / Crank-Nicolson discretisation of Correia & Martins,
+ * "Abelian-Higgs cosmic string evolution with multiple GPUs", section 2:
+ *
+ *   (1+delta) Pi^{n+1/2}  = (1-delta) Pi^{n-1/2}
+ *                            + deta [ D_j^- D_j^+ phi^n - (lambda0/2) f_n (|phi^n|^2 - sigma^2) phi^n ]
+ *   (1+omega) E_i^{n+1/2} = (1-omega) E_i^{n-1/2}
+ *                            + deta [ -sum_{j!=i} d_j^- F_ij^n + 2 e0^2 f_n Im(phi^* D_i^+ phi)^n ]
+ *   phi^{n+1} = phi^n + deta Pi^{n+1/2},   A_i^{n+1} = A_i^n + deta E_i^{n+1/2}
+ *
+ * with links U_j = exp(-i dx A_j), the covariant Laplacian
+ * D_j^- D_j^+ phi^x = sum_j [U_j^x phi^{x+j} - 2 phi^x + conj(U_j^{x-j}) phi^{x-j}] / dx^2,
+ * the compact plaquette field strength F_ij = sin(Theta_ij)/dx^2 with
+ * Theta_ij^x = dx (A_i^x + A_j^{x+i} - A_i^{x+j} - A_j^x) (or Theta/dx^2 for
+ * the non-compact action), a(eta) = (eta/eta_ref)^m, f = a^(2s),
+ * delta = (alpha/2) m deta/eta and omega = (1-s) delta (section 2, damping
+ * coefficients and coupling scaling).
+ *
+ * Diagnostics (section 2, string-separation and velocity estimators):
+ * xi_W from gauge-invariant plaquette windings, xi_L from the Lagrangian
+ * sum, <v^2>_phi = 2R/(1+R) with the Lagrangian-weighted ratio R, plus the
+ * energy split and the discrete Gauss-law residual.
+ *
+ * Conventions
+ *   - site index idx = x0 + N*(x1 + N*x2); periodic in all three directions.
+ *   - host state buffers are structure-of-arrays FP64, 10*N^3 doubles, in the
+ *     component order phi_re, phi_im, pi_re, pi_im, A0, A1, A2, E0, E1, E2;
+ *     they are owned by the caller and only read or written during the call.
+ *   - snapshot n holds phi, A at eta_n = eta0 + n*deta and Pi, E at eta_n - deta/2.
+ *   - every function returns AH_OK (0) or a negative AH_E_* code and never
+ *     throws across the ABI; ah_last_error() gives the text of the last error
+ *     on a handle (including the HIP error string for AH_E_DEVICE).
+ *   - numerical trouble (blow-up) is not an error: it is reported in
+ *     ah_measurement.flags and .nonfinite.
+ *   - threading: a handle must be used from one host thread at a time;
+ *     distinct handles are independent.
+ *   - all device work of a handle is enqueued on the HIP stream given at
+ *     creation (NULL = the null stream).  Calls documented "asynchronous"
+ *     return before the GPU has finished; kernel errors surface at the next
+ *     synchronising call.
+ */
+#ifndef AH_H
+#define AH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define AH_OK 0
+#define AH_E_INVAL (-1)  /* bad argument or parameter */
+#define AH_E_NOMEM (-2)  /* device allocation failed or arena too small */
+#define AH_E_DEVICE (-3) /* HIP runtime error; see ah_last_error */
+#define AH_E_STATE (-4)  /* call out of order (e.g. step before init) */
+#define AH_E_AGAIN (-5)  /* resource busy or full now; retry later */
+
+#define AH_FP64 0
+#define AH_FP32 1
+
+#define AH_COMPACT 0    /* F = sin(Theta)/dx^2 (compact Wilson action) */
+#define AH_NONCOMPACT 1 /* F = Theta/dx^2 */
+
+#define AH_FLAG_UNSTABLE 1u  /* leapfrog stability margin deta*sqrt(max(lambda0,2e0^2) f sigma^2 + 12/dx^2) >= 2 */
+#define AH_FLAG_NONFINITE 2u /* some field value is NaN or Inf */
+
+/* --------------------------------------------------------------- params */
+typedef struct ah_params {
+    int32_t N;            /* lattice side, N >= 4 */
+    int32_t precision;    /* AH_FP64 or AH_FP32: type of the stored fields and of the step arithmetic */
+    int32_t gauge_action; /* AH_COMPACT or AH_NONCOMPACT */
+    int32_t reserved;     /* must be 0 */
+    double dx, deta;      /* lattice spacing and conformal time step (section 2: 0.5, 0.1) */
+    double lambda0, e0, sigma; /* couplings and vacuum expectation value (section 2: 2, 1, 1) */
+    double m;             /* d ln a / d ln eta: 0 flat, 1 radiation, 2 matter */
+    double alpha;         /* damping multiplier; 2 is Crank-Nicolson Hubble friction */
+    double s_early, s_late, eta_switch; /* s = s_early for eta < eta_switch, else s_late */
+    double eta0;          /* initial conformal time (section 2: 1) */
+    double eta_ref;       /* a(eta_ref) = 1; <= 0 selects the half light-crossing time dx*N/2 */
+} ah_params;
+
+/* Fill *p with the paper's standard choices (section 2): N = 64, FP64,
+ * compact, dx = 0.5, deta = 0.1, lambda0 = 2, e0 = 1, sigma = 1, m = 1,
+ * alpha = 2, s = 0 throughout, eta0 = 1, eta_ref = dx*N/2. */
+int ah_params_default(ah_params* p);
+
+/* ---------------------------------------------------------- measurement */
+typedef struct ah_measurement {
+    int64_t step;               /* snapshot index n */
+    double eta, a, f;           /* eta_n, a(eta_n), f_n = a^(2 s_n) */
+    int64_t winding_sum_abs;    /* sum over sites and orientations i<j of |W_ij| (exact) */
+    double L_W, xi_W;           /* dx * winding_sum_abs ; sqrt((N dx)^3 / L_W) */
+    double sum_L, xi_L;         /* dx^3 sum_x L_x ; sqrt(-2 pi sigma^2 (N dx)^3 / sum_L) (NaN if sum_L >= 0) */
+    double R, v2_phi;           /* sum |Pi|^2 L / sum |D+phi|^2 L ; 2R/(1+R) */
+    double energy, e_kin, e_grad, e_pot, e_el, e_mag; /* dx^3-weighted sums with centred momenta */
+    double gauss_rms, gauss_max, gauss_rel; /* norms of the Gauss residual G^x */
+    int64_t nonfinite;          /* sites with a non-finite field value */
+    uint32_t flags;             /* AH_FLAG_* */
+    uint32_t reserved;
+} ah_measurement;
+
+typedef struct ah_handle ah_handle;
+
+/* Device bytes one lattice needs: 15 field arrays (10 state + phi/A ping-pong)
+ * of N^3 reals each, plus reduction scratch.  AH_E_INVAL on bad params. */
+int ah_required_bytes(const ah_params* p, size_t* bytes);
+
+/* Create a handle on the current HIP device.
+ *   dev_arena == NULL: the library allocates (hipMalloc) and owns the memory.
+ *   else: dev_arena is device memory of at least ah_required_bytes bytes,
+ *         256-byte aligned, owned by the caller, which keeps it alive until
+ *         ah_destroy returns (AH_E_NOMEM if arena_bytes is too small).
+ *   hip_stream: a hipStream_t (NULL = null stream) on which all work runs.
+ * The lattice is uninitialised until ah_init or ah_set_state. */
+int ah_create(const ah_params* p, void* dev_arena, size_t arena_bytes, void* hip_stream, ah_handle** out);
+
+/* Random-phase initial condition at eta0, step 0 (section 2): phi = sigma
+ * exp(2 pi i u_x) with u_x = (SplitMix64(seed) output number idx >> 11) *
+ * 2^-53 evaluated in FP64 (rounded to the storage type), Pi = A = E = 0.
+ * Asynchronous. */
+int ah_init(ah_handle* h, uint64_t seed);
+
+/* Upload a host FP64 SoA state (10*N^3 doubles, see conventions) as snapshot
+ * `step` (>= 0).  Values are rounded to the storage type.  Synchronous. */
+int ah_set_state(ah_handle* h, const double* host_soa, int64_t step);
+
+/* Download the current snapshot as FP64 SoA (10*N^3 doubles) and its step
+ * index (step may be NULL).  Synchronous. */
+int ah_get_state(ah_handle* h, double* host_soa, int64_t* step);
+
+/* Current snapshot index (host-side counter; no synchronisation). */
+int ah_get_step(const ah_handle* h, int64_t* step);
+
+/* Advance nsteps (>= 0) full leapfrog steps (kick + drift).  Asynchronous.
+ * AH_E_STATE before ah_init/ah_set_state. */
+int ah_step(ah_handle* h, int64_t nsteps);
+
+/* All diagnostics of the current snapshot, reduced in FP64 in a fixed order
+ * (bitwise reproducible for a given handle configuration).  Windings are
+ * computed in FP64 from the stored values even for FP32 lattices.  The
+ * snapshot is not modified.  Synchronous. */
+int ah_measure(ah_handle* h, ah_measurement* out);
+
+/* Per-plaquette windings of the current snapshot: 3*N^3 int8 values,
+ * orientation-major ((0,1), (0,2), (1,2)), site index inside.  Allocates a
+ * temporary device buffer of 3*N^3 bytes.  Synchronous. */
+int ah_get_winding(ah_handle* h, int8_t* host_w);
+
+/* Wait for all work enqueued on the handle's stream. */
+int ah_synchronize(ah_handle* h);
+
+/* Step-kernel timing with HIP events on the handle's stream.  While enabled
+ * every step-kernel launch is bracketed by an event pair; ah_get_timing
+ * synchronises and returns the summed kernel time (ms) and the number of
+ * timed launches since the last enable.  Lattice results do not change. */
+int ah_set_timing(ah_handle* h, int enable);
+int ah_get_timing(ah_handle* h, double* total_ms, int64_t* launches);
+
+/* Free what the library allocated; the handle is invalid afterwards. */
+int ah_destroy(ah_handle* h);
+
+/* Static description of an error code. */
+const char* ah_strerror(int code);
+
+/* Text of the last error on h ("" if none); valid until the next call on h. */
+const char* ah_last_error(const ah_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AH_H */

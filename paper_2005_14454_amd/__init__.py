@@ -1,0 +1,179 @@
+"""MI355X-native Abelian-Higgs lattice evolution (Correia & Martins, section 2).
+
+Python binding of libah.so.  Every step of the path runs in the HIP kernels
+behind the C ABI of include/ah.h; this module only marshals arguments.
+PyTorch provides device memory (the lattice arena) and the HIP stream.
+"""
+import ctypes
+import math
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+from . import _lib
+from ._lib import AHError, AH_FP32, AH_FP64, AH_COMPACT, AH_NONCOMPACT, AH_FLAG_NONFINITE, AH_FLAG_UNSTABLE
+
+__all__ = ["Params", "Lattice", "AHError", "AH_FP32", "AH_FP64", "AH_COMPACT", "AH_NONCOMPACT",
+           "AH_FLAG_NONFINITE", "AH_FLAG_UNSTABLE", "required_bytes"]
+
+
+@dataclass
+class Params:
+    """Lattice and model parameters (section 2 standard choices as defaults).
+
+    precision: "fp64" or "fp32"; gauge_action: "compact" or "noncompact";
+    eta_ref <= 0 selects a(dx*N/2) = 1."""
+    N: int = 64
+    precision: str = "fp64"
+    gauge_action: str = "compact"
+    dx: float = 0.5
+    deta: float = 0.1
+    lambda0: float = 2.0
+    e0: float = 1.0
+    sigma: float = 1.0
+    m: float = 1.0
+    alpha: float = 2.0
+    s_early: float = 0.0
+    s_late: float = 0.0
+    eta_switch: float = math.inf
+    eta0: float = 1.0
+    eta_ref: float = 0.0
+
+    def to_c(self) -> _lib.ah_params:
+        c = _lib.ah_params()
+        for f in fields(self):
+            v = getattr(self, f.name)
+            if f.name == "precision":
+                v = {"fp64": AH_FP64, "fp32": AH_FP32}[v]
+            elif f.name == "gauge_action":
+                v = {"compact": AH_COMPACT, "noncompact": AH_NONCOMPACT}[v]
+            setattr(c, f.name, v)
+        c.reserved = 0
+        return c
+
+    @property
+    def eta_end(self) -> float:
+        return 0.5 * self.dx * self.N
+
+
+def required_bytes(p: Params) -> int:
+    lib = _lib.load()
+    n = ctypes.c_size_t()
+    _lib.check(lib.ah_required_bytes(ctypes.byref(p.to_c()), ctypes.byref(n)), what="ah_required_bytes")
+    return n.value
+
+
+def _meas_dict(m: _lib.ah_measurement) -> dict:
+    return {k: getattr(m, k) for k, _ in _lib.ah_measurement._fields_ if k != "reserved"}
+
+
+class Lattice:
+    """One periodic N^3 lattice resident on the GPU.
+
+    arena="torch": the arena is a torch uint8 tensor owned by this object;
+    arena="library": libah hipMallocs and frees it.  stream: a torch.cuda.Stream
+    (default: the current stream of the device)."""
+
+    def __init__(self, params: Params, device=None, stream=None, arena: str = "torch"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lattice library has no CPU path")
+        lib = _lib.load()
+        self.params = params
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self._torch = torch
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            cp = params.to_c()
+            nbytes = required_bytes(params)
+            self._arena = None
+            ptr, size = None, 0
+            if arena == "torch":
+                self._arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+                base = self._arena.data_ptr()
+                ptr = (base + 255) // 256 * 256
+                size = nbytes
+            elif arena != "library":
+                raise ValueError("arena must be 'torch' or 'library'")
+            h = ctypes.c_void_p()
+            _lib.check(lib.ah_create(ctypes.byref(cp), ptr, size, self.stream.cuda_stream, ctypes.byref(h)),
+                       what="ah_create")
+            self._h = h
+        self._lib = lib
+        self.N = params.N
+        self.V = params.N ** 3
+
+    # -- lifecycle -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            with self._torch.cuda.device(self.device):
+                self._lib.ah_destroy(self._h)
+            self._h = None
+            self._arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _call(self, fn, *args, what=""):
+        with self._torch.cuda.device(self.device):
+            _lib.check(fn(self._h, *args), self._h, what)
+
+    # -- evolution -------------------------------------------------------------
+    def init(self, seed: int):
+        self._call(self._lib.ah_init, ctypes.c_uint64(seed), what="ah_init")
+
+    def step(self, nsteps: int = 1):
+        self._call(self._lib.ah_step, nsteps, what="ah_step")
+
+    def measure(self) -> dict:
+        m = _lib.ah_measurement()
+        self._call(self._lib.ah_measure, ctypes.byref(m), what="ah_measure")
+        return _meas_dict(m)
+
+    def synchronize(self):
+        self._call(self._lib.ah_synchronize, what="ah_synchronize")
+
+    @property
+    def step_index(self) -> int:
+        s = ctypes.c_int64()
+        _lib.check(self._lib.ah_get_step(self._h, ctypes.byref(s)))
+        return s.value
+
+    # -- state I/O -------------------------------------------------------------
+    def set_state(self, state: np.ndarray, step: int = 0):
+        st = np.ascontiguousarray(state, dtype=np.float64)
+        if st.size != 10 * self.V:
+            raise ValueError(f"state has {st.size} values, expected {10 * self.V}")
+        self._call(self._lib.ah_set_state, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), step,
+                   what="ah_set_state")
+
+    def get_state(self) -> np.ndarray:
+        st = np.empty((10, self.V), dtype=np.float64)
+        s = ctypes.c_int64()
+        self._call(self._lib.ah_get_state, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(s),
+                   what="ah_get_state")
+        return st
+
+    def winding(self) -> np.ndarray:
+        w = np.empty((3, self.V), dtype=np.int8)
+        self._call(self._lib.ah_get_winding, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), what="ah_get_winding")
+        return w
+
+    # -- timing ----------------------------------------------------------------
+    def set_timing(self, enable: bool):
+        self._call(self._lib.ah_set_timing, 1 if enable else 0, what="ah_set_timing")
+
+    def get_timing(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._call(self._lib.ah_get_timing, ctypes.byref(ms), ctypes.byref(n), what="ah_get_timing")
+        return ms.value, n.value

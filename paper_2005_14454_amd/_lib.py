@@ -1,0 +1,103 @@
+"""ctypes declarations of the C ABI in include/ah.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libah.so")
+
+AH_OK = 0
+AH_E_INVAL = -1
+AH_E_NOMEM = -2
+AH_E_DEVICE = -3
+AH_E_STATE = -4
+AH_E_AGAIN = -5
+
+AH_FP64 = 0
+AH_FP32 = 1
+AH_COMPACT = 0
+AH_NONCOMPACT = 1
+AH_FLAG_UNSTABLE = 1
+AH_FLAG_NONFINITE = 2
+
+
+class ah_params(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int32), ("precision", ctypes.c_int32), ("gauge_action", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("deta", ctypes.c_double),
+        ("lambda0", ctypes.c_double), ("e0", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("m", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("s_early", ctypes.c_double), ("s_late", ctypes.c_double), ("eta_switch", ctypes.c_double),
+        ("eta0", ctypes.c_double), ("eta_ref", ctypes.c_double),
+    ]
+
+
+class ah_measurement(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("eta", ctypes.c_double), ("a", ctypes.c_double), ("f", ctypes.c_double),
+        ("winding_sum_abs", ctypes.c_int64), ("L_W", ctypes.c_double), ("xi_W", ctypes.c_double),
+        ("sum_L", ctypes.c_double), ("xi_L", ctypes.c_double), ("R", ctypes.c_double), ("v2_phi", ctypes.c_double),
+        ("energy", ctypes.c_double), ("e_kin", ctypes.c_double), ("e_grad", ctypes.c_double),
+        ("e_pot", ctypes.c_double), ("e_el", ctypes.c_double), ("e_mag", ctypes.c_double),
+        ("gauss_rms", ctypes.c_double), ("gauss_max", ctypes.c_double), ("gauss_rel", ctypes.c_double),
+        ("nonfinite", ctypes.c_int64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+    ]
+
+
+class AHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libah.so; raises if the HIP library has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built: run paper_2005_14454_amd.build.build() "
+                           "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    sig = {
+        "ah_params_default": ([P(ah_params)], ctypes.c_int),
+        "ah_required_bytes": ([P(ah_params), P(ctypes.c_size_t)], ctypes.c_int),
+        "ah_create": ([P(ah_params), vp, ctypes.c_size_t, vp, P(vp)], ctypes.c_int),
+        "ah_init": ([vp, ctypes.c_uint64], ctypes.c_int),
+        "ah_set_state": ([vp, P(ctypes.c_double), i64], ctypes.c_int),
+        "ah_get_state": ([vp, P(ctypes.c_double), P(i64)], ctypes.c_int),
+        "ah_get_step": ([vp, P(i64)], ctypes.c_int),
+        "ah_step": ([vp, i64], ctypes.c_int),
+        "ah_measure": ([vp, P(ah_measurement)], ctypes.c_int),
+        "ah_get_winding": ([vp, P(ctypes.c_int8)], ctypes.c_int),
+        "ah_synchronize": ([vp], ctypes.c_int),
+        "ah_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
+        "ah_get_timing": ([vp, P(ctypes.c_double), P(i64)], ctypes.c_int),
+        "ah_destroy": ([vp], ctypes.c_int),
+        "ah_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "ah_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(rc, handle=None, what=""):
+    if rc == AH_OK:
+        return
+    lib = load()
+    msg = lib.ah_strerror(rc).decode()
+    if handle:
+        detail = lib.ah_last_error(handle).decode()
+        if detail:
+            msg = f"{msg}: {detail}"
+    raise AHError(rc, f"{what}: {msg}" if what else msg)

@@ -1,0 +1,87 @@
+// Internal declarations shared by the host runtime and the HIP kernels of libah.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ah {
+
+// Structure-of-arrays field pointers of one lattice snapshot.  phi and A come
+// from the current ping-pong buffer, Pi and E are single buffers updated in
+// place; the drift writes phi and A into the other ping-pong buffer.
+template <typename R>
+struct Fields {
+    R* phr;
+    R* phi;
+    R* pir;
+    R* pii;
+    R* a0;
+    R* a1;
+    R* a2;
+    R* e0;
+    R* e1;
+    R* e2;
+};
+
+// Per-step scalars of the update, formed on the host in FP64 and rounded to
+// the storage type (kick: X^{n+1/2} = c1 X^{n-1/2} + c2 force).
+struct StepCoef {
+    double cP1, cP2;   // (1-delta)/(1+delta), deta/(1+delta)
+    double cE1, cE2;   // (1-omega)/(1+omega), deta/(1+omega)
+    double lam_half;   // lambda0 f / 2
+    double kappa;      // 2 e0^2 f
+};
+
+// Lattice-wide constants.
+struct LatticeConst {
+    int N;
+    int compact;
+    double dx, deta, sigma2;
+};
+
+// Diagnostics reduction slots (FP64 sums over sites unless noted).
+enum MeasSlot {
+    M_KIN = 0,   // |Pi_bar|^2
+    M_GRAD,      // sum_i |D_i^+ phi|^2
+    M_POT,       // lambda0 f/4 (|phi|^2 - sigma^2)^2
+    M_EL,        // sum_i E_bar_i^2 / (2 e0^2 f)
+    M_MAG,       // sum_{i<j} B_ij^2 / (2 e0^2 f)
+    M_L,         // Lagrangian density
+    M_KINL,      // |Pi_bar|^2 L
+    M_GRADL,     // sum_i |D_i^+ phi|^2 L
+    M_G2,        // G^2
+    M_DIV2,      // (div E)^2
+    M_CRHO2,     // (c rho)^2
+    M_GMAX,      // max |G|   (max-reduced)
+    M_WABS,      // sum_{i<j} |W_ij|  (exact integer in FP64)
+    M_NONFIN,    // count of sites with a non-finite value
+    M_COUNT
+};
+constexpr int kMeasStride = 16;        // doubles per partial record
+constexpr int kMeasBlocks = 2048;      // fixed grid of the measurement kernel
+constexpr int kMeasThreads = 256;
+
+struct MeasConst {
+    double inv_2e2f;   // 1 / (2 e0^2 f)
+    double lam_quarter;// lambda0 f / 4
+    double gauss_c;    // coupling of the Gauss residual
+};
+
+// ---- launchers (ah_kernels.hip) -------------------------------------------
+template <typename R>
+hipError_t launch_init(const Fields<R>& f, int N, double sigma, uint64_t seed, hipStream_t s);
+
+template <typename R>
+hipError_t launch_step(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2,
+                       const LatticeConst& L, const StepCoef& c, hipStream_t s);
+
+template <typename R>
+hipError_t launch_measure(const Fields<R>& f, const LatticeConst& L, const StepCoef& c,
+                          const MeasConst& mc, double* partials, double* result, hipStream_t s);
+
+template <typename R>
+hipError_t launch_winding(const Fields<R>& f, const LatticeConst& L, int8_t* w, hipStream_t s);
+
+}  // namespace ah

@@ -1,0 +1,572 @@
+// Host runtime of libah: parameter validation, device arena layout, the FP64
+// per-step coefficient formulas, phi/A ping-pong, state I/O, diagnostics
+// assembly and the C ABI declared in include/ah.h.
+#include "ah.h"
+#include "ah_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace ah;
+
+struct ah_handle {
+    ah_params p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool owns_arena = false;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    int64_t V = 0;
+    size_t real_bytes = 8;
+    // ping-pong phi/A buffers [2][5] (phr, phi, a0, a1, a2), then pir, pii, e0, e1, e2
+    void* pp[2][5] = {};
+    void* mom[5] = {};
+    double* partials = nullptr;
+    double* result = nullptr;
+    double* host_result = nullptr;  // pinned
+    int cur = 0;
+    int64_t step = 0;
+    bool ready = false;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // start/stop pairs
+    size_t ev_used = 0;
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int fail(ah_handle* h, int code, const std::string& msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+int hip_fail(ah_handle* h, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(h, AH_E_DEVICE, m);
+}
+
+double eta_ref_of(const ah_params& p) { return p.eta_ref > 0.0 ? p.eta_ref : 0.5 * p.dx * (double)p.N; }
+
+// Section 2 scalars at snapshot n.
+struct Scalars {
+    double eta, s, a, f, delta, omega;
+};
+Scalars scalars_at(const ah_params& p, int64_t n)
+{
+    Scalars r;
+    r.eta = p.eta0 + (double)n * p.deta;
+    r.s = r.eta < p.eta_switch ? p.s_early : p.s_late;
+    r.a = std::pow(r.eta / eta_ref_of(p), p.m);
+    r.f = std::pow(r.a, 2.0 * r.s);
+    r.delta = 0.5 * p.alpha * p.m * p.deta / r.eta;
+    r.omega = (1.0 - r.s) * r.delta;
+    return r;
+}
+
+StepCoef coef_at(const ah_params& p, int64_t n)
+{
+    const Scalars s = scalars_at(p, n);
+    StepCoef c;
+    c.cP1 = (1.0 - s.delta) / (1.0 + s.delta);
+    c.cP2 = p.deta / (1.0 + s.delta);
+    c.cE1 = (1.0 - s.omega) / (1.0 + s.omega);
+    c.cE2 = p.deta / (1.0 + s.omega);
+    c.lam_half = 0.5 * p.lambda0 * s.f;
+    c.kappa = 2.0 * p.e0 * p.e0 * s.f;
+    return c;
+}
+
+// Coupling c_{n-1/2} of the Gauss residual: the kick keeps
+// div E^{n-1/2} = c_{n-1/2} Im[conj(phi^n) Pi^{n-1/2}] exactly when
+// c_{n-1/2} = 2 e0^2 f_{n-1} (1+delta_{n-1}) / (1+omega_{n-1}); 2 e0^2 f_0 at n = 0.
+double gauss_coupling(const ah_params& p, int64_t n)
+{
+    if (n <= 0) return 2.0 * p.e0 * p.e0 * scalars_at(p, 0).f;
+    const Scalars s = scalars_at(p, n - 1);
+    return 2.0 * p.e0 * p.e0 * s.f * (1.0 + s.delta) / (1.0 + s.omega);
+}
+
+bool unstable_at(const ah_params& p, int64_t n)
+{
+    const Scalars s = scalars_at(p, n);
+    const double g = std::fmax(p.lambda0, 2.0 * p.e0 * p.e0) * s.f * p.sigma * p.sigma + 12.0 / (p.dx * p.dx);
+    return p.deta * std::sqrt(g) >= 2.0;
+}
+
+int validate(const ah_params* p, std::string* why)
+{
+    if (!p) {
+        *why = "params is NULL";
+        return AH_E_INVAL;
+    }
+    if (p->N < 4 || p->N > 4096) {
+        *why = "N must be in [4, 4096]";
+        return AH_E_INVAL;
+    }
+    if (p->precision != AH_FP64 && p->precision != AH_FP32) {
+        *why = "precision must be AH_FP64 or AH_FP32";
+        return AH_E_INVAL;
+    }
+    if (p->gauge_action != AH_COMPACT && p->gauge_action != AH_NONCOMPACT) {
+        *why = "gauge_action must be AH_COMPACT or AH_NONCOMPACT";
+        return AH_E_INVAL;
+    }
+    if (p->reserved != 0) {
+        *why = "reserved must be 0";
+        return AH_E_INVAL;
+    }
+    if (!(p->dx > 0.0) || !(p->deta > 0.0) || !std::isfinite(p->dx) || !std::isfinite(p->deta)) {
+        *why = "dx and deta must be positive and finite";
+        return AH_E_INVAL;
+    }
+    if (!(p->eta0 > 0.0) || !std::isfinite(p->eta0)) {
+        *why = "eta0 must be positive";
+        return AH_E_INVAL;
+    }
+    if (!(p->e0 > 0.0) || !std::isfinite(p->lambda0) || !std::isfinite(p->sigma) || !std::isfinite(p->m) ||
+        !std::isfinite(p->alpha) || !std::isfinite(p->s_early) || !std::isfinite(p->s_late) ||
+        std::isnan(p->eta_switch) || !std::isfinite(p->eta_ref)) {
+        *why = "non-finite or invalid coupling / expansion parameter (e0 must be > 0)";
+        return AH_E_INVAL;
+    }
+    return AH_OK;
+}
+
+size_t field_bytes(const ah_params& p)
+{
+    const size_t V = (size_t)p.N * p.N * p.N;
+    return align_up(V * (p.precision == AH_FP64 ? 8 : 4));
+}
+
+size_t required_bytes(const ah_params& p)
+{
+    return 15 * field_bytes(p) + align_up((size_t)kMeasBlocks * kMeasStride * sizeof(double)) +
+           align_up(kMeasStride * sizeof(double));
+}
+
+template <typename R>
+Fields<R> fields_of(const ah_handle* h, int buf)
+{
+    Fields<R> f;
+    f.phr = (R*)h->pp[buf][0];
+    f.phi = (R*)h->pp[buf][1];
+    f.a0 = (R*)h->pp[buf][2];
+    f.a1 = (R*)h->pp[buf][3];
+    f.a2 = (R*)h->pp[buf][4];
+    f.pir = (R*)h->mom[0];
+    f.pii = (R*)h->mom[1];
+    f.e0 = (R*)h->mom[2];
+    f.e1 = (R*)h->mom[3];
+    f.e2 = (R*)h->mom[4];
+    return f;
+}
+
+LatticeConst lconst(const ah_params& p)
+{
+    LatticeConst L;
+    L.N = p.N;
+    L.compact = p.gauge_action == AH_COMPACT ? 1 : 0;
+    L.dx = p.dx;
+    L.deta = p.deta;
+    L.sigma2 = p.sigma * p.sigma;
+    return L;
+}
+
+// component c of the state (order phi_re, phi_im, pi_re, pi_im, A0..2, E0..2)
+void* comp_ptr(ah_handle* h, int c)
+{
+    switch (c) {
+    case 0: return h->pp[h->cur][0];
+    case 1: return h->pp[h->cur][1];
+    case 2: return h->mom[0];
+    case 3: return h->mom[1];
+    case 4: return h->pp[h->cur][2];
+    case 5: return h->pp[h->cur][3];
+    case 6: return h->pp[h->cur][4];
+    default: return h->mom[c - 5];
+    }
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int now = -1;
+        if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename R>
+hipError_t do_step(ah_handle* h)
+{
+    const Fields<R> in = fields_of<R>(h, h->cur);
+    const Fields<R> out = fields_of<R>(h, h->cur ^ 1);
+    const StepCoef c = coef_at(h->p, h->step);
+    hipError_t e;
+    if (h->timing) {
+        if (h->ev_used + 2 > h->ev.size()) {
+            for (int k = 0; k < 2; ++k) {
+                hipEvent_t ev;
+                e = hipEventCreate(&ev);
+                if (e != hipSuccess) return e;
+                h->ev.push_back(ev);
+            }
+        }
+        e = hipEventRecord(h->ev[h->ev_used], h->stream);
+        if (e != hipSuccess) return e;
+    }
+    e = launch_step<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, h->stream);
+    if (e != hipSuccess) return e;
+    if (h->timing) {
+        e = hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+        if (e != hipSuccess) return e;
+        h->ev_used += 2;
+    }
+    h->cur ^= 1;
+    h->step += 1;
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ah_params_default(ah_params* p)
+{
+    if (!p) return AH_E_INVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->N = 64;
+    p->precision = AH_FP64;
+    p->gauge_action = AH_COMPACT;
+    p->dx = 0.5;
+    p->deta = 0.1;
+    p->lambda0 = 2.0;
+    p->e0 = 1.0;
+    p->sigma = 1.0;
+    p->m = 1.0;
+    p->alpha = 2.0;
+    p->s_early = 0.0;
+    p->s_late = 0.0;
+    p->eta_switch = HUGE_VAL;
+    p->eta0 = 1.0;
+    p->eta_ref = 0.0;
+    return AH_OK;
+}
+
+int ah_required_bytes(const ah_params* p, size_t* bytes)
+{
+    std::string why;
+    int rc = validate(p, &why);
+    if (rc != AH_OK) return rc;
+    if (!bytes) return AH_E_INVAL;
+    *bytes = required_bytes(*p);
+    return AH_OK;
+}
+
+int ah_create(const ah_params* p, void* dev_arena, size_t arena_bytes, void* hip_stream, ah_handle** out)
+{
+    if (!out) return AH_E_INVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = validate(p, &why);
+    if (rc != AH_OK) {
+        std::fprintf(stderr, "ah_create: %s\n", why.c_str());
+        return rc;
+    }
+    ah_handle* h = new (std::nothrow) ah_handle;
+    if (!h) return AH_E_NOMEM;
+    h->p = *p;
+    h->stream = (hipStream_t)hip_stream;
+    h->V = (int64_t)p->N * p->N * p->N;
+    h->real_bytes = p->precision == AH_FP64 ? 8 : 4;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return AH_E_DEVICE;
+    }
+    const size_t need = required_bytes(*p);
+    if (dev_arena) {
+        if (arena_bytes < need || ((uintptr_t)dev_arena % kAlign) != 0) {
+            delete h;
+            return AH_E_NOMEM;
+        }
+        h->arena = dev_arena;
+        h->arena_bytes = arena_bytes;
+    } else {
+        e = hipMalloc(&h->arena, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete h;
+            return AH_E_NOMEM;
+        }
+        h->owns_arena = true;
+        h->arena_bytes = need;
+    }
+    char* base = (char*)h->arena;
+    const size_t fb = field_bytes(*p);
+    for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 5; ++c) {
+            h->pp[b][c] = base;
+            base += fb;
+        }
+    for (int c = 0; c < 5; ++c) {
+        h->mom[c] = base;
+        base += fb;
+    }
+    h->partials = (double*)base;
+    base += align_up((size_t)kMeasBlocks * kMeasStride * sizeof(double));
+    h->result = (double*)base;
+    e = hipHostMalloc((void**)&h->host_result, kMeasStride * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        if (h->owns_arena) (void)hipFree(h->arena);
+        delete h;
+        return AH_E_NOMEM;
+    }
+    *out = h;
+    return AH_OK;
+}
+
+int ah_init(ah_handle* h, uint64_t seed)
+{
+    if (!h) return AH_E_INVAL;
+    DeviceGuard g(h->device);
+    h->cur = 0;
+    h->step = 0;
+    hipError_t e = h->p.precision == AH_FP64
+                       ? launch_init<double>(fields_of<double>(h, 0), h->p.N, h->p.sigma, seed, h->stream)
+                       : launch_init<float>(fields_of<float>(h, 0), h->p.N, h->p.sigma, seed, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_init launch");
+    h->ready = true;
+    return AH_OK;
+}
+
+int ah_set_state(ah_handle* h, const double* host_soa, int64_t step)
+{
+    if (!h || !host_soa || step < 0) return fail(h, AH_E_INVAL, "ah_set_state: bad argument");
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_set_state sync");
+    h->cur = 0;
+    const size_t V = (size_t)h->V;
+    std::vector<float> tmp;
+    if (h->real_bytes == 4) tmp.resize(V);
+    for (int c = 0; c < 10; ++c) {
+        const double* src = host_soa + (size_t)c * V;
+        if (h->real_bytes == 8) {
+            e = hipMemcpyAsync(comp_ptr(h, c), src, V * 8, hipMemcpyHostToDevice, h->stream);
+        } else {
+            for (size_t i = 0; i < V; ++i) tmp[i] = (float)src[i];
+            e = hipMemcpyAsync(comp_ptr(h, c), tmp.data(), V * 4, hipMemcpyHostToDevice, h->stream);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "ah_set_state copy");
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_set_state sync");
+    }
+    h->step = step;
+    h->ready = true;
+    return AH_OK;
+}
+
+int ah_get_state(ah_handle* h, double* host_soa, int64_t* step)
+{
+    if (!h || !host_soa) return fail(h, AH_E_INVAL, "ah_get_state: bad argument");
+    if (!h->ready) return fail(h, AH_E_STATE, "ah_get_state before ah_init/ah_set_state");
+    DeviceGuard g(h->device);
+    const size_t V = (size_t)h->V;
+    std::vector<float> tmp;
+    if (h->real_bytes == 4) tmp.resize(V);
+    for (int c = 0; c < 10; ++c) {
+        double* dst = host_soa + (size_t)c * V;
+        hipError_t e;
+        if (h->real_bytes == 8) {
+            e = hipMemcpyAsync(dst, comp_ptr(h, c), V * 8, hipMemcpyDeviceToHost, h->stream);
+        } else {
+            e = hipMemcpyAsync(tmp.data(), comp_ptr(h, c), V * 4, hipMemcpyDeviceToHost, h->stream);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "ah_get_state copy");
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_get_state sync");
+        if (h->real_bytes == 4)
+            for (size_t i = 0; i < V; ++i) dst[i] = (double)tmp[i];
+    }
+    if (step) *step = h->step;
+    return AH_OK;
+}
+
+int ah_get_step(const ah_handle* h, int64_t* step)
+{
+    if (!h || !step) return AH_E_INVAL;
+    *step = h->step;
+    return AH_OK;
+}
+
+int ah_step(ah_handle* h, int64_t nsteps)
+{
+    if (!h || nsteps < 0) return fail(h, AH_E_INVAL, "ah_step: bad argument");
+    if (!h->ready) return fail(h, AH_E_STATE, "ah_step before ah_init/ah_set_state");
+    DeviceGuard g(h->device);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        hipError_t e = h->p.precision == AH_FP64 ? do_step<double>(h) : do_step<float>(h);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_step launch");
+    }
+    return AH_OK;
+}
+
+int ah_measure(ah_handle* h, ah_measurement* out)
+{
+    if (!h || !out) return fail(h, AH_E_INVAL, "ah_measure: bad argument");
+    if (!h->ready) return fail(h, AH_E_STATE, "ah_measure before ah_init/ah_set_state");
+    DeviceGuard g(h->device);
+    const ah_params& p = h->p;
+    const Scalars sc = scalars_at(p, h->step);
+    MeasConst mc;
+    mc.inv_2e2f = 1.0 / (2.0 * p.e0 * p.e0 * sc.f);
+    mc.lam_quarter = 0.25 * p.lambda0 * sc.f;
+    mc.gauss_c = gauss_coupling(p, h->step);
+    const StepCoef c = coef_at(p, h->step);
+    hipError_t e = p.precision == AH_FP64
+                       ? launch_measure<double>(fields_of<double>(h, h->cur), lconst(p), c, mc, h->partials,
+                                                h->result, h->stream)
+                       : launch_measure<float>(fields_of<float>(h, h->cur), lconst(p), c, mc, h->partials,
+                                               h->result, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_measure launch");
+    e = hipMemcpyAsync(h->host_result, h->result, M_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_measure copy");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_measure sync");
+    const double* r = h->host_result;
+
+    const double dx3 = p.dx * p.dx * p.dx;
+    const double vol = std::pow((double)p.N * p.dx, 3.0);
+    std::memset(out, 0, sizeof(*out));
+    out->step = h->step;
+    out->eta = sc.eta;
+    out->a = sc.a;
+    out->f = sc.f;
+    out->winding_sum_abs = (int64_t)r[M_WABS];
+    out->L_W = p.dx * r[M_WABS];
+    out->xi_W = std::sqrt(vol / out->L_W);
+    out->e_kin = dx3 * r[M_KIN];
+    out->e_grad = dx3 * r[M_GRAD];
+    out->e_pot = dx3 * r[M_POT];
+    out->e_el = dx3 * r[M_EL];
+    out->e_mag = dx3 * r[M_MAG];
+    out->energy = out->e_kin + out->e_grad + out->e_pot + out->e_el + out->e_mag;
+    out->sum_L = dx3 * r[M_L];
+    out->xi_L = out->sum_L < 0.0 ? std::sqrt(-2.0 * M_PI * p.sigma * p.sigma * vol / out->sum_L) : NAN;
+    out->R = r[M_KINL] / r[M_GRADL];
+    out->v2_phi = 2.0 * out->R / (1.0 + out->R);
+    out->gauss_rms = std::sqrt(r[M_G2] / (double)h->V);
+    out->gauss_max = r[M_GMAX];
+    const double den = std::sqrt(r[M_DIV2] + r[M_CRHO2]);
+    out->gauss_rel = den > 0.0 ? std::sqrt(r[M_G2]) / den : 0.0;
+    out->nonfinite = (int64_t)r[M_NONFIN];
+    out->flags = (unstable_at(p, h->step) ? AH_FLAG_UNSTABLE : 0u) | (out->nonfinite ? AH_FLAG_NONFINITE : 0u);
+    return AH_OK;
+}
+
+int ah_get_winding(ah_handle* h, int8_t* host_w)
+{
+    if (!h || !host_w) return fail(h, AH_E_INVAL, "ah_get_winding: bad argument");
+    if (!h->ready) return fail(h, AH_E_STATE, "ah_get_winding before ah_init/ah_set_state");
+    DeviceGuard g(h->device);
+    int8_t* d = nullptr;
+    const size_t bytes = 3 * (size_t)h->V;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, AH_E_NOMEM, "ah_get_winding: cannot allocate the temporary winding buffer");
+    }
+    e = h->p.precision == AH_FP64 ? launch_winding<double>(fields_of<double>(h, h->cur), lconst(h->p), d, h->stream)
+                                  : launch_winding<float>(fields_of<float>(h, h->cur), lconst(h->p), d, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_w, d, bytes, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    hipError_t e2 = hipFree(d);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_get_winding");
+    if (e2 != hipSuccess) return hip_fail(h, e2, "ah_get_winding free");
+    return AH_OK;
+}
+
+int ah_synchronize(ah_handle* h)
+{
+    if (!h) return AH_E_INVAL;
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_synchronize");
+    return AH_OK;
+}
+
+int ah_set_timing(ah_handle* h, int enable)
+{
+    if (!h) return AH_E_INVAL;
+    h->timing = enable != 0;
+    h->ev_used = 0;
+    return AH_OK;
+}
+
+int ah_get_timing(ah_handle* h, double* total_ms, int64_t* launches)
+{
+    if (!h || !total_ms || !launches) return fail(h, AH_E_INVAL, "ah_get_timing: bad argument");
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing sync");
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing elapsed");
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)(h->ev_used / 2);
+    return AH_OK;
+}
+
+int ah_destroy(ah_handle* h)
+{
+    if (!h) return AH_E_INVAL;
+    DeviceGuard g(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t ev : h->ev) (void)hipEventDestroy(ev);
+    if (h->host_result) (void)hipHostFree(h->host_result);
+    if (h->owns_arena && h->arena) (void)hipFree(h->arena);
+    delete h;
+    return AH_OK;
+}
+
+const char* ah_strerror(int code)
+{
+    switch (code) {
+    case AH_OK: return "ok";
+    case AH_E_INVAL: return "invalid argument";
+    case AH_E_NOMEM: return "out of device memory or arena too small";
+    case AH_E_DEVICE: return "HIP device error";
+    case AH_E_STATE: return "call out of order";
+    case AH_E_AGAIN: return "resource busy; retry later";
+    default: return "unknown error";
+    }
+}
+
+const char* ah_last_error(const ah_handle* h)
+{
+    if (!h) return "";
+    return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,35 @@
+"""Test helpers: one parameter set expressed for both the oracle and the GPU binding,
+and the field-scaled error norm used for parity (per field f in {phi, Pi, A, E}:
+max_x |f_gpu - f_ref| / max_x |f_ref|, reported as the max over fields)."""
+import math
+
+import numpy as np
+
+FIELD_GROUPS = {"phi": (0, 1), "pi": (2, 3), "A": (4, 5, 6), "E": (7, 8, 9)}
+
+
+def both_params(oracle_mod, N, precision="fp64", **kw):
+    from paper_2005_14454_amd import Params
+    gauge = kw.pop("gauge_action", "compact")
+    op = oracle_mod.params(N=N, compact=1 if gauge == "compact" else 0, **kw)
+    gp = Params(N=N, precision=precision, gauge_action=gauge, **{k: v for k, v in op.items() if k not in ("N", "compact")})
+    return op, gp
+
+
+def field_scaled_error(got: np.ndarray, ref: np.ndarray) -> dict:
+    out = {}
+    for name, comps in FIELD_GROUPS.items():
+        g = got[list(comps)]
+        r = ref[list(comps)]
+        scale = np.max(np.abs(r))
+        diff = np.max(np.abs(g - r))
+        out[name] = diff / scale if scale > 0 else diff
+    return out
+
+
+def max_field_error(got, ref) -> float:
+    return max(field_scaled_error(got, ref).values())
+
+
+def ulp_distance(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    return np.abs(a - b) / np.spacing(np.maximum(np.abs(a), np.abs(b)))

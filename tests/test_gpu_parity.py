@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+identical seeded inputs.
+
+Tolerances (field-scaled max norm per field, max over phi, Pi, A, E):
+  one step from an identical FP64 snapshot      <= 1e-13
+  64^3 radiation era, 100 steps, FP64            <= 1e-10
+  64^3 radiation era, 100 steps, FP32 vs FP64    <= 1e-4
+  windings on identical snapshots                bit-exact
+  FP64 diagnostics on identical snapshots        <= 1e-11 relative
+"""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import both_params, field_scaled_error, max_field_error, ulp_distance
+from inputs import random_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ah():
+    import paper_2005_14454_amd as ah
+    return ah
+
+
+def _run_gpu(ah, gp, state, step0, nsteps):
+    with ah.Lattice(gp) as lat:
+        lat.set_state(state, step0)
+        lat.step(nsteps)
+        return lat.get_state()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_initial_condition_matches_oracle(oracle_mod, ah, precision):
+    op, gp = both_params(oracle_mod, 20, precision, sigma=1.3)
+    with ah.Lattice(gp) as lat:
+        lat.init(1234)
+        st = lat.get_state()
+        assert lat.step_index == 0
+    ref = oracle_mod.init(op, 1234)
+    assert np.all(st[2:] == 0.0)
+    if precision == "fp64":
+        assert ulp_distance(st[:2], ref[:2]).max() <= 2.0
+    else:
+        r32 = ref[:2].astype(np.float32).astype(np.float64)
+        assert np.max(np.abs(st[:2] - r32) / np.spacing(np.abs(r32).astype(np.float32)).astype(np.float64)) <= 1.0
+
+
+@pytest.mark.parametrize("N", [4, 5, 20, 67])
+@pytest.mark.parametrize("m,s", [(1.0, 0.0), (2.0, 1.0)])
+def test_one_step_fp64(oracle_mod, ah, N, m, s):
+    op, gp = both_params(oracle_mod, N, "fp64", m=m, s_early=s, s_late=s)
+    st = random_state(N, seed=100 + N)
+    got = _run_gpu(ah, gp, st, 3, 1)
+    ref = oracle_mod.step(op, st, 3, 1)
+    err = field_scaled_error(got, ref)
+    print("one-step fp64", N, m, s, err)
+    assert max(err.values()) <= 1e-13, err
+
+
+@pytest.mark.parametrize("gauge", ["compact", "noncompact"])
+def test_one_step_gauge_actions(oracle_mod, ah, gauge):
+    N = 12
+    op, gp = both_params(oracle_mod, N, "fp64", gauge_action=gauge)
+    st = random_state(N, seed=7, a_amp=2.0)
+    got = _run_gpu(ah, gp, st, 0, 1)
+    ref = oracle_mod.step(op, st, 0, 1)
+    assert max_field_error(got, ref) <= 1e-13
+
+
+def test_one_step_fp32(oracle_mod, ah):
+    N = 24
+    op, gp = both_params(oracle_mod, N, "fp32")
+    st = random_state(N, seed=3).astype(np.float32).astype(np.float64)
+    got = _run_gpu(ah, gp, st, 2, 1)
+    ref = oracle_mod.step(op, st, 2, 1)
+    err = field_scaled_error(got, ref)
+    print("one-step fp32", err)
+    assert max(err.values()) <= 2e-6, err
+
+
+@pytest.fixture(scope="module")
+def config1_reference(oracle_mod):
+    """64^3 radiation era, s = 0, random-phase IC from seed 0, 100 oracle steps."""
+    op = oracle_mod.params(N=64, m=1.0)
+    ic = oracle_mod.init(op, 0)
+    return op, ic, oracle_mod.step(op, ic, 0, 100)
+
+
+def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference):
+    op, ic, ref = config1_reference
+    _, gp = both_params(oracle_mod, 64, "fp64", m=1.0)
+    with ah.Lattice(gp) as lat:
+        lat.set_state(ic, 0)
+        for _ in range(10):
+            lat.step(10)
+        got = lat.get_state()
+        err = field_scaled_error(got, ref)
+        print("config1 fp64 100 steps", err)
+        assert max(err.values()) <= 1e-10, err
+        # diagnostics of the GPU snapshot against the oracle on the same snapshot
+        gm = lat.measure()
+        om = oracle_mod.measure(op, got, 100)
+        assert gm["winding_sum_abs"] == om["winding_sum_abs"]
+        for k in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag", "sum_L", "xi_L", "R", "v2_phi", "xi_W"):
+            assert abs(gm[k] - om[k]) <= 1e-11 * abs(om[k]), (k, gm[k], om[k])
+        assert gm["gauss_rel"] < 1e-12 and om["gauss_rel"] < 1e-12
+        assert gm["nonfinite"] == 0 and gm["flags"] == 0
+        assert gm["step"] == 100 and abs(gm["eta"] - 11.0) < 1e-12
+        assert np.array_equal(lat.winding(), oracle_mod.winding(op, got).astype(np.int8))
+
+
+def test_config1_fp32_100_steps(oracle_mod, ah, config1_reference):
+    op, ic, ref = config1_reference
+    _, gp = both_params(oracle_mod, 64, "fp32", m=1.0)
+    with ah.Lattice(gp) as lat:
+        lat.set_state(ic, 0)
+        lat.step(100)
+        got = lat.get_state()
+        err = field_scaled_error(got, ref)
+        print("config1 fp32 vs fp64 oracle, 100 steps", err)
+        assert max(err.values()) <= 1e-4, err
+        # windings bit-exact on the identical (FP32) snapshot, computed in FP64 on both sides
+        assert np.array_equal(lat.winding(), oracle_mod.winding(op, got).astype(np.int8))
+        gm = lat.measure()
+        om = oracle_mod.measure(op, got, 100)
+        assert gm["winding_sum_abs"] == om["winding_sum_abs"]
+        for k in ("energy", "e_grad", "e_mag", "sum_L"):
+            assert abs(gm[k] - om[k]) <= 1e-11 * abs(om[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_measure_on_random_snapshot(oracle_mod, ah, precision):
+    N = 20
+    op, gp = both_params(oracle_mod, N, precision, m=2.0)
+    st = random_state(N, seed=77)
+    if precision == "fp32":
+        st = st.astype(np.float32).astype(np.float64)
+    with ah.Lattice(gp) as lat:
+        lat.set_state(st, 5)
+        gm = lat.measure()
+        w = lat.winding()
+    om = oracle_mod.measure(op, st, 5)
+    assert gm["winding_sum_abs"] == om["winding_sum_abs"]
+    assert np.array_equal(w, oracle_mod.winding(op, st).astype(np.int8))
+    for k in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag", "sum_L", "R", "gauss_rms", "gauss_max",
+              "gauss_rel"):
+        assert abs(gm[k] - om[k]) <= 1e-11 * abs(om[k]), (k, gm[k], om[k])
+
+
+def test_deterministic_and_resumable(ah):
+    from paper_2005_14454_amd import Params
+    gp = Params(N=32, m=1.0)
+    with ah.Lattice(gp) as a:
+        a.init(5)
+        a.step(30)
+        full = a.get_state()
+        ma = a.measure()
+    with ah.Lattice(gp) as b:
+        b.init(5)
+        b.step(15)
+        mid = b.get_state()
+    with ah.Lattice(gp, arena="library") as c:
+        c.set_state(mid, 15)
+        c.step(15)
+        resumed = c.get_state()
+        mc = c.measure()
+    assert np.array_equal(full, resumed)
+    assert ma == mc
+
+
+def test_errors_and_edge_cases(ah):
+    from paper_2005_14454_amd import Params, _lib
+    with pytest.raises(ah.AHError):
+        ah.Lattice(Params(N=3))
+    with ah.Lattice(Params(N=8)) as lat:
+        with pytest.raises(ah.AHError) as ei:
+            lat.step(1)
+        assert ei.value.code == _lib.AH_E_STATE
+        lat.init(1)
+        before = lat.get_state()
+        lat.step(0)
+        assert np.array_equal(before, lat.get_state())
+        with pytest.raises(ah.AHError):
+            lat.step(-1)
+        with pytest.raises(ValueError):
+            lat.set_state(np.zeros(5))
+
+
+def test_vacuum_bitwise_static_on_gpu(ah):
+    from paper_2005_14454_amd import Params
+    for prec in ("fp64", "fp32"):
+        gp = Params(N=9, precision=prec, m=2.0)
+        st = np.zeros((10, 9 ** 3))
+        st[0] = 1.0
+        with ah.Lattice(gp) as lat:
+            lat.set_state(st, 0)
+            lat.step(20)
+            assert np.array_equal(lat.get_state(), st)
