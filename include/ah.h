@@ -152,6 +152,26 @@ int ah_measure(ah_handle* h, ah_measurement* out);
  * temporary device buffer of 3*N^3 bytes.  Synchronous. */
 int ah_get_winding(ah_handle* h, int8_t* host_w);
 
+/* ------------------------------------------------------ step kernel choice */
+#define AH_KERNEL_AUTO 0 /* tiled kernel for the compact action, site kernel otherwise */
+#define AH_KERNEL_SITE 1 /* one thread per site, every neighbour read from global memory */
+#define AH_KERNEL_TILE 2 /* z-marching tiles with links shared through LDS (compact action only) */
+
+/* Performance knobs of the step; they do not change the equations.  The
+ * tiled kernel gives bitwise-identical results for every tile shape and
+ * z-chunk; the site kernel agrees with it to rounding. */
+typedef struct ah_step_config {
+    int32_t kernel;         /* AH_KERNEL_* */
+    int32_t tile_x, tile_y; /* tiled kernel: (64,8), (64,4), (32,8) (FP32 also (64,16)); 0,0 = default */
+    int32_t zchunk;         /* x2-planes per workgroup of the tiled kernel; 0 = automatic */
+} ah_step_config;
+
+/* Select the step kernel; AH_E_INVAL for an unsupported combination. */
+int ah_set_step_config(ah_handle* h, const ah_step_config* c);
+
+/* The configuration in use, with automatic choices resolved. */
+int ah_get_step_config(const ah_handle* h, ah_step_config* c);
+
 /* Wait for all work enqueued on the handle's stream. */
 int ah_synchronize(ah_handle* h);
 

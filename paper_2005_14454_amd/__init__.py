@@ -168,6 +168,19 @@ class Lattice:
         self._call(self._lib.ah_get_winding, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), what="ah_get_winding")
         return w
 
+    # -- kernel choice ---------------------------------------------------------
+    def set_step_config(self, kernel="auto", tile=(0, 0), zchunk=0):
+        """kernel: "auto", "site" or "tile"; tile: (tile_x, tile_y); zchunk: planes per workgroup."""
+        k = {"auto": _lib.AH_KERNEL_AUTO, "site": _lib.AH_KERNEL_SITE, "tile": _lib.AH_KERNEL_TILE}[kernel]
+        c = _lib.ah_step_config(k, tile[0], tile[1], zchunk)
+        self._call(self._lib.ah_set_step_config, ctypes.byref(c), what="ah_set_step_config")
+
+    def get_step_config(self) -> dict:
+        c = _lib.ah_step_config()
+        _lib.check(self._lib.ah_get_step_config(self._h, ctypes.byref(c)))
+        name = {_lib.AH_KERNEL_SITE: "site", _lib.AH_KERNEL_TILE: "tile"}.get(c.kernel, "auto")
+        return {"kernel": name, "tile": (c.tile_x, c.tile_y), "zchunk": c.zchunk}
+
     # -- timing ----------------------------------------------------------------
     def set_timing(self, enable: bool):
         self._call(self._lib.ah_set_timing, 1 if enable else 0, what="ah_set_timing")

@@ -44,6 +44,16 @@ class ah_measurement(ctypes.Structure):
     ]
 
 
+AH_KERNEL_AUTO = 0
+AH_KERNEL_SITE = 1
+AH_KERNEL_TILE = 2
+
+
+class ah_step_config(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("zchunk", ctypes.c_int32)]
+
+
 class AHError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (code {code})")
@@ -76,6 +86,8 @@ def load():
         "ah_step": ([vp, i64], ctypes.c_int),
         "ah_measure": ([vp, P(ah_measurement)], ctypes.c_int),
         "ah_get_winding": ([vp, P(ctypes.c_int8)], ctypes.c_int),
+        "ah_set_step_config": ([vp, P(ah_step_config)], ctypes.c_int),
+        "ah_get_step_config": ([vp, P(ah_step_config)], ctypes.c_int),
         "ah_synchronize": ([vp], ctypes.c_int),
         "ah_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "ah_get_timing": ([vp, P(ctypes.c_double), P(i64)], ctypes.c_int),

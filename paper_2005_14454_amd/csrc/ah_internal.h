@@ -69,13 +69,23 @@ struct MeasConst {
     double gauss_c;    // coupling of the Gauss residual
 };
 
-// ---- launchers (ah_kernels.hip) -------------------------------------------
+// Tiled step kernel shape: TX x TY sites per workgroup, zchunk x2-planes per
+// workgroup (0 = the whole lattice).
+struct TileConfig {
+    int tx, ty, zchunk;
+};
+
+// ---- launchers (ah_kernels.hip, ah_step_tile.hip) -------------------------
 template <typename R>
 hipError_t launch_init(const Fields<R>& f, int N, double sigma, uint64_t seed, hipStream_t s);
 
 template <typename R>
 hipError_t launch_step(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2,
                        const LatticeConst& L, const StepCoef& c, hipStream_t s);
+
+template <typename R>
+hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2, const LatticeConst& L,
+                            const StepCoef& c, const TileConfig& tc, hipStream_t s);
 
 template <typename R>
 hipError_t launch_measure(const Fields<R>& f, const LatticeConst& L, const StepCoef& c,

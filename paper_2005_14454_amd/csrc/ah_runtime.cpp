@@ -36,6 +36,7 @@ struct ah_handle {
     bool timing = false;
     std::vector<hipEvent_t> ev;  // start/stop pairs
     size_t ev_used = 0;
+    ah_step_config cfg{AH_KERNEL_AUTO, 0, 0, 0};
     std::string err;
 };
 
@@ -212,6 +213,57 @@ struct DeviceGuard {
     }
 };
 
+bool tile_supported(int precision, int tx, int ty)
+{
+    if (tx == 64 && (ty == 8 || ty == 4)) return true;
+    if (tx == 32 && ty == 8) return true;
+    if (tx == 64 && ty == 16) return precision == AH_FP32;
+    return false;
+}
+
+// Resolve automatic choices of a step configuration for the lattice.
+int resolve_config(const ah_params& p, const ah_step_config& in, ah_step_config* out, std::string* why)
+{
+    ah_step_config c = in;
+    if (c.kernel == AH_KERNEL_AUTO) c.kernel = p.gauge_action == AH_COMPACT ? AH_KERNEL_TILE : AH_KERNEL_SITE;
+    if (c.kernel != AH_KERNEL_SITE && c.kernel != AH_KERNEL_TILE) {
+        *why = "unknown kernel";
+        return AH_E_INVAL;
+    }
+    if (c.kernel == AH_KERNEL_SITE) {
+        c.tile_x = c.tile_y = c.zchunk = 0;
+        *out = c;
+        return AH_OK;
+    }
+    if (p.gauge_action != AH_COMPACT) {
+        *why = "the tiled kernel supports the compact gauge action only";
+        return AH_E_INVAL;
+    }
+    if (c.tile_x == 0 && c.tile_y == 0) {
+        c.tile_x = 64;
+        c.tile_y = 8;
+    }
+    if (!tile_supported(p.precision, c.tile_x, c.tile_y)) {
+        *why = "unsupported tile shape";
+        return AH_E_INVAL;
+    }
+    if (c.zchunk < 0) {
+        *why = "zchunk must be >= 0";
+        return AH_E_INVAL;
+    }
+    if (c.zchunk == 0) {
+        // enough workgroups to fill 256 CUs a few times over
+        const int64_t per_chunk = (int64_t)((p.N + c.tile_x - 1) / c.tile_x) * ((p.N + c.tile_y - 1) / c.tile_y);
+        int64_t zc = (int64_t)p.N * per_chunk / 1024;
+        if (zc < 8) zc = 8;
+        if (zc > p.N) zc = p.N;
+        c.zchunk = (int32_t)zc;
+    }
+    if (c.zchunk > p.N) c.zchunk = p.N;
+    *out = c;
+    return AH_OK;
+}
+
 template <typename R>
 hipError_t do_step(ah_handle* h)
 {
@@ -231,7 +283,12 @@ hipError_t do_step(ah_handle* h)
         e = hipEventRecord(h->ev[h->ev_used], h->stream);
         if (e != hipSuccess) return e;
     }
-    e = launch_step<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, h->stream);
+    if (h->cfg.kernel == AH_KERNEL_TILE) {
+        const TileConfig tc{h->cfg.tile_x, h->cfg.tile_y, h->cfg.zchunk};
+        e = launch_step_tile<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, tc, h->stream);
+    } else {
+        e = launch_step<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, h->stream);
+    }
     if (e != hipSuccess) return e;
     if (h->timing) {
         e = hipEventRecord(h->ev[h->ev_used + 1], h->stream);
@@ -338,7 +395,35 @@ int ah_create(const ah_params* p, void* dev_arena, size_t arena_bytes, void* hip
         delete h;
         return AH_E_NOMEM;
     }
+    {
+        std::string why2;
+        const ah_step_config dflt{AH_KERNEL_AUTO, 0, 0, 0};
+        if (resolve_config(h->p, dflt, &h->cfg, &why2) != AH_OK) {
+            (void)hipHostFree(h->host_result);
+            if (h->owns_arena) (void)hipFree(h->arena);
+            delete h;
+            return AH_E_INVAL;
+        }
+    }
     *out = h;
+    return AH_OK;
+}
+
+int ah_set_step_config(ah_handle* h, const ah_step_config* c)
+{
+    if (!h || !c) return fail(h, AH_E_INVAL, "ah_set_step_config: bad argument");
+    std::string why;
+    ah_step_config r;
+    int rc = resolve_config(h->p, *c, &r, &why);
+    if (rc != AH_OK) return fail(h, rc, "ah_set_step_config: " + why);
+    h->cfg = r;
+    return AH_OK;
+}
+
+int ah_get_step_config(const ah_handle* h, ah_step_config* c)
+{
+    if (!h || !c) return AH_E_INVAL;
+    *c = h->cfg;
     return AH_OK;
 }
 

@@ -25,8 +25,14 @@ def ah():
     return ah
 
 
-def _run_gpu(ah, gp, state, step0, nsteps):
+KERNELS = [("site", (0, 0), 0), ("tile", (64, 8), 0), ("tile", (64, 4), 3), ("tile", (32, 8), 5)]
+KERNEL_IDS = ["site", "tile64x8", "tile64x4z3", "tile32x8z5"]
+
+
+def _run_gpu(ah, gp, state, step0, nsteps, kernel=None):
     with ah.Lattice(gp) as lat:
+        if kernel is not None:
+            lat.set_step_config(kernel[0], kernel[1], kernel[2])
         lat.set_state(state, step0)
         lat.step(nsteps)
         return lat.get_state()
@@ -48,12 +54,13 @@ def test_initial_condition_matches_oracle(oracle_mod, ah, precision):
         assert np.max(np.abs(st[:2] - r32) / np.spacing(np.abs(r32).astype(np.float32)).astype(np.float64)) <= 1.0
 
 
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
 @pytest.mark.parametrize("N", [4, 5, 20, 67])
 @pytest.mark.parametrize("m,s", [(1.0, 0.0), (2.0, 1.0)])
-def test_one_step_fp64(oracle_mod, ah, N, m, s):
+def test_one_step_fp64(oracle_mod, ah, N, m, s, kernel):
     op, gp = both_params(oracle_mod, N, "fp64", m=m, s_early=s, s_late=s)
     st = random_state(N, seed=100 + N)
-    got = _run_gpu(ah, gp, st, 3, 1)
+    got = _run_gpu(ah, gp, st, 3, 1, kernel)
     ref = oracle_mod.step(op, st, 3, 1)
     err = field_scaled_error(got, ref)
     print("one-step fp64", N, m, s, err)
@@ -70,11 +77,12 @@ def test_one_step_gauge_actions(oracle_mod, ah, gauge):
     assert max_field_error(got, ref) <= 1e-13
 
 
-def test_one_step_fp32(oracle_mod, ah):
-    N = 24
+@pytest.mark.parametrize("kernel", KERNELS + [("tile", (64, 16), 0)], ids=KERNEL_IDS + ["tile64x16"])
+@pytest.mark.parametrize("N", [24, 70])
+def test_one_step_fp32(oracle_mod, ah, N, kernel):
     op, gp = both_params(oracle_mod, N, "fp32")
     st = random_state(N, seed=3).astype(np.float32).astype(np.float64)
-    got = _run_gpu(ah, gp, st, 2, 1)
+    got = _run_gpu(ah, gp, st, 2, 1, kernel)
     ref = oracle_mod.step(op, st, 2, 1)
     err = field_scaled_error(got, ref)
     print("one-step fp32", err)
@@ -89,10 +97,12 @@ def config1_reference(oracle_mod):
     return op, ic, oracle_mod.step(op, ic, 0, 100)
 
 
-def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference):
+@pytest.mark.parametrize("kernel", ["site", "tile"])
+def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference, kernel):
     op, ic, ref = config1_reference
     _, gp = both_params(oracle_mod, 64, "fp64", m=1.0)
     with ah.Lattice(gp) as lat:
+        lat.set_step_config(kernel)
         lat.set_state(ic, 0)
         for _ in range(10):
             lat.step(10)
@@ -112,10 +122,12 @@ def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference):
         assert np.array_equal(lat.winding(), oracle_mod.winding(op, got).astype(np.int8))
 
 
-def test_config1_fp32_100_steps(oracle_mod, ah, config1_reference):
+@pytest.mark.parametrize("kernel", ["site", "tile"])
+def test_config1_fp32_100_steps(oracle_mod, ah, config1_reference, kernel):
     op, ic, ref = config1_reference
     _, gp = both_params(oracle_mod, 64, "fp32", m=1.0)
     with ah.Lattice(gp) as lat:
+        lat.set_step_config(kernel)
         lat.set_state(ic, 0)
         lat.step(100)
         got = lat.get_state()
@@ -199,3 +211,34 @@ def test_vacuum_bitwise_static_on_gpu(ah):
             lat.set_state(st, 0)
             lat.step(20)
             assert np.array_equal(lat.get_state(), st)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tile_shapes_bitwise_identical(ah, precision):
+    """Every tile shape and z-chunk computes each site with the same expression
+    tree from the same inputs, so the fields agree bit for bit."""
+    from paper_2005_14454_amd import Params
+    N = 40
+    gp = Params(N=N, precision=precision, m=2.0)
+    st = random_state(N, seed=9)
+    shapes = [((64, 8), 0), ((64, 4), 7), ((32, 8), 1), ((64, 8), 40), ((32, 8), 13)]
+    if precision == "fp32":
+        shapes.append(((64, 16), 3))
+    outs = [_run_gpu(ah, gp, st, 0, 12, ("tile", t, z)) for t, z in shapes]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    again = _run_gpu(ah, gp, st, 0, 12, ("tile", (64, 8), 0))
+    assert np.array_equal(again, outs[0])
+
+
+def test_default_kernel_choice(ah):
+    from paper_2005_14454_amd import Params
+    with ah.Lattice(Params(N=16)) as lat:
+        assert lat.get_step_config()["kernel"] == "tile"
+    with ah.Lattice(Params(N=16, gauge_action="noncompact")) as lat:
+        assert lat.get_step_config()["kernel"] == "site"
+        with pytest.raises(ah.AHError):
+            lat.set_step_config("tile")
+    with ah.Lattice(Params(N=16, precision="fp64")) as lat:
+        with pytest.raises(ah.AHError):
+            lat.set_step_config("tile", (64, 16))
