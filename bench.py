@@ -68,8 +68,30 @@ def run_gpu(precision, N, steps, warmup, measure_every, seed):
     }
 
 
-def cpu_baseline(N, seed):
-    """The FP64 CPU oracle timed on this host: one step of the same 512^3
+def copy_probe(nbytes=8 << 30, reps=10):
+    """Achievable HBM bandwidth of a plain device-to-device copy (torch's copy
+    kernel) of nbytes: (read + write bytes) / time."""
+    import torch
+    n = nbytes // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * n * 4, "ms": ms, "GB/s": 2 * n * 4 / ms / 1e6}
+
+
+def cpu_baseline(N, seed, steps=4):
+    """The FP64 CPU oracle timed on this host: `steps` steps of the same 512^3
     workload after one untimed step (so that the links are non-trivial)."""
     import oracle
 
@@ -77,10 +99,10 @@ def cpu_baseline(N, seed):
     st = oracle.init(p, seed)
     st = oracle.step(p, st, 0, 1)
     t0 = time.perf_counter()
-    oracle.step(p, st, 1, 1)
+    oracle.step(p, st, 1, steps)
     dt = time.perf_counter() - t0
-    return {"value": N ** 3 / dt, "unit": "site-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"one FP64 step of the {N}^3 lattice (after one untimed step), {dt:.1f} s"}
+    return {"value": steps * N ** 3 / dt, "unit": "site-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the {N}^3 lattice after one untimed step, {dt:.1f} s"}
 
 
 def main():
@@ -92,6 +114,7 @@ def main():
     ap.add_argument("--measure-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -109,6 +132,7 @@ def main():
         fp64 = run_gpu("fp64", args.N, args.steps, args.warmup, args.measure_every, seed)
         print(f"# fp64: {fp64['value']:.4e} su/s, {fp64['ms_per_step']:.3f} ms/step, kernel "
               f"{fp64['kernel_ms']:.3f} ms", file=sys.stderr, flush=True)
+    probe = None if args.no_copy_probe else copy_probe()
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.N, seed)
 
     out = {
@@ -129,6 +153,7 @@ def main():
                    "N": args.N, "measure_every": args.measure_every, "parallelism": "single GPU"},
         "roofline": fp32["roofline"],
         "cpu_baseline": cpu,
+        "hbm_copy_probe": probe,
         "fp64": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
                                            "roofline": fp64["roofline"], "dtype": "f64"},
         "kernel_ms": {"fp32": fp32["kernel_ms"], "fp64": None if fp64 is None else fp64["kernel_ms"]},

@@ -76,6 +76,7 @@ def _load():
     lib.ahref_step.argtypes = [P(_Params), dp, ctypes.c_int64, ctypes.c_int64]
     lib.ahref_step_sites.argtypes = [P(_Params), dp, ctypes.c_int64, P(ctypes.c_int64), ctypes.c_int64, dp]
     lib.ahref_winding.argtypes = [P(_Params), dp, P(ctypes.c_int32)]
+    lib.ahref_winding_sites.argtypes = [P(_Params), dp, P(ctypes.c_int64), ctypes.c_int64, P(ctypes.c_int32)]
     lib.ahref_gauss.argtypes = [P(_Params), dp, ctypes.c_int64, dp]
     lib.ahref_measure.argtypes = [P(_Params), dp, ctypes.c_int64, P(_Meas)]
     lib.ahref_num_threads.restype = ctypes.c_int
@@ -171,6 +172,16 @@ def winding(p: dict, st: np.ndarray) -> np.ndarray:
     st = _state(p, st)
     W = np.zeros((3, p["N"] ** 3), dtype=np.int32)
     _load().ahref_winding(ctypes.byref(_c(p)), _dptr(st), W.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return W
+
+
+def winding_sites(p: dict, st: np.ndarray, sites) -> np.ndarray:
+    """Windings (len(sites), 3) of the plaquettes (0,1), (0,2), (1,2) based at the listed sites."""
+    st = _state(p, st)
+    sites = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    W = np.zeros((len(sites), 3), dtype=np.int32)
+    _load().ahref_winding_sites(ctypes.byref(_c(p)), _dptr(st), sites.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                len(sites), W.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return W
 
 

@@ -339,6 +339,18 @@ void ahref_winding(const ahref_params* p, const double* st, int32_t* W)
     }
 }
 
+void ahref_winding_sites(const ahref_params* p, const double* st, const int64_t* sites, int64_t count, int32_t* W)
+{
+    int N = p->N;
+    int64_t V = (int64_t)N * N * N;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < count; ++k) {
+        int x[3];
+        coords(N, sites[k], x);
+        for (int q = 0; q < 3; ++q) W[3 * k + q] = plaquette_winding(p, st, V, x, PAIRS[q][0], PAIRS[q][1]);
+    }
+}
+
 /* ----------------------------------------------------------------- Gauss */
 
 /* Discrete Gauss law on snapshot n (section 2, Gauss's law with the

@@ -89,6 +89,9 @@ void ahref_step_sites(const ahref_params* p, const double* st, int64_t n,
 /* plaquette windings W (3 N^3 int32; orientation (0,1), (0,2), (1,2)) */
 void ahref_winding(const ahref_params* p, const double* st, int32_t* W);
 
+/* windings of the 3 plaquettes based at each listed site: W[3*k + q] */
+void ahref_winding_sites(const ahref_params* p, const double* st, const int64_t* sites, int64_t count, int32_t* W);
+
 /* Gauss residual per site at snapshot n (N^3 doubles) */
 void ahref_gauss(const ahref_params* p, const double* st, int64_t n, double* G);
 

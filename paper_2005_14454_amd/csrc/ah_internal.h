@@ -62,6 +62,8 @@ enum MeasSlot {
 constexpr int kMeasStride = 16;        // doubles per partial record
 constexpr int kMeasBlocks = 2048;      // fixed grid of the measurement kernel
 constexpr int kMeasThreads = 256;
+constexpr int kMeasTileX = 64;         // tile of the tiled diagnostics pass
+constexpr int kMeasTileY = 8;
 
 struct MeasConst {
     double inv_2e2f;   // 1 / (2 e0^2 f)
@@ -90,6 +92,16 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
 template <typename R>
 hipError_t launch_measure(const Fields<R>& f, const LatticeConst& L, const StepCoef& c,
                           const MeasConst& mc, double* partials, double* result, hipStream_t s);
+
+// second-stage fold of nblocks per-workgroup records into result[M_COUNT]
+hipError_t launch_measure_final(const double* partials, int nblocks, double* result, hipStream_t s);
+
+// number of workgroups (= partial records) of the tiled diagnostics pass
+int measure_tile_blocks(int N, int zchunk);
+
+template <typename R>
+hipError_t launch_measure_tile(const Fields<R>& f, const LatticeConst& L, const StepCoef& c, const MeasConst& mc,
+                               int zchunk, double* partials, double* result, hipStream_t s);
 
 template <typename R>
 hipError_t launch_winding(const Fields<R>& f, const LatticeConst& L, int8_t* w, hipStream_t s);

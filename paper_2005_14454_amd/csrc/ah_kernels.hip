@@ -379,7 +379,12 @@ hipError_t launch_measure(const Fields<R>& f, const LatticeConst& L, const StepC
                        c, mc, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_measure_final, dim3(1), dim3(256), 0, s, (const double*)partials, kMeasBlocks, result);
+    return launch_measure_final(partials, kMeasBlocks, result, s);
+}
+
+hipError_t launch_measure_final(const double* partials, int nblocks, double* result, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_measure_final, dim3(1), dim3(256), 0, s, partials, nblocks, result);
     return hipGetLastError();
 }
 

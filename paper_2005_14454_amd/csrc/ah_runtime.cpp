@@ -150,9 +150,25 @@ size_t field_bytes(const ah_params& p)
     return align_up(V * (p.precision == AH_FP64 ? 8 : 4));
 }
 
+// x2-planes per workgroup of the tiled diagnostics pass: about 2048 workgroups
+int meas_zchunk(int N)
+{
+    const int64_t tiles = (int64_t)((N + kMeasTileX - 1) / kMeasTileX) * ((N + kMeasTileY - 1) / kMeasTileY);
+    int64_t zc = (int64_t)N * tiles / 2048;
+    if (zc < 8) zc = 8;
+    if (zc > N) zc = N;
+    return (int)zc;
+}
+
+size_t partial_records(const ah_params& p)
+{
+    const int nb = measure_tile_blocks(p.N, meas_zchunk(p.N));
+    return (size_t)(nb > kMeasBlocks ? nb : kMeasBlocks);
+}
+
 size_t required_bytes(const ah_params& p)
 {
-    return 15 * field_bytes(p) + align_up((size_t)kMeasBlocks * kMeasStride * sizeof(double)) +
+    return 15 * field_bytes(p) + align_up(partial_records(p) * kMeasStride * sizeof(double)) +
            align_up(kMeasStride * sizeof(double));
 }
 
@@ -387,7 +403,7 @@ int ah_create(const ah_params* p, void* dev_arena, size_t arena_bytes, void* hip
         base += fb;
     }
     h->partials = (double*)base;
-    base += align_up((size_t)kMeasBlocks * kMeasStride * sizeof(double));
+    base += align_up(partial_records(*p) * kMeasStride * sizeof(double));
     h->result = (double*)base;
     e = hipHostMalloc((void**)&h->host_result, kMeasStride * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -525,11 +541,19 @@ int ah_measure(ah_handle* h, ah_measurement* out)
     mc.lam_quarter = 0.25 * p.lambda0 * sc.f;
     mc.gauss_c = gauss_coupling(p, h->step);
     const StepCoef c = coef_at(p, h->step);
-    hipError_t e = p.precision == AH_FP64
-                       ? launch_measure<double>(fields_of<double>(h, h->cur), lconst(p), c, mc, h->partials,
-                                                h->result, h->stream)
-                       : launch_measure<float>(fields_of<float>(h, h->cur), lconst(p), c, mc, h->partials,
-                                               h->result, h->stream);
+    hipError_t e;
+    if (p.gauge_action == AH_COMPACT) {
+        const int zc = meas_zchunk(p.N);
+        e = p.precision == AH_FP64 ? launch_measure_tile<double>(fields_of<double>(h, h->cur), lconst(p), c, mc, zc,
+                                                                 h->partials, h->result, h->stream)
+                                   : launch_measure_tile<float>(fields_of<float>(h, h->cur), lconst(p), c, mc, zc,
+                                                                h->partials, h->result, h->stream);
+    } else {
+        e = p.precision == AH_FP64 ? launch_measure<double>(fields_of<double>(h, h->cur), lconst(p), c, mc,
+                                                            h->partials, h->result, h->stream)
+                                   : launch_measure<float>(fields_of<float>(h, h->cur), lconst(p), c, mc,
+                                                           h->partials, h->result, h->stream);
+    }
     if (e != hipSuccess) return hip_fail(h, e, "ah_measure launch");
     e = hipMemcpyAsync(h->host_result, h->result, M_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "ah_measure copy");
