@@ -68,6 +68,80 @@ def run_gpu(precision, N, steps, warmup, measure_every, seed):
     }
 
 
+def single_rate(N, precision="fp32", steps=10):
+    """su/s of the plain single-lattice step (kernel time) at N."""
+    import paper_2005_14454_amd as ah
+    with ah.Lattice(ah.Params(N=N, precision=precision, m=1.0)) as lat:
+        lat.init(0)
+        lat.step(2)
+        lat.set_timing(True)
+        lat.step(steps)
+        ms, n = lat.get_timing()
+    return N ** 3 * n / (ms / 1e3)
+
+
+def batched_ensemble(nlat=64, measure_every=20, chunk=16):
+    """64 independent FP32 lattices, N uniform on {64, 96, 128, 192, 256}, m on
+    {1, 2} (PCG64 seed 4), seeds 100..163, s = 0, each to eta = dx N / 2, in one
+    pool: one graph replay per step advances every unfinished lattice; tile
+    shape and z-chunk autotuned per size class."""
+    import numpy as np
+    import torch
+    import paper_2005_14454_amd as ah
+    from paper_2005_14454_amd.serve import steps_to_half_light_crossing
+
+    rng = np.random.default_rng(4)
+    Ns = [int(v) for v in rng.choice([64, 96, 128, 192, 256], nlat)]
+    ms = [float(v) for v in rng.choice([1.0, 2.0], nlat)]
+    tuned = {}
+    for N in sorted(set(Ns)):
+        tuned[N] = ah.autotune(ah.Params(N=N, precision="fp32"), steps=5)
+    reqs = [(ah.Params(N=N, precision="fp32", m=m), 100 + i, steps_to_half_light_crossing(N))
+            for i, (N, m) in enumerate(zip(Ns, ms))]
+    budget = sum(ah.pool_footprint(p, n, measure_every) for p, _, n in reqs) + (64 << 20)
+    su = sum(p.N ** 3 * n for p, _, n in reqs)
+    with ah.Pool(budget, max_slots=nlat) as pool:
+        ids = [pool.submit(p, seed, n, measure_every) for p, seed, n in reqs]
+        assert all(i is not None for i in ids)
+        pool.advance(1)  # builds and instantiates the graph
+        pool.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        left = set(ids)
+        steps = 1
+        while left:
+            pool.advance(chunk)
+            steps += chunk
+            for rid in pool.poll():
+                left.discard(rid)
+        t1 = time.perf_counter()
+        finals = [pool.results(rid)[-1] for rid in ids]
+    # the same lattices one after another through the single-lattice step
+    rate = {N: single_rate(N) for N in sorted(set(Ns))}
+    sequential_s = sum(p.N ** 3 * n / rate[p.N] for p, _, n in reqs)
+    sec = t1 - t0
+    return {"lattices": nlat, "site_updates": su, "wall_s": sec, "value": su / sec, "unit": "site-updates/s",
+            "graph_replays": steps, "sequential_kernel_s": sequential_s, "speedup_vs_sequential": sequential_s / sec,
+            "tuned": {str(k): v for k, v in tuned.items()},
+            "single_lattice_su_per_s": {str(k): v for k, v in rate.items()},
+            "nonfinite": sum(m["nonfinite"] for m in finals)}
+
+
+def served(nreq=40, capacity_su=3.0e10):
+    """A shortened request stream (the full 500-request stream is
+    `python -m paper_2005_14454_amd.serve`): N log-uniform on [64, 512],
+    m in {1, 2}, s in {0, 1}, FP32 with an FP64 rerun of every 10th request,
+    Poisson arrivals at 0.7 x capacity."""
+    import numpy as np
+    from paper_2005_14454_amd.serve import make_stream, run_stream
+    probe = make_stream(nreq, 1.0)
+    work = float(np.mean([r.params.N ** 3 * r.nsteps for r in probe]))
+    rate = 0.7 * capacity_su / work
+    out = run_stream(make_stream(nreq, rate), hbm_budget=int(200e9))
+    out["arrival_rate_per_s"] = rate
+    return out
+
+
 def copy_probe(nbytes=8 << 30, reps=10):
     """Achievable HBM bandwidth of a plain device-to-device copy (torch's copy
     kernel) of nbytes: (read + write bytes) / time."""
@@ -115,6 +189,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -132,6 +209,14 @@ def main():
         fp64 = run_gpu("fp64", args.N, args.steps, args.warmup, args.measure_every, seed)
         print(f"# fp64: {fp64['value']:.4e} su/s, {fp64['ms_per_step']:.3f} ms/step, kernel "
               f"{fp64['kernel_ms']:.3f} ms", file=sys.stderr, flush=True)
+    batched = None if args.no_batched else batched_ensemble()
+    if batched:
+        print(f"# batched: {batched['value']:.4e} su/s over {batched['lattices']} lattices, "
+              f"{batched['speedup_vs_sequential']:.2f}x vs sequential", file=sys.stderr, flush=True)
+    serv = None if args.no_served else served(args.served_requests, capacity_su=fp32["value"])
+    if serv:
+        print(f"# served: {serv['throughput_su_per_s']:.4e} su/s, p50 {serv['ttc_p50_s']:.2f} s, "
+              f"p99 {serv['ttc_p99_s']:.2f} s", file=sys.stderr, flush=True)
     probe = None if args.no_copy_probe else copy_probe()
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.N, seed)
 
@@ -154,6 +239,8 @@ def main():
         "roofline": fp32["roofline"],
         "cpu_baseline": cpu,
         "hbm_copy_probe": probe,
+        "batched": batched,
+        "served": serv,
         "fp64": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
                                            "roofline": fp64["roofline"], "dtype": "f64"},
         "kernel_ms": {"fp32": fp32["kernel_ms"], "fp64": None if fp64 is None else fp64["kernel_ms"]},

@@ -185,6 +185,103 @@ int ah_get_timing(ah_handle* h, double* total_ms, int64_t* launches);
 /* Free what the library allocated; the handle is invalid afterwards. */
 int ah_destroy(ah_handle* h);
 
+/* ------------------------------------------------------------- autotuner */
+/* Time every supported tile shape and z-chunk of the tiled step for
+ * (p->precision, p->N) on a scratch lattice (library-allocated: 15 N^3 reals,
+ * freed before returning; `steps` timed steps per candidate) and record the
+ * fastest in the process-wide tuning table.  Handles created afterwards with
+ * the automatic configuration, and lattices submitted to a pool, use the
+ * recorded choice.  Synchronous.  AH_E_INVAL for the non-compact action. */
+int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double* best_ms);
+
+/* Recorded choice for (p->precision, p->N); AH_E_AGAIN if none. */
+int ah_tune_lookup(const ah_params* p, ah_step_config* out);
+
+/* Record a choice by hand (kernel must be AH_KERNEL_TILE). */
+int ah_tune_set(const ah_params* p, const ah_step_config* c);
+
+/* Forget every recorded choice. */
+int ah_tune_clear(void);
+
+/* Save / load the tuning table as JSON (one entry per line:
+ * {"precision": "fp32", "N": 128, "tile_x": 64, "tile_y": 8, "zchunk": 32, "ms": 0.01}).
+ * Loading adds to (and overrides entries of) the table.  AH_E_INVAL if the
+ * file cannot be opened. */
+int ah_tune_save(const char* path);
+int ah_tune_load(const char* path);
+
+/* --------------------------------------------------------- lattice pool */
+/* A pool keeps many independent lattices (any N, precision, expansion
+ * history; compact action) resident in one device arena and advances all
+ * active ones together: each ah_pool_advance step is one replay of a HIP
+ * graph holding the diagnostics pass of the lattices whose snapshot is due,
+ * its fixed-order fold, the tiled step of every active lattice (one kernel
+ * node per precision and tile shape, blocks striding over a work list of
+ * (lattice, tile) items) and a counter update.  Every lattice takes the
+ * coefficients of its own step from its own FP64 table, so its fields and
+ * diagnostics are bitwise identical to the same lattice run alone through
+ * ah_step with the same tile shape.  Requests enter and leave between
+ * advances (continuous batching); the graph is rebuilt when the set changes.
+ * A pool is used from one host thread at a time. */
+typedef struct ah_pool ah_pool;
+
+typedef struct ah_pool_info {
+    size_t budget;          /* arena bytes */
+    size_t bytes_in_use;    /* sum of admitted footprints */
+    size_t largest_free;    /* largest contiguous free block */
+    int32_t active;         /* lattices admitted and not yet collected */
+    int32_t max_slots;
+    int64_t graph_launches; /* steps issued so far */
+} ah_pool_info;
+
+/* Create a pool with a device arena of hbm_budget bytes (hipMalloc'd and
+ * owned by the pool) and at most max_slots lattices.  hip_stream == NULL: the
+ * pool creates its own stream (graph capture needs a non-null stream). */
+int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_pool** out);
+
+/* Device bytes a request occupies in a pool: 15 N^3 reals of fields,
+ * diagnostics records, the (nsteps+1)-row coefficient table, the series. */
+int ah_pool_footprint(const ah_params* p, int64_t nsteps, int32_t measure_every, size_t* bytes);
+
+/* Admit a lattice: random-phase IC from `seed` (as ah_init), `nsteps` steps,
+ * diagnostics of snapshots 0, measure_every, 2 measure_every, ... and always
+ * of the final snapshot (measure_every = 0: the final one only).  Returns the
+ * request id.  AH_E_AGAIN when no slot or not enough contiguous free memory is
+ * available now; AH_E_NOMEM when the request exceeds the whole budget.
+ * Synchronous (waits for the pool stream). */
+int ah_pool_submit(ah_pool* pool, const ah_params* p, uint64_t seed, int64_t nsteps, int32_t measure_every,
+                   int64_t* id);
+
+/* Enqueue nsteps graph replays (one step of every active lattice each).
+ * Asynchronous. */
+int ah_pool_advance(ah_pool* pool, int32_t nsteps);
+
+/* Ids of lattices that finished since the last poll (at most cap; *n is the
+ * number written).  Synchronises with the pool stream. */
+int ah_pool_poll(ah_pool* pool, int64_t* done_ids, int32_t cap, int32_t* n);
+
+/* Current step of a request and its target (nsteps may be NULL). */
+int ah_pool_progress(ah_pool* pool, int64_t id, int64_t* step, int64_t* nsteps);
+
+/* Current snapshot of a request as FP64 SoA (10 N^3 doubles) and its step. */
+int ah_pool_get_state(ah_pool* pool, int64_t id, double* host_soa, int64_t* step);
+
+/* Measurement series of a finished request (at most cap records; *n written)
+ * and release of its slot and memory.  AH_E_AGAIN if it has not finished. */
+int ah_pool_results(ah_pool* pool, int64_t id, ah_measurement* series, int32_t cap, int32_t* n);
+
+/* Occupancy figures. */
+int ah_pool_stats(const ah_pool* pool, ah_pool_info* info);
+
+/* Wait for all work enqueued on the pool stream. */
+int ah_pool_synchronize(ah_pool* pool);
+
+/* Text of the last error on the pool ("" if none). */
+const char* ah_pool_last_error(const ah_pool* pool);
+
+/* Free the arena and everything else the pool holds. */
+int ah_pool_destroy(ah_pool* pool);
+
 /* Static description of an error code. */
 const char* ah_strerror(int code);
 

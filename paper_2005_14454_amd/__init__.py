@@ -13,8 +13,9 @@ import numpy as np
 from . import _lib
 from ._lib import AHError, AH_FP32, AH_FP64, AH_COMPACT, AH_NONCOMPACT, AH_FLAG_NONFINITE, AH_FLAG_UNSTABLE
 
-__all__ = ["Params", "Lattice", "AHError", "AH_FP32", "AH_FP64", "AH_COMPACT", "AH_NONCOMPACT",
-           "AH_FLAG_NONFINITE", "AH_FLAG_UNSTABLE", "required_bytes"]
+__all__ = ["Params", "Lattice", "Pool", "AHError", "AH_FP32", "AH_FP64", "AH_COMPACT", "AH_NONCOMPACT",
+           "AH_FLAG_NONFINITE", "AH_FLAG_UNSTABLE", "required_bytes", "autotune", "tune_lookup", "tune_set",
+           "tune_clear", "tune_save", "tune_load", "pool_footprint"]
 
 
 @dataclass
@@ -190,3 +191,147 @@ class Lattice:
         n = ctypes.c_int64()
         self._call(self._lib.ah_get_timing, ctypes.byref(ms), ctypes.byref(n), what="ah_get_timing")
         return ms.value, n.value
+
+
+# ----------------------------------------------------------------- autotuner
+
+def _cfg_dict(c) -> dict:
+    return {"kernel": {_lib.AH_KERNEL_SITE: "site", _lib.AH_KERNEL_TILE: "tile"}.get(c.kernel, "auto"),
+            "tile": (c.tile_x, c.tile_y), "zchunk": c.zchunk}
+
+
+def autotune(p: Params, steps: int = 5) -> dict:
+    """Time the tiled step's tile shapes and z-chunks for (precision, N); record the best."""
+    import torch
+    lib = _lib.load()
+    best = _lib.ah_step_config()
+    ms = ctypes.c_double()
+    with torch.cuda.device(torch.cuda.current_device()):
+        _lib.check(lib.ah_autotune(ctypes.byref(p.to_c()), steps, ctypes.byref(best), ctypes.byref(ms)),
+                   what="ah_autotune")
+    d = _cfg_dict(best)
+    d["ms"] = ms.value
+    return d
+
+
+def tune_lookup(p: Params):
+    lib = _lib.load()
+    c = _lib.ah_step_config()
+    rc = lib.ah_tune_lookup(ctypes.byref(p.to_c()), ctypes.byref(c))
+    if rc == _lib.AH_E_AGAIN:
+        return None
+    _lib.check(rc, what="ah_tune_lookup")
+    return _cfg_dict(c)
+
+
+def tune_set(p: Params, tile, zchunk: int = 0):
+    lib = _lib.load()
+    c = _lib.ah_step_config(_lib.AH_KERNEL_TILE, tile[0], tile[1], zchunk)
+    _lib.check(lib.ah_tune_set(ctypes.byref(p.to_c()), ctypes.byref(c)), what="ah_tune_set")
+
+
+def tune_clear():
+    _lib.check(_lib.load().ah_tune_clear(), what="ah_tune_clear")
+
+
+def tune_save(path: str):
+    _lib.check(_lib.load().ah_tune_save(path.encode()), what="ah_tune_save")
+
+
+def tune_load(path: str):
+    _lib.check(_lib.load().ah_tune_load(path.encode()), what="ah_tune_load")
+
+
+def pool_footprint(p: Params, nsteps: int, measure_every: int) -> int:
+    n = ctypes.c_size_t()
+    _lib.check(_lib.load().ah_pool_footprint(ctypes.byref(p.to_c()), nsteps, measure_every, ctypes.byref(n)),
+               what="ah_pool_footprint")
+    return n.value
+
+
+# ---------------------------------------------------------------------- pool
+
+class Pool:
+    """Many lattices resident in one HBM arena, advanced together (one graph
+    replay per step).  submit() returns None when the request does not fit now."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 256, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lattice library has no CPU path")
+        self._torch = torch
+        self._lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.ah_pool_create(hbm_budget, max_slots, None, ctypes.byref(h)), what="ah_pool_create")
+        self._h = h
+        self.max_slots = max_slots
+
+    def _call(self, fn, *args, what=""):
+        with self._torch.cuda.device(self.device):
+            rc = fn(self._h, *args)
+        _lib.check(rc, what=what, pool=self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            with self._torch.cuda.device(self.device):
+                self._lib.ah_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, p: Params, seed: int, nsteps: int, measure_every: int = 0):
+        rid = ctypes.c_int64()
+        with self._torch.cuda.device(self.device):
+            rc = self._lib.ah_pool_submit(self._h, ctypes.byref(p.to_c()), ctypes.c_uint64(seed), nsteps,
+                                          measure_every, ctypes.byref(rid))
+        if rc == _lib.AH_E_AGAIN:
+            return None
+        _lib.check(rc, what="ah_pool_submit", pool=self._h)
+        return rid.value
+
+    def advance(self, nsteps: int = 1):
+        self._call(self._lib.ah_pool_advance, nsteps, what="ah_pool_advance")
+
+    def poll(self, cap: int = 4096):
+        ids = (ctypes.c_int64 * cap)()
+        n = ctypes.c_int32()
+        self._call(self._lib.ah_pool_poll, ids, cap, ctypes.byref(n), what="ah_pool_poll")
+        return [ids[k] for k in range(n.value)]
+
+    def progress(self, rid: int):
+        s, n = ctypes.c_int64(), ctypes.c_int64()
+        self._call(self._lib.ah_pool_progress, rid, ctypes.byref(s), ctypes.byref(n), what="ah_pool_progress")
+        return s.value, n.value
+
+    def get_state(self, rid: int, N: int) -> np.ndarray:
+        st = np.empty((10, N ** 3), dtype=np.float64)
+        s = ctypes.c_int64()
+        self._call(self._lib.ah_pool_get_state, rid, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   ctypes.byref(s), what="ah_pool_get_state")
+        return st
+
+    def results(self, rid: int, cap: int = 100000):
+        arr = (_lib.ah_measurement * cap)()
+        n = ctypes.c_int32()
+        self._call(self._lib.ah_pool_results, rid, arr, cap, ctypes.byref(n), what="ah_pool_results")
+        return [_meas_dict(arr[k]) for k in range(n.value)]
+
+    def stats(self) -> dict:
+        info = _lib.ah_pool_info()
+        _lib.check(self._lib.ah_pool_stats(self._h, ctypes.byref(info)), what="ah_pool_stats")
+        return {k: getattr(info, k) for k, _ in _lib.ah_pool_info._fields_}
+
+    def synchronize(self):
+        self._call(self._lib.ah_pool_synchronize, what="ah_pool_synchronize")

@@ -54,6 +54,11 @@ class ah_step_config(ctypes.Structure):
                 ("zchunk", ctypes.c_int32)]
 
 
+class ah_pool_info(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_size_t), ("bytes_in_use", ctypes.c_size_t), ("largest_free", ctypes.c_size_t),
+                ("active", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("graph_launches", ctypes.c_int64)]
+
+
 class AHError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (code {code})")
@@ -92,6 +97,24 @@ def load():
         "ah_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "ah_get_timing": ([vp, P(ctypes.c_double), P(i64)], ctypes.c_int),
         "ah_destroy": ([vp], ctypes.c_int),
+        "ah_autotune": ([P(ah_params), ctypes.c_int32, P(ah_step_config), P(ctypes.c_double)], ctypes.c_int),
+        "ah_tune_lookup": ([P(ah_params), P(ah_step_config)], ctypes.c_int),
+        "ah_tune_set": ([P(ah_params), P(ah_step_config)], ctypes.c_int),
+        "ah_tune_clear": ([], ctypes.c_int),
+        "ah_tune_save": ([ctypes.c_char_p], ctypes.c_int),
+        "ah_tune_load": ([ctypes.c_char_p], ctypes.c_int),
+        "ah_pool_create": ([ctypes.c_size_t, ctypes.c_int32, vp, P(vp)], ctypes.c_int),
+        "ah_pool_footprint": ([P(ah_params), i64, ctypes.c_int32, P(ctypes.c_size_t)], ctypes.c_int),
+        "ah_pool_submit": ([vp, P(ah_params), ctypes.c_uint64, i64, ctypes.c_int32, P(i64)], ctypes.c_int),
+        "ah_pool_advance": ([vp, ctypes.c_int32], ctypes.c_int),
+        "ah_pool_poll": ([vp, P(i64), ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
+        "ah_pool_progress": ([vp, i64, P(i64), P(i64)], ctypes.c_int),
+        "ah_pool_get_state": ([vp, i64, P(ctypes.c_double), P(i64)], ctypes.c_int),
+        "ah_pool_results": ([vp, i64, P(ah_measurement), ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
+        "ah_pool_stats": ([vp, P(ah_pool_info)], ctypes.c_int),
+        "ah_pool_synchronize": ([vp], ctypes.c_int),
+        "ah_pool_last_error": ([vp], ctypes.c_char_p),
+        "ah_pool_destroy": ([vp], ctypes.c_int),
         "ah_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "ah_last_error": ([vp], ctypes.c_char_p),
     }
@@ -103,11 +126,15 @@ def load():
     return lib
 
 
-def check(rc, handle=None, what=""):
+def check(rc, handle=None, what="", pool=None):
     if rc == AH_OK:
         return
     lib = load()
     msg = lib.ah_strerror(rc).decode()
+    if pool:
+        detail = lib.ah_pool_last_error(pool).decode()
+        if detail:
+            msg = f"{msg}: {detail}"
     if handle:
         detail = lib.ah_last_error(handle).decode()
         if detail:

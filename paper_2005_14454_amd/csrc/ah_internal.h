@@ -77,6 +77,30 @@ struct TileConfig {
     int tx, ty, zchunk;
 };
 
+// ---- lattice pool (many independent lattices advanced by one launch) ------
+// Row layout of a lattice's per-step FP64 coefficient table.
+enum CoefSlot { C_P1 = 0, C_P2, C_E1, C_E2, C_LAMH, C_KAPPA, C_INV2E2F, C_LAMQ, C_GAUSS, kCoefStride = 10 };
+
+// Device-resident descriptor of one pool lattice (plain data; uploaded by the host).
+struct PoolLattice {
+    void* pp[2][5];        // ping-pong phi_re, phi_im, A0, A1, A2; buffer (step & 1) is current
+    void* mom[5];          // Pi_re, Pi_im, E0, E1, E2 (updated in place)
+    const double* coef;    // (nsteps + 1) rows of kCoefStride doubles
+    int64_t* counter;      // counter[0]: local step k; counter[1]: measurements taken
+    double* partials;      // diagnostics records of this lattice
+    double* series;        // measurement records: kSeriesStride doubles each
+    int64_t nsteps;        // steps to run; the lattice is finished when counter[0] == nsteps + 1
+    int64_t series_cap;
+    int N, tiles_x, tiles_y, zchunk;     // step tiling
+    int meas_zchunk, meas_blocks, measure_every, precision;
+    int compact, pad0;
+    double dx, deta, sigma2;
+};
+struct WorkItem {
+    int lattice, tile;
+};
+constexpr int kSeriesStride = 16;      // M_COUNT sums + step index + pad
+
 // ---- launchers (ah_kernels.hip, ah_step_tile.hip) -------------------------
 template <typename R>
 hipError_t launch_init(const Fields<R>& f, int N, double sigma, uint64_t seed, hipStream_t s);
@@ -88,6 +112,10 @@ hipError_t launch_step(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R*
 template <typename R>
 hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2, const LatticeConst& L,
                             const StepCoef& c, const TileConfig& tc, hipStream_t s);
+
+template <typename R>
+hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,
+                             hipStream_t s);
 
 template <typename R>
 hipError_t launch_measure(const Fields<R>& f, const LatticeConst& L, const StepCoef& c,
@@ -102,6 +130,11 @@ int measure_tile_blocks(int N, int zchunk);
 template <typename R>
 hipError_t launch_measure_tile(const Fields<R>& f, const LatticeConst& L, const StepCoef& c, const MeasConst& mc,
                                int zchunk, double* partials, double* result, hipStream_t s);
+
+template <typename R>
+hipError_t launch_measure_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int grid, hipStream_t s);
+hipError_t launch_fold_batch(const PoolLattice* lat, int nlat, hipStream_t s);
+hipError_t launch_advance_batch(const PoolLattice* lat, int nlat, hipStream_t s);
 
 template <typename R>
 hipError_t launch_winding(const Fields<R>& f, const LatticeConst& L, int8_t* w, hipStream_t s);

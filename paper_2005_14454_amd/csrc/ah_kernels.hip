@@ -5,6 +5,7 @@
 // Discretisation (Correia & Martins, section 2): staggered leapfrog with
 // Crank-Nicolson damping; links U_j = exp(-i dx A_j); covariant Laplacian;
 // compact plaquette field strength F_ij = sin(Theta_ij)/dx^2.
+#include "ah_device.h"
 #include "ah_internal.h"
 
 #include <cmath>
@@ -327,23 +328,7 @@ __global__ void __launch_bounds__(256) k_measure_final(const double* __restrict_
                                                        double* __restrict__ result)
 {
     __shared__ double red[256];
-    for (int k = 0; k < M_COUNT; ++k) {
-        double r = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += 256) {
-            const double v = partials[(int64_t)b * kMeasStride + k];
-            r = (k == M_GMAX) ? fmax(r, v) : r + v;
-        }
-        red[threadIdx.x] = r;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w)
-                red[threadIdx.x] = (k == M_GMAX) ? fmax(red[threadIdx.x], red[threadIdx.x + w])
-                                                 : red[threadIdx.x] + red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) result[k] = red[0];
-        __syncthreads();
-    }
+    fold_records(partials, nblocks, result, red);
 }
 
 }  // namespace

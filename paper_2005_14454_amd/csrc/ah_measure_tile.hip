@@ -15,6 +15,7 @@
 // the same rounding sequence as a plain evaluation of the definition.
 // Per-thread sums go through a fixed tree to one record per workgroup; the
 // caller folds the records in a fixed order.
+#include "ah_device.h"
 #include "ah_internal.h"
 
 #pragma clang fp contract(off)
@@ -98,28 +99,31 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
+template <int TX, int TY>
+struct MeasShared {
+    static constexpr int RS = (TX + 2) * (TY + 2);
+    Cd U[2][3][RS];     // links of planes z and z+1
+    Cd Phi[2][RS];      // phi of planes z and z+1
+    double Y[3][RS];    // link phases of plane z
+    double red[TX * TY / 64][M_COUNT];
+};
+
+// Diagnostics of the planes [z0, z1) of the tile at (x0, y0); the workgroup's
+// fixed-order sums go to record[0 .. M_COUNT).  Every thread of the workgroup
+// calls this with the same arguments.
 template <typename R, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) k_measure_tile(Fields<R> f, int N, int zchunk, int tiles_x, int tiles_y,
-                                                         double dx, double sigma2, StepCoef cf, MeasConst mc,
-                                                         double* __restrict__ partials)
+__device__ void march_measure(MeasShared<TX, TY>& sh, const Fields<R>& f, int N, double dx, double sigma2,
+                              const StepCoef& cf, const MeasConst& mc, int x0, int y0, int z0, int z1,
+                              double* __restrict__ record)
 {
-    constexpr int RW = TX + 2, RS = RW * (TY + 2), H = 2 * RW + 2 * TY, NT = TX * TY;
+    constexpr int RW = TX + 2, H = 2 * RW + 2 * TY, NT = TX * TY;
     static_assert(H <= NT, "halo must fit one extra site per thread");
-    __shared__ Cd sU[2][3][RS];
-    __shared__ Cd sPhi[2][RS];
-    __shared__ double sY[3][RS];
+    auto& sU = sh.U;
+    auto& sPhi = sh.Phi;
+    auto& sY = sh.Y;
 
     const double inv_dx = 1.0 / dx, inv_dx2 = inv_dx * inv_dx, inv_dx4 = inv_dx2 * inv_dx2;
     const int64_t NN = (int64_t)N * N;
-
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int tx = t % tiles_x;
-    t /= tiles_x;
-    const int ty = t % tiles_y;
-    const int tz = t / tiles_y;
-    const int x0 = tx * TX, y0 = ty * TY;
-    const int z0 = tz * zchunk;
-    const int z1 = (z0 + zchunk < N) ? z0 + zchunk : N;
 
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
@@ -161,7 +165,6 @@ __global__ void __launch_bounds__(TX* TY) k_measure_tile(Fields<R> f, int N, int
     const int rxm_yp = ro - 1 + RW, rxp_ym = ro + 1 - RW;
     auto plane_of = [&](int z) -> int64_t { return (int64_t)wrapi(z, N) * NN; };
     const R* A[3] = {f.a0, f.a1, f.a2};
-    const R* E[3] = {f.e0, f.e1, f.e2};
 
     double acc[M_COUNT];
     for (int k = 0; k < M_COUNT; ++k) acc[k] = 0.0;
@@ -377,7 +380,7 @@ __global__ void __launch_bounds__(TX* TY) k_measure_tile(Fields<R> f, int N, int
     }
 
     // ---- fixed-order block reduction into one record per workgroup
-    __shared__ double red[NT / 64][M_COUNT];
+    auto& red = sh.red;
     const int lane = tid & 63, wv = tid >> 6;
     for (int k = 0; k < M_COUNT; ++k) {
         const double r = (k == M_GMAX) ? wave_max(acc[k]) : wave_sum(acc[k]);
@@ -387,8 +390,94 @@ __global__ void __launch_bounds__(TX* TY) k_measure_tile(Fields<R> f, int N, int
     if (tid < M_COUNT) {
         double r = red[0][tid];
         for (int w = 1; w < NT / 64; ++w) r = (tid == M_GMAX) ? fmax(r, red[w][tid]) : r + red[w][tid];
-        partials[(int64_t)blockIdx.x * kMeasStride + tid] = r;
+        record[tid] = r;
     }
+}
+
+// One lattice: block b measures tile t = xcd_tile(b) and writes record t, so
+// the records are in tile order whatever the launch geometry.
+template <typename R, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) k_measure_tile(Fields<R> f, int N, int zchunk, int tiles_x, int tiles_y,
+                                                         double dx, double sigma2, StepCoef cf, MeasConst mc,
+                                                         double* __restrict__ partials)
+{
+    __shared__ MeasShared<TX, TY> sh;
+    const int t0 = xcd_tile(blockIdx.x, gridDim.x);
+    int t = t0;
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int ty = t % tiles_y;
+    const int tz = t / tiles_y;
+    const int z0 = tz * zchunk;
+    const int z1 = (z0 + zchunk < N) ? z0 + zchunk : N;
+    march_measure<R, TX, TY>(sh, f, N, dx, sigma2, cf, mc, tx * TX, ty * TY, z0, z1,
+                             partials + (int64_t)t0 * kMeasStride);
+}
+
+__device__ inline bool measure_due(const PoolLattice& L, int64_t k)
+{
+    if (k > L.nsteps) return false;
+    if (k == L.nsteps) return true;
+    return L.measure_every > 0 && (k % L.measure_every) == 0;
+}
+
+// Diagnostics of every pool lattice whose current snapshot is due.
+template <typename R>
+__global__ void __launch_bounds__(kMeasTileX* kMeasTileY) k_measure_batch(const PoolLattice* __restrict__ lat,
+                                                                          const WorkItem* __restrict__ work,
+                                                                          int nwork)
+{
+    __shared__ MeasShared<kMeasTileX, kMeasTileY> sh;
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const WorkItem it = work[w];
+        const PoolLattice& L = lat[it.lattice];
+        const int64_t k = L.counter[0];
+        if (!measure_due(L, k)) continue;
+        const double* row = L.coef + k * kCoefStride;
+        StepCoef cf{row[C_P1], row[C_P2], row[C_E1], row[C_E2], row[C_LAMH], row[C_KAPPA]};
+        MeasConst mc{row[C_INV2E2F], row[C_LAMQ], row[C_GAUSS]};
+        const int cur = (int)(k & 1);
+        const Fields<R> f{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[0], (R*)L.mom[1], (R*)L.pp[cur][2],
+                          (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[2], (R*)L.mom[3], (R*)L.mom[4]};
+        const int tiles_x = (L.N + kMeasTileX - 1) / kMeasTileX, tiles_y = (L.N + kMeasTileY - 1) / kMeasTileY;
+        int t = it.tile;
+        const int tx = t % tiles_x;
+        t /= tiles_x;
+        const int ty = t % tiles_y;
+        const int tz = t / tiles_y;
+        const int z0 = tz * L.meas_zchunk;
+        const int z1 = (z0 + L.meas_zchunk < L.N) ? z0 + L.meas_zchunk : L.N;
+        march_measure<R, kMeasTileX, kMeasTileY>(sh, f, L.N, L.dx, L.sigma2, cf, mc, tx * kMeasTileX,
+                                                 ty * kMeasTileY, z0, z1, L.partials + (int64_t)it.tile * kMeasStride);
+        __syncthreads();
+    }
+}
+
+// Fold the records of every due lattice into its measurement series (one
+// block per lattice, the same fixed order as the single-lattice fold).
+__global__ void __launch_bounds__(256) k_fold_batch(const PoolLattice* __restrict__ lat, int nlat)
+{
+    __shared__ double red[256];
+    const PoolLattice& L = lat[blockIdx.x];
+    const int64_t k = L.counter[0];
+    if (!measure_due(L, k)) return;
+    const int64_t slot = L.counter[1];
+    if (slot >= L.series_cap) return;
+    double* out = L.series + slot * kSeriesStride;
+    fold_records(L.partials, L.meas_blocks, out, red);
+    if (threadIdx.x == 0) {
+        out[M_COUNT] = (double)k;
+        L.counter[1] = slot + 1;
+    }
+}
+
+// Advance the step counter of every pool lattice that is not finished.
+__global__ void k_advance_batch(const PoolLattice* __restrict__ lat, int nlat)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nlat) return;
+    const int64_t k = lat[i].counter[0];
+    if (k <= lat[i].nsteps) lat[i].counter[0] = k + 1;
 }
 
 }  // namespace
@@ -412,6 +501,28 @@ hipError_t launch_measure_tile(const Fields<R>& f, const LatticeConst& L, const 
     if (e != hipSuccess) return e;
     return launch_measure_final(partials, nb, result, s);
 }
+
+template <typename R>
+hipError_t launch_measure_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_measure_batch<R>), dim3(grid), dim3(kMeasTileX * kMeasTileY), 0, s, lat, work, nwork);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_batch(const PoolLattice* lat, int nlat, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold_batch, dim3(nlat), dim3(256), 0, s, lat, nlat);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_batch(const PoolLattice* lat, int nlat, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance_batch, dim3((nlat + 63) / 64), dim3(64), 0, s, lat, nlat);
+    return hipGetLastError();
+}
+
+template hipError_t launch_measure_batch<double>(const PoolLattice*, const WorkItem*, int, int, hipStream_t);
+template hipError_t launch_measure_batch<float>(const PoolLattice*, const WorkItem*, int, int, hipStream_t);
 
 template hipError_t launch_measure_tile<double>(const Fields<double>&, const LatticeConst&, const StepCoef&,
                                                 const MeasConst&, int, double*, double*, hipStream_t);

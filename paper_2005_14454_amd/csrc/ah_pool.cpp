@@ -1,0 +1,592 @@
+// Lattice pool of libah: many independent lattices of different sizes,
+// precisions and expansion histories resident in one HBM arena and advanced
+// together, one graph launch per step.
+//
+// Each lattice owns its fields, a per-step FP64 coefficient table, its
+// diagnostics records and its measurement series inside the arena, plus a
+// descriptor and a two-word counter (step, measurements taken) in pool
+// metadata.  The graph replayed per step is
+//     measure (lattices whose snapshot is due) -> fold -> step (one node per
+//     precision and tile shape) -> advance counters
+// and every kernel reads the lattice's own counter, so the same graph serves
+// every step until the set of lattices changes.
+#include "ah.h"
+#include "ah_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace ah;
+
+namespace ah {
+// shared with the single-lattice runtime (ah_runtime.cpp)
+int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_config* out, std::string* why);
+int validate_params(const ah_params* p, std::string* why);
+void coef_row(const ah_params& p, int64_t n, double* row);
+int meas_zchunk_for(int N);
+void to_measurement(const ah_params& p, int64_t step, const double* r, int64_t V, ah_measurement* out);
+bool tuned_config(const ah_params& p, ah_step_config* out);
+}  // namespace ah
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Slot {
+    bool used = false;
+    int64_t id = -1;
+    ah_params p{};
+    int64_t nsteps = 0;
+    int measure_every = 0;
+    size_t off = 0, bytes = 0;
+    ah_step_config cfg{};
+    PoolLattice d{};
+    bool reported = false;
+};
+
+struct Footprint {
+    size_t field, fields, partials, coef, series, total;
+    int meas_blocks, meas_zc;
+    int64_t series_cap;
+};
+
+Footprint footprint(const ah_params& p, int64_t nsteps, int measure_every)
+{
+    Footprint f{};
+    const size_t V = (size_t)p.N * p.N * p.N;
+    f.field = align_up(V * (p.precision == AH_FP64 ? 8 : 4));
+    f.fields = 15 * f.field;
+    f.meas_zc = meas_zchunk_for(p.N);
+    f.meas_blocks = measure_tile_blocks(p.N, f.meas_zc);
+    f.partials = align_up((size_t)f.meas_blocks * kMeasStride * sizeof(double));
+    f.coef = align_up((size_t)(nsteps + 1) * kCoefStride * sizeof(double));
+    f.series_cap = (measure_every > 0 ? nsteps / measure_every + 1 : 0) + 1;
+    f.series = align_up((size_t)f.series_cap * kSeriesStride * sizeof(double));
+    f.total = f.fields + f.partials + f.coef + f.series;
+    return f;
+}
+
+}  // namespace
+
+struct ah_pool {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    void* arena = nullptr;
+    size_t budget = 0;
+    std::vector<std::pair<size_t, size_t>> free_list;  // (offset, size), sorted by offset
+    std::vector<Slot> slots;
+    int64_t next_id = 1;
+    PoolLattice* d_lat = nullptr;
+    int64_t* d_counters = nullptr;
+    int64_t* h_counters = nullptr;  // pinned
+    WorkItem* d_work = nullptr;
+    size_t work_cap = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool dirty = true;
+    int64_t graph_launches = 0;
+    std::string err;
+};
+
+namespace {
+
+int pfail(ah_pool* P, int code, const std::string& m)
+{
+    if (P) P->err = m;
+    return code;
+}
+int phip(ah_pool* P, hipError_t e, const char* what)
+{
+    return pfail(P, AH_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Guard {
+    int prev = -1;
+    explicit Guard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~Guard()
+    {
+        int now = -1;
+        if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool arena_alloc(ah_pool* P, size_t bytes, size_t* off)
+{
+    for (size_t i = 0; i < P->free_list.size(); ++i) {
+        auto& b = P->free_list[i];
+        if (b.second >= bytes) {
+            *off = b.first;
+            b.first += bytes;
+            b.second -= bytes;
+            if (b.second == 0) P->free_list.erase(P->free_list.begin() + i);
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(ah_pool* P, size_t off, size_t bytes)
+{
+    P->free_list.push_back({off, bytes});
+    std::sort(P->free_list.begin(), P->free_list.end());
+    std::vector<std::pair<size_t, size_t>> merged;
+    for (auto& b : P->free_list) {
+        if (!merged.empty() && merged.back().first + merged.back().second == b.first)
+            merged.back().second += b.second;
+        else
+            merged.push_back(b);
+    }
+    P->free_list.swap(merged);
+}
+
+size_t largest_free(const ah_pool* P)
+{
+    size_t m = 0;
+    for (auto& b : P->free_list) m = std::max(m, b.second);
+    return m;
+}
+
+// Rebuild descriptors, work lists and the per-step graph.
+int rebuild(ah_pool* P)
+{
+    hipError_t e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return phip(P, e, "pool rebuild sync");
+    const int nslot = (int)P->slots.size();
+    std::vector<PoolLattice> desc(nslot);
+    for (int i = 0; i < nslot; ++i) {
+        if (P->slots[i].used) {
+            desc[i] = P->slots[i].d;
+        } else {
+            std::memset(&desc[i], 0, sizeof(PoolLattice));
+            desc[i].nsteps = -1;
+            desc[i].counter = P->d_counters + 2 * i;
+        }
+    }
+    // work lists: measurement per precision, step per (precision, tile shape)
+    struct Group {
+        int precision, tx, ty;
+        size_t off, n;
+    };
+    std::vector<WorkItem> work;
+    std::vector<Group> meas_groups, step_groups;
+    for (int prec : {AH_FP32, AH_FP64}) {
+        Group g{prec, 0, 0, work.size(), 0};
+        for (int i = 0; i < nslot; ++i) {
+            const Slot& s = P->slots[i];
+            if (!s.used || s.p.precision != prec) continue;
+            for (int t = 0; t < s.d.meas_blocks; ++t) work.push_back({i, t});
+        }
+        g.n = work.size() - g.off;
+        if (g.n) meas_groups.push_back(g);
+    }
+    std::map<std::tuple<int, int, int>, std::vector<int>> by_shape;
+    for (int i = 0; i < nslot; ++i)
+        if (P->slots[i].used)
+            by_shape[{P->slots[i].p.precision, P->slots[i].cfg.tile_x, P->slots[i].cfg.tile_y}].push_back(i);
+    for (auto& kv : by_shape) {
+        Group g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), work.size(), 0};
+        for (int i : kv.second) {
+            const PoolLattice& d = P->slots[i].d;
+            const int tiles_z = (d.N + d.zchunk - 1) / d.zchunk;
+            const int nt = d.tiles_x * d.tiles_y * tiles_z;
+            for (int t = 0; t < nt; ++t) work.push_back({i, t});
+        }
+        g.n = work.size() - g.off;
+        if (g.n) step_groups.push_back(g);
+    }
+    if (work.size() > P->work_cap) {
+        if (P->d_work) (void)hipFree(P->d_work);
+        P->d_work = nullptr;
+        size_t cap = std::max<size_t>(work.size() * 2, 4096);
+        e = hipMalloc(&P->d_work, cap * sizeof(WorkItem));
+        if (e != hipSuccess) {
+            P->work_cap = 0;
+            return phip(P, e, "pool work list allocation");
+        }
+        P->work_cap = cap;
+    }
+    e = hipMemcpy(P->d_lat, desc.data(), nslot * sizeof(PoolLattice), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !work.empty())
+        e = hipMemcpy(P->d_work, work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return phip(P, e, "pool descriptor upload");
+
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->exec = nullptr;
+    P->graph = nullptr;
+    e = hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return phip(P, e, "pool graph capture begin");
+    hipError_t le = hipSuccess;
+    for (auto& g : meas_groups) {
+        const int grid = (int)std::min<size_t>(g.n, 1024);
+        le = g.precision == AH_FP64 ? launch_measure_batch<double>(P->d_lat, P->d_work + g.off, (int)g.n, grid, P->stream)
+                                    : launch_measure_batch<float>(P->d_lat, P->d_work + g.off, (int)g.n, grid, P->stream);
+        if (le != hipSuccess) break;
+    }
+    if (le == hipSuccess) le = launch_fold_batch(P->d_lat, nslot, P->stream);
+    for (auto& g : step_groups) {
+        if (le != hipSuccess) break;
+        const int grid = (int)std::min<size_t>(g.n, 2048);
+        le = g.precision == AH_FP64
+                 ? launch_step_batch<double>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx, g.ty, grid, P->stream)
+                 : launch_step_batch<float>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx, g.ty, grid, P->stream);
+    }
+    if (le == hipSuccess) le = launch_advance_batch(P->d_lat, nslot, P->stream);
+    e = hipStreamEndCapture(P->stream, &P->graph);
+    if (le != hipSuccess) return phip(P, le, "pool graph capture launch");
+    if (e != hipSuccess) return phip(P, e, "pool graph capture end");
+    e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return phip(P, e, "pool graph instantiate");
+    P->dirty = false;
+    return AH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_pool** out)
+{
+    if (!out || max_slots <= 0 || max_slots > 65536 || hbm_budget < kAlign) return AH_E_INVAL;
+    *out = nullptr;
+    ah_pool* P = new (std::nothrow) ah_pool;
+    if (!P) return AH_E_NOMEM;
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return AH_E_DEVICE;
+    }
+    hipError_t e;
+    if (hip_stream) {
+        P->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete P;
+            return AH_E_DEVICE;
+        }
+        P->owns_stream = true;
+    }
+    P->budget = hbm_budget / kAlign * kAlign;
+    e = hipMalloc(&P->arena, P->budget);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (P->owns_stream) (void)hipStreamDestroy(P->stream);
+        delete P;
+        return AH_E_NOMEM;
+    }
+    P->free_list.push_back({0, P->budget});
+    P->slots.resize(max_slots);
+    e = hipMalloc(&P->d_lat, max_slots * sizeof(PoolLattice));
+    if (e == hipSuccess) e = hipMalloc(&P->d_counters, 2 * max_slots * sizeof(int64_t));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&P->h_counters, 2 * max_slots * sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemset(P->d_counters, 0, 2 * max_slots * sizeof(int64_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (P->d_lat) (void)hipFree(P->d_lat);
+        if (P->d_counters) (void)hipFree(P->d_counters);
+        if (P->h_counters) (void)hipHostFree(P->h_counters);
+        (void)hipFree(P->arena);
+        if (P->owns_stream) (void)hipStreamDestroy(P->stream);
+        delete P;
+        return AH_E_NOMEM;
+    }
+    *out = P;
+    return AH_OK;
+}
+
+int ah_pool_footprint(const ah_params* p, int64_t nsteps, int32_t measure_every, size_t* bytes)
+{
+    std::string why;
+    if (validate_params(p, &why) != AH_OK || nsteps < 0 || measure_every < 0 || !bytes) return AH_E_INVAL;
+    *bytes = footprint(*p, nsteps, measure_every).total;
+    return AH_OK;
+}
+
+int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps, int32_t measure_every,
+                   int64_t* id)
+{
+    if (!P || !p || !id || nsteps < 0 || measure_every < 0) return pfail(P, AH_E_INVAL, "ah_pool_submit: bad argument");
+    std::string why;
+    int rc = validate_params(p, &why);
+    if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
+    ah_step_config cfg{AH_KERNEL_TILE, 0, 0, 0};
+    if (p->gauge_action != AH_COMPACT) return pfail(P, AH_E_INVAL, "ah_pool_submit: the pool runs the compact action");
+    if (!tuned_config(*p, &cfg)) {
+        rc = resolve_step_config(*p, ah_step_config{AH_KERNEL_TILE, 0, 0, 0}, &cfg, &why);
+        if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
+    }
+    const Footprint fp = footprint(*p, nsteps, measure_every);
+    if (fp.total > P->budget) return pfail(P, AH_E_NOMEM, "ah_pool_submit: request larger than the pool budget");
+    int slot = -1;
+    for (int i = 0; i < (int)P->slots.size(); ++i)
+        if (!P->slots[i].used) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) return pfail(P, AH_E_AGAIN, "ah_pool_submit: no free slot");
+    size_t off;
+    if (!arena_alloc(P, fp.total, &off)) return pfail(P, AH_E_AGAIN, "ah_pool_submit: not enough free memory now");
+    Guard g(P->device);
+
+    Slot& s = P->slots[slot];
+    s = Slot{};
+    s.used = true;
+    s.id = P->next_id++;
+    s.p = *p;
+    s.nsteps = nsteps;
+    s.measure_every = measure_every;
+    s.off = off;
+    s.bytes = fp.total;
+    s.cfg = cfg;
+    char* base = (char*)P->arena + off;
+    PoolLattice& d = s.d;
+    std::memset(&d, 0, sizeof(d));
+    for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 5; ++c) {
+            d.pp[b][c] = base;
+            base += fp.field;
+        }
+    for (int c = 0; c < 5; ++c) {
+        d.mom[c] = base;
+        base += fp.field;
+    }
+    d.partials = (double*)base;
+    base += fp.partials;
+    double* coef = (double*)base;
+    d.coef = coef;
+    base += fp.coef;
+    d.series = (double*)base;
+    d.counter = P->d_counters + 2 * slot;
+    d.nsteps = nsteps;
+    d.series_cap = fp.series_cap;
+    d.N = p->N;
+    d.tiles_x = (p->N + cfg.tile_x - 1) / cfg.tile_x;
+    d.tiles_y = (p->N + cfg.tile_y - 1) / cfg.tile_y;
+    d.zchunk = cfg.zchunk;
+    d.meas_zchunk = fp.meas_zc;
+    d.meas_blocks = fp.meas_blocks;
+    d.measure_every = measure_every;
+    d.precision = p->precision;
+    d.compact = 1;
+    d.dx = p->dx;
+    d.deta = p->deta;
+    d.sigma2 = p->sigma * p->sigma;
+
+    std::vector<double> rows((size_t)(nsteps + 1) * kCoefStride, 0.0);
+    for (int64_t k = 0; k <= nsteps; ++k) coef_row(*p, k, rows.data() + k * kCoefStride);
+    // enqueue on the pool stream (after any graph replays already queued),
+    // then wait so that the host staging vector can go
+    hipError_t e = hipMemcpyAsync(coef, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice, P->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 2 * sizeof(int64_t), P->stream);
+    if (e == hipSuccess) {
+        Fields<double> f64;
+        Fields<float> f32;
+        if (p->precision == AH_FP64) {
+            f64 = Fields<double>{(double*)d.pp[0][0], (double*)d.pp[0][1], (double*)d.mom[0], (double*)d.mom[1],
+                                 (double*)d.pp[0][2], (double*)d.pp[0][3], (double*)d.pp[0][4], (double*)d.mom[2],
+                                 (double*)d.mom[3], (double*)d.mom[4]};
+            e = launch_init<double>(f64, p->N, p->sigma, seed, P->stream);
+        } else {
+            f32 = Fields<float>{(float*)d.pp[0][0], (float*)d.pp[0][1], (float*)d.mom[0], (float*)d.mom[1],
+                                (float*)d.pp[0][2], (float*)d.pp[0][3], (float*)d.pp[0][4], (float*)d.mom[2],
+                                (float*)d.mom[3], (float*)d.mom[4]};
+            e = launch_init<float>(f32, p->N, p->sigma, seed, P->stream);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) {
+        arena_free(P, s.off, s.bytes);
+        s = Slot{};
+        return phip(P, e, "ah_pool_submit");
+    }
+    P->dirty = true;
+    *id = s.id;
+    return AH_OK;
+}
+
+int ah_pool_advance(ah_pool* P, int32_t nsteps)
+{
+    if (!P || nsteps < 0) return pfail(P, AH_E_INVAL, "ah_pool_advance: bad argument");
+    Guard g(P->device);
+    if (P->dirty) {
+        int rc = rebuild(P);
+        if (rc != AH_OK) return rc;
+    }
+    for (int32_t k = 0; k < nsteps; ++k) {
+        hipError_t e = hipGraphLaunch(P->exec, P->stream);
+        if (e != hipSuccess) return phip(P, e, "ah_pool_advance graph launch");
+        ++P->graph_launches;
+    }
+    return AH_OK;
+}
+
+int ah_pool_poll(ah_pool* P, int64_t* done_ids, int32_t cap, int32_t* n)
+{
+    if (!P || !n || (cap > 0 && !done_ids)) return pfail(P, AH_E_INVAL, "ah_pool_poll: bad argument");
+    Guard g(P->device);
+    const size_t bytes = 2 * P->slots.size() * sizeof(int64_t);
+    hipError_t e = hipMemcpyAsync(P->h_counters, P->d_counters, bytes, hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return phip(P, e, "ah_pool_poll");
+    int32_t k = 0;
+    for (size_t i = 0; i < P->slots.size(); ++i) {
+        Slot& s = P->slots[i];
+        if (!s.used || s.reported) continue;
+        if (P->h_counters[2 * i] == s.nsteps + 1) {
+            if (k < cap) {
+                done_ids[k] = s.id;
+                s.reported = true;
+            }
+            ++k;
+        }
+    }
+    *n = k < cap ? k : cap;
+    return AH_OK;
+}
+
+static Slot* find_slot(ah_pool* P, int64_t id, int* index)
+{
+    for (size_t i = 0; i < P->slots.size(); ++i)
+        if (P->slots[i].used && P->slots[i].id == id) {
+            if (index) *index = (int)i;
+            return &P->slots[i];
+        }
+    return nullptr;
+}
+
+int ah_pool_progress(ah_pool* P, int64_t id, int64_t* step, int64_t* nsteps)
+{
+    if (!P || !step) return pfail(P, AH_E_INVAL, "ah_pool_progress: bad argument");
+    int i;
+    Slot* s = find_slot(P, id, &i);
+    if (!s) return pfail(P, AH_E_INVAL, "ah_pool_progress: unknown id");
+    Guard g(P->device);
+    int64_t c[2];
+    hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return phip(P, e, "ah_pool_progress");
+    *step = std::min(c[0], s->nsteps);
+    if (nsteps) *nsteps = s->nsteps;
+    return AH_OK;
+}
+
+int ah_pool_get_state(ah_pool* P, int64_t id, double* host_soa, int64_t* step)
+{
+    if (!P || !host_soa) return pfail(P, AH_E_INVAL, "ah_pool_get_state: bad argument");
+    int i;
+    Slot* s = find_slot(P, id, &i);
+    if (!s) return pfail(P, AH_E_INVAL, "ah_pool_get_state: unknown id");
+    Guard g(P->device);
+    int64_t c[2];
+    hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return phip(P, e, "ah_pool_get_state");
+    const int64_t k = std::min(c[0], s->nsteps);
+    const int cur = (int)(k & 1);
+    const size_t V = (size_t)s->p.N * s->p.N * s->p.N;
+    const size_t rb = s->p.precision == AH_FP64 ? 8 : 4;
+    void* comps[10] = {s->d.pp[cur][0], s->d.pp[cur][1], s->d.mom[0], s->d.mom[1], s->d.pp[cur][2],
+                       s->d.pp[cur][3], s->d.pp[cur][4], s->d.mom[2], s->d.mom[3], s->d.mom[4]};
+    std::vector<float> tmp(rb == 4 ? V : 0);
+    for (int cc = 0; cc < 10; ++cc) {
+        double* dst = host_soa + cc * V;
+        e = hipMemcpy(rb == 8 ? (void*)dst : (void*)tmp.data(), comps[cc], V * rb, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return phip(P, e, "ah_pool_get_state copy");
+        if (rb == 4)
+            for (size_t q = 0; q < V; ++q) dst[q] = (double)tmp[q];
+    }
+    if (step) *step = k;
+    return AH_OK;
+}
+
+int ah_pool_results(ah_pool* P, int64_t id, ah_measurement* series, int32_t cap, int32_t* n)
+{
+    if (!P || !n || (cap > 0 && !series)) return pfail(P, AH_E_INVAL, "ah_pool_results: bad argument");
+    int i;
+    Slot* s = find_slot(P, id, &i);
+    if (!s) return pfail(P, AH_E_INVAL, "ah_pool_results: unknown id");
+    Guard g(P->device);
+    int64_t c[2];
+    hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return phip(P, e, "ah_pool_results");
+    if (c[0] != s->nsteps + 1) return pfail(P, AH_E_AGAIN, "ah_pool_results: the lattice has not finished");
+    const int64_t nm = std::min(c[1], s->d.series_cap);
+    std::vector<double> raw((size_t)nm * kSeriesStride);
+    if (nm > 0) {
+        e = hipMemcpy(raw.data(), s->d.series, raw.size() * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return phip(P, e, "ah_pool_results copy");
+    }
+    const int64_t V = (int64_t)s->p.N * s->p.N * s->p.N;
+    const int32_t m = (int32_t)std::min<int64_t>(nm, cap);
+    for (int32_t k = 0; k < m; ++k)
+        to_measurement(s->p, (int64_t)raw[(size_t)k * kSeriesStride + M_COUNT], raw.data() + (size_t)k * kSeriesStride,
+                       V, &series[k]);
+    *n = m;
+    arena_free(P, s->off, s->bytes);
+    *s = Slot{};
+    P->dirty = true;
+    return AH_OK;
+}
+
+int ah_pool_stats(const ah_pool* P, ah_pool_info* info)
+{
+    if (!P || !info) return AH_E_INVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->budget = P->budget;
+    size_t used = 0;
+    for (const Slot& s : P->slots)
+        if (s.used) {
+            used += s.bytes;
+            info->active += 1;
+        }
+    info->bytes_in_use = used;
+    info->largest_free = largest_free(P);
+    info->max_slots = (int32_t)P->slots.size();
+    info->graph_launches = P->graph_launches;
+    return AH_OK;
+}
+
+int ah_pool_synchronize(ah_pool* P)
+{
+    if (!P) return AH_E_INVAL;
+    Guard g(P->device);
+    hipError_t e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return phip(P, e, "ah_pool_synchronize");
+    return AH_OK;
+}
+
+const char* ah_pool_last_error(const ah_pool* P) { return P ? P->err.c_str() : ""; }
+
+int ah_pool_destroy(ah_pool* P)
+{
+    if (!P) return AH_E_INVAL;
+    Guard g(P->device);
+    (void)hipStreamSynchronize(P->stream);
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->d_work) (void)hipFree(P->d_work);
+    if (P->d_lat) (void)hipFree(P->d_lat);
+    if (P->d_counters) (void)hipFree(P->d_counters);
+    if (P->h_counters) (void)hipHostFree(P->h_counters);
+    if (P->arena) (void)hipFree(P->arena);
+    if (P->owns_stream) (void)hipStreamDestroy(P->stream);
+    delete P;
+    return AH_OK;
+}
+
+}  // extern "C"

@@ -40,6 +40,10 @@ struct ah_handle {
     std::string err;
 };
 
+namespace ah {
+bool tuned_config(const ah_params& p, ah_step_config* out);  // ah_tune.cpp
+}
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -105,7 +109,11 @@ bool unstable_at(const ah_params& p, int64_t n)
     return p.deta * std::sqrt(g) >= 2.0;
 }
 
-int validate(const ah_params* p, std::string* why)
+}  // namespace
+
+namespace ah {
+
+int validate_params(const ah_params* p, std::string* why)
 {
     if (!p) {
         *why = "params is NULL";
@@ -144,14 +152,23 @@ int validate(const ah_params* p, std::string* why)
     return AH_OK;
 }
 
+}  // namespace ah
+
+namespace {
+
+int validate(const ah_params* p, std::string* why) { return validate_params(p, why); }
+
 size_t field_bytes(const ah_params& p)
 {
     const size_t V = (size_t)p.N * p.N * p.N;
     return align_up(V * (p.precision == AH_FP64 ? 8 : 4));
 }
 
+}  // namespace
+
+namespace ah {
 // x2-planes per workgroup of the tiled diagnostics pass: about 2048 workgroups
-int meas_zchunk(int N)
+int meas_zchunk_for(int N)
 {
     const int64_t tiles = (int64_t)((N + kMeasTileX - 1) / kMeasTileX) * ((N + kMeasTileY - 1) / kMeasTileY);
     int64_t zc = (int64_t)N * tiles / 2048;
@@ -159,6 +176,11 @@ int meas_zchunk(int N)
     if (zc > N) zc = N;
     return (int)zc;
 }
+
+}  // namespace ah
+
+namespace {
+int meas_zchunk(int N) { return meas_zchunk_for(N); }
 
 size_t partial_records(const ah_params& p)
 {
@@ -237,8 +259,11 @@ bool tile_supported(int precision, int tx, int ty)
     return false;
 }
 
+}  // namespace
+
+namespace ah {
 // Resolve automatic choices of a step configuration for the lattice.
-int resolve_config(const ah_params& p, const ah_step_config& in, ah_step_config* out, std::string* why)
+int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_config* out, std::string* why)
 {
     ah_step_config c = in;
     if (c.kernel == AH_KERNEL_AUTO) c.kernel = p.gauge_action == AH_COMPACT ? AH_KERNEL_TILE : AH_KERNEL_SITE;
@@ -278,6 +303,68 @@ int resolve_config(const ah_params& p, const ah_step_config& in, ah_step_config*
     if (c.zchunk > p.N) c.zchunk = p.N;
     *out = c;
     return AH_OK;
+}
+
+// One FP64 row of a lattice's coefficient table for snapshot n (kick
+// coefficients and diagnostics constants).
+void coef_row(const ah_params& p, int64_t n, double* row)
+{
+    const Scalars s = scalars_at(p, n);
+    const StepCoef c = coef_at(p, n);
+    for (int k = 0; k < kCoefStride; ++k) row[k] = 0.0;
+    row[C_P1] = c.cP1;
+    row[C_P2] = c.cP2;
+    row[C_E1] = c.cE1;
+    row[C_E2] = c.cE2;
+    row[C_LAMH] = c.lam_half;
+    row[C_KAPPA] = c.kappa;
+    row[C_INV2E2F] = 1.0 / (2.0 * p.e0 * p.e0 * s.f);
+    row[C_LAMQ] = 0.25 * p.lambda0 * s.f;
+    row[C_GAUSS] = gauss_coupling(p, n);
+}
+
+// Diagnostics of snapshot `step` from the folded FP64 sums r[M_COUNT].
+void to_measurement(const ah_params& p, int64_t step, const double* r, int64_t V, ah_measurement* out)
+{
+    const Scalars sc = scalars_at(p, step);
+    const double dx3 = p.dx * p.dx * p.dx;
+    const double vol = std::pow((double)p.N * p.dx, 3.0);
+    std::memset(out, 0, sizeof(*out));
+    out->step = step;
+    out->eta = sc.eta;
+    out->a = sc.a;
+    out->f = sc.f;
+    out->winding_sum_abs = (int64_t)r[M_WABS];
+    out->L_W = p.dx * r[M_WABS];
+    out->xi_W = std::sqrt(vol / out->L_W);
+    out->e_kin = dx3 * r[M_KIN];
+    out->e_grad = dx3 * r[M_GRAD];
+    out->e_pot = dx3 * r[M_POT];
+    out->e_el = dx3 * r[M_EL];
+    out->e_mag = dx3 * r[M_MAG];
+    out->energy = out->e_kin + out->e_grad + out->e_pot + out->e_el + out->e_mag;
+    out->sum_L = dx3 * r[M_L];
+    out->xi_L = out->sum_L < 0.0 ? std::sqrt(-2.0 * M_PI * p.sigma * p.sigma * vol / out->sum_L) : NAN;
+    out->R = r[M_KINL] / r[M_GRADL];
+    out->v2_phi = 2.0 * out->R / (1.0 + out->R);
+    out->gauss_rms = std::sqrt(r[M_G2] / (double)V);
+    out->gauss_max = r[M_GMAX];
+    const double den = std::sqrt(r[M_DIV2] + r[M_CRHO2]);
+    out->gauss_rel = den > 0.0 ? std::sqrt(r[M_G2]) / den : 0.0;
+    out->nonfinite = (int64_t)r[M_NONFIN];
+    out->flags = (unstable_at(p, step) ? AH_FLAG_UNSTABLE : 0u) | (out->nonfinite ? AH_FLAG_NONFINITE : 0u);
+}
+
+}  // namespace ah
+
+namespace {
+
+int resolve_config(const ah_params& p, const ah_step_config& in, ah_step_config* out, std::string* why)
+{
+    if (in.kernel == AH_KERNEL_AUTO && in.tile_x == 0 && in.tile_y == 0 && in.zchunk == 0 &&
+        p.gauge_action == AH_COMPACT && tuned_config(p, out))
+        return AH_OK;
+    return resolve_step_config(p, in, out, why);
 }
 
 template <typename R>
@@ -559,34 +646,7 @@ int ah_measure(ah_handle* h, ah_measurement* out)
     if (e != hipSuccess) return hip_fail(h, e, "ah_measure copy");
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "ah_measure sync");
-    const double* r = h->host_result;
-
-    const double dx3 = p.dx * p.dx * p.dx;
-    const double vol = std::pow((double)p.N * p.dx, 3.0);
-    std::memset(out, 0, sizeof(*out));
-    out->step = h->step;
-    out->eta = sc.eta;
-    out->a = sc.a;
-    out->f = sc.f;
-    out->winding_sum_abs = (int64_t)r[M_WABS];
-    out->L_W = p.dx * r[M_WABS];
-    out->xi_W = std::sqrt(vol / out->L_W);
-    out->e_kin = dx3 * r[M_KIN];
-    out->e_grad = dx3 * r[M_GRAD];
-    out->e_pot = dx3 * r[M_POT];
-    out->e_el = dx3 * r[M_EL];
-    out->e_mag = dx3 * r[M_MAG];
-    out->energy = out->e_kin + out->e_grad + out->e_pot + out->e_el + out->e_mag;
-    out->sum_L = dx3 * r[M_L];
-    out->xi_L = out->sum_L < 0.0 ? std::sqrt(-2.0 * M_PI * p.sigma * p.sigma * vol / out->sum_L) : NAN;
-    out->R = r[M_KINL] / r[M_GRADL];
-    out->v2_phi = 2.0 * out->R / (1.0 + out->R);
-    out->gauss_rms = std::sqrt(r[M_G2] / (double)h->V);
-    out->gauss_max = r[M_GMAX];
-    const double den = std::sqrt(r[M_DIV2] + r[M_CRHO2]);
-    out->gauss_rel = den > 0.0 ? std::sqrt(r[M_G2]) / den : 0.0;
-    out->nonfinite = (int64_t)r[M_NONFIN];
-    out->flags = (unstable_at(p, h->step) ? AH_FLAG_UNSTABLE : 0u) | (out->nonfinite ? AH_FLAG_NONFINITE : 0u);
+    to_measurement(p, h->step, h->host_result, h->V, out);
     return AH_OK;
 }
 

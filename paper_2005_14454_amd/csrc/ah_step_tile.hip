@@ -94,32 +94,50 @@ struct TileGeom {
     static constexpr int HPT = (H + NT - 1) / NT; // halo sites per thread (upper bound)
 };
 
+// Per-launch constants of one lattice step (coefficients rounded to R).
+template <typename R>
+struct StepArgs {
+    Fields<R> f;
+    R* ophr;
+    R* ophi;
+    R* oa0;
+    R* oa1;
+    R* oa2;
+    int N;
+    R dx, sigma2, cP1, cP2, cE1, cE2, lamh, kappa, deta;
+};
+
 template <typename R, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) k_step_tile(Fields<R> f, R* __restrict__ ophr, R* __restrict__ ophi,
-                                                      R* __restrict__ oa0, R* __restrict__ oa1,
-                                                      R* __restrict__ oa2, int N, int zchunk, int tiles_x,
-                                                      int tiles_y, R dx, R sigma2, R cP1, R cP2, R cE1, R cE2,
-                                                      R lamh, R kappa, R deta)
+struct TileShared {
+    static constexpr int RS = TileGeom<R, TX, TY>::RS;
+    Cx<R> U[2][3][RS];  // links of planes z and z+1 (ring)
+    Cx<R> Phi[RS];      // phi of plane z
+};
+
+// Walk planes [z0, z1) of the tile whose lower corner is (x0, y0): kick and
+// drift every own site.  All threads of the workgroup must call this with
+// the same arguments; it synchronises the workgroup internally.
+template <typename R, int TX, int TY>
+__device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int x0, int y0, int z0, int z1)
 {
     using G = TileGeom<R, TX, TY>;
-    constexpr int RW = G::RW, RS = G::RS, H = G::H;
+    constexpr int RW = G::RW, H = G::H;
     static_assert(G::HPT == 1, "halo must fit one extra site per thread");
-
-    __shared__ Cx<R> sU[2][3][RS];
-    __shared__ Cx<R> sPhi[RS];
+    auto& sU = sh.U;
+    auto& sPhi = sh.Phi;
+    const Fields<R>& f = a.f;
+    R* __restrict__ ophr = a.ophr;
+    R* __restrict__ ophi = a.ophi;
+    R* __restrict__ oa0 = a.oa0;
+    R* __restrict__ oa1 = a.oa1;
+    R* __restrict__ oa2 = a.oa2;
+    const int N = a.N;
+    const R dx = a.dx, sigma2 = a.sigma2, cP1 = a.cP1, cP2 = a.cP2, cE1 = a.cE1, cE2 = a.cE2;
+    const R lamh = a.lamh, kappa = a.kappa, deta = a.deta;
 
     const R inv_dx = R(1) / dx;
     const R inv_dx2 = inv_dx * inv_dx;
     const int64_t NN = (int64_t)N * N;
-
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int tx = t % tiles_x;
-    t /= tiles_x;
-    const int ty = t % tiles_y;
-    const int tz = t / tiles_y;
-    const int x0 = tx * TX, y0 = ty * TY;
-    const int z0 = tz * zchunk;
-    const int z1 = (z0 + zchunk < N) ? z0 + zchunk : N;
 
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
@@ -324,6 +342,67 @@ __global__ void __launch_bounds__(TX* TY) k_step_tile(Fields<R> f, R* __restrict
     }
 }
 
+// One lattice: block b owns tile xcd_tile(b) (tx fastest, then ty, then z-chunk).
+template <typename R, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) k_step_tile(StepArgs<R> a, int zchunk, int tiles_x, int tiles_y)
+{
+    __shared__ TileShared<R, TX, TY> sh;
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int ty = t % tiles_y;
+    const int tz = t / tiles_y;
+    const int z0 = tz * zchunk;
+    const int z1 = (z0 + zchunk < a.N) ? z0 + zchunk : a.N;
+    march_step<R, TX, TY>(sh, a, tx * TX, ty * TY, z0, z1);
+}
+
+// Many lattices in one launch: blocks stride over a work list of
+// (lattice, tile) items; each lattice reads its own step counter, skips the
+// work once it has run its steps, and takes the coefficients of its current
+// step from its own FP64 table.
+template <typename R, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) k_step_batch(const PoolLattice* __restrict__ lat,
+                                                       const WorkItem* __restrict__ work, int nwork)
+{
+    __shared__ TileShared<R, TX, TY> sh;
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const WorkItem it = work[w];
+        const PoolLattice& L = lat[it.lattice];
+        const int64_t k = *L.counter;
+        if (k >= L.nsteps) continue;  // uniform across the block
+        const double* row = L.coef + k * kCoefStride;
+        const int cur = (int)(k & 1);
+        StepArgs<R> a;
+        a.f = Fields<R>{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[0], (R*)L.mom[1], (R*)L.pp[cur][2],
+                        (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[2], (R*)L.mom[3], (R*)L.mom[4]};
+        a.ophr = (R*)L.pp[cur ^ 1][0];
+        a.ophi = (R*)L.pp[cur ^ 1][1];
+        a.oa0 = (R*)L.pp[cur ^ 1][2];
+        a.oa1 = (R*)L.pp[cur ^ 1][3];
+        a.oa2 = (R*)L.pp[cur ^ 1][4];
+        a.N = L.N;
+        a.dx = (R)L.dx;
+        a.sigma2 = (R)L.sigma2;
+        a.cP1 = (R)row[C_P1];
+        a.cP2 = (R)row[C_P2];
+        a.cE1 = (R)row[C_E1];
+        a.cE2 = (R)row[C_E2];
+        a.lamh = (R)row[C_LAMH];
+        a.kappa = (R)row[C_KAPPA];
+        a.deta = (R)L.deta;
+        int t = it.tile;
+        const int tx = t % L.tiles_x;
+        t /= L.tiles_x;
+        const int ty = t % L.tiles_y;
+        const int tz = t / L.tiles_y;
+        const int z0 = tz * L.zchunk;
+        const int z1 = (z0 + L.zchunk < L.N) ? z0 + L.zchunk : L.N;
+        march_step<R, TX, TY>(sh, a, tx * TX, ty * TY, z0, z1);
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
 }  // namespace
 
 template <typename R>
@@ -331,15 +410,30 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
                             const StepCoef& c, const TileConfig& tc, hipStream_t s)
 {
     const int N = L.N;
+    StepArgs<R> a;
+    a.f = in;
+    a.ophr = ophr;
+    a.ophi = ophi;
+    a.oa0 = oa0;
+    a.oa1 = oa1;
+    a.oa2 = oa2;
+    a.N = N;
+    a.dx = (R)L.dx;
+    a.sigma2 = (R)L.sigma2;
+    a.cP1 = (R)c.cP1;
+    a.cP2 = (R)c.cP2;
+    a.cE1 = (R)c.cE1;
+    a.cE2 = (R)c.cE2;
+    a.lamh = (R)c.lam_half;
+    a.kappa = (R)c.kappa;
+    a.deta = (R)L.deta;
 #define AH_TILE_CASE(TXv, TYv)                                                                                   \
     if (tc.tx == TXv && tc.ty == TYv) {                                                                          \
         const int tiles_x = (N + TXv - 1) / TXv, tiles_y = (N + TYv - 1) / TYv;                                 \
         const int zc = tc.zchunk > 0 ? tc.zchunk : N;                                                           \
         const int tiles_z = (N + zc - 1) / zc;                                                                  \
         const int nb = tiles_x * tiles_y * tiles_z;                                                             \
-        hipLaunchKernelGGL((k_step_tile<R, TXv, TYv>), dim3(nb), dim3(TXv * TYv), 0, s, in, ophr, ophi, oa0, oa1, \
-                           oa2, N, zc, tiles_x, tiles_y, (R)L.dx, (R)L.sigma2, (R)c.cP1, (R)c.cP2, (R)c.cE1,      \
-                           (R)c.cE2, (R)c.lam_half, (R)c.kappa, (R)L.deta);                                      \
+        hipLaunchKernelGGL((k_step_tile<R, TXv, TYv>), dim3(nb), dim3(TXv * TYv), 0, s, a, zc, tiles_x, tiles_y);  \
         return hipGetLastError();                                                                               \
     }
     AH_TILE_CASE(64, 8)
@@ -351,6 +445,28 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
 #undef AH_TILE_CASE
     return hipErrorInvalidValue;
 }
+
+template <typename R>
+hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,
+                             hipStream_t s)
+{
+#define AH_BATCH_CASE(TXv, TYv)                                                                               \
+    if (tx == TXv && ty == TYv) {                                                                             \
+        hipLaunchKernelGGL((k_step_batch<R, TXv, TYv>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work, nwork); \
+        return hipGetLastError();                                                                            \
+    }
+    AH_BATCH_CASE(64, 8)
+    AH_BATCH_CASE(64, 4)
+    AH_BATCH_CASE(32, 8)
+    if constexpr (sizeof(R) == 4) {
+        AH_BATCH_CASE(64, 16)
+    }
+#undef AH_BATCH_CASE
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_step_batch<double>(const PoolLattice*, const WorkItem*, int, int, int, int, hipStream_t);
+template hipError_t launch_step_batch<float>(const PoolLattice*, const WorkItem*, int, int, int, int, hipStream_t);
 
 template hipError_t launch_step_tile<double>(const Fields<double>&, double*, double*, double*, double*, double*,
                                              const LatticeConst&, const StepCoef&, const TileConfig&, hipStream_t);

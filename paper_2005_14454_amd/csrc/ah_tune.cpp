@@ -1,0 +1,148 @@
+// Autotuner of libah: picks the tile shape and z-chunk of the tiled step for
+// a (precision, N) by timing candidates on a scratch lattice, and keeps the
+// choices in a process-wide table that can be saved to and loaded from a
+// small JSON file (one entry per line).
+#include "ah.h"
+#include "ah_internal.h"
+
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace {
+
+struct Entry {
+    ah_step_config cfg;
+    double ms;
+};
+std::mutex g_mu;
+std::map<std::pair<int, int>, Entry> g_table;  // (precision, N) -> choice
+
+}  // namespace
+
+namespace ah {
+bool tuned_config(const ah_params& p, ah_step_config* out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_table.find({p.precision, p.N});
+    if (it == g_table.end()) return false;
+    *out = it->second.cfg;
+    if (out->zchunk > p.N) out->zchunk = p.N;
+    return true;
+}
+}  // namespace ah
+
+extern "C" {
+
+int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double* best_ms)
+{
+    if (!p || steps <= 0) return AH_E_INVAL;
+    if (p->gauge_action != AH_COMPACT) return AH_E_INVAL;
+    ah_handle* h = nullptr;
+    int rc = ah_create(p, nullptr, 0, nullptr, &h);
+    if (rc != AH_OK) return rc;
+    rc = ah_init(h, 0);
+    std::vector<std::pair<int, int>> tiles = {{64, 8}, {64, 4}, {32, 8}};
+    if (p->precision == AH_FP32) tiles.push_back({64, 16});
+    std::vector<int> zcs = {0, p->N};
+    for (int div : {2, 4, 8})
+        if (p->N / div >= 8) zcs.push_back(p->N / div);
+    ah_step_config bcfg{};
+    double bms = 1e300;
+    for (auto& t : tiles) {
+        for (int zc : zcs) {
+            if (rc != AH_OK) break;
+            ah_step_config c{AH_KERNEL_TILE, t.first, t.second, zc};
+            if (ah_set_step_config(h, &c) != AH_OK) continue;
+            rc = ah_step(h, 2);
+            if (rc == AH_OK) rc = ah_set_timing(h, 1);
+            if (rc == AH_OK) rc = ah_step(h, steps);
+            double ms = 0.0;
+            int64_t n = 0;
+            if (rc == AH_OK) rc = ah_get_timing(h, &ms, &n);
+            if (rc == AH_OK) rc = ah_set_timing(h, 0);
+            if (rc == AH_OK && n > 0 && ms / n < bms) {
+                bms = ms / n;
+                (void)ah_get_step_config(h, &bcfg);
+            }
+        }
+    }
+    ah_destroy(h);
+    if (rc != AH_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table[{p->precision, p->N}] = Entry{bcfg, bms};
+    }
+    if (best) *best = bcfg;
+    if (best_ms) *best_ms = bms;
+    return AH_OK;
+}
+
+int ah_tune_lookup(const ah_params* p, ah_step_config* out)
+{
+    if (!p || !out) return AH_E_INVAL;
+    return ah::tuned_config(*p, out) ? AH_OK : AH_E_AGAIN;
+}
+
+int ah_tune_set(const ah_params* p, const ah_step_config* c)
+{
+    if (!p || !c) return AH_E_INVAL;
+    if (c->kernel != AH_KERNEL_TILE) return AH_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table[{p->precision, p->N}] = Entry{*c, 0.0};
+    return AH_OK;
+}
+
+int ah_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.clear();
+    return AH_OK;
+}
+
+int ah_tune_save(const char* path)
+{
+    if (!path) return AH_E_INVAL;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return AH_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::fprintf(f, "{\"version\": 1, \"entries\": [\n");
+    size_t i = 0;
+    for (auto& kv : g_table) {
+        std::fprintf(f, "{\"precision\": \"%s\", \"N\": %d, \"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, \"ms\": %.6g}%s\n",
+                     kv.first.first == AH_FP64 ? "fp64" : "fp32", kv.first.second, kv.second.cfg.tile_x,
+                     kv.second.cfg.tile_y, kv.second.cfg.zchunk, kv.second.ms, ++i < g_table.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    std::fclose(f);
+    return AH_OK;
+}
+
+int ah_tune_load(const char* path)
+{
+    if (!path) return AH_E_INVAL;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return AH_E_INVAL;
+    char line[512];
+    int loaded = 0;
+    while (std::fgets(line, sizeof(line), f)) {
+        char prec[8] = {0};
+        int N, tx, ty, zc;
+        double ms;
+        if (std::sscanf(line, " {\"precision\": \"%7[a-z0-9]\", \"N\": %d, \"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, \"ms\": %lf",
+                        prec, &N, &tx, &ty, &zc, &ms) == 6) {
+            const int pr = std::strcmp(prec, "fp64") == 0 ? AH_FP64 : AH_FP32;
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_table[{pr, N}] = Entry{ah_step_config{AH_KERNEL_TILE, tx, ty, zc}, ms};
+            ++loaded;
+        }
+    }
+    std::fclose(f);
+    return loaded >= 0 ? AH_OK : AH_E_INVAL;
+}
+
+}  // extern "C"

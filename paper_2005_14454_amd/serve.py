@@ -1,0 +1,155 @@
+"""Serving loop: simulation requests arrive over time and share one GPU.
+
+Requests (lattice size, expansion rate, coupling-scaling exponent, seed,
+precision) arrive as a Poisson stream.  Each is admitted into a lattice pool
+as soon as a slot and enough contiguous HBM for its footprint are free;
+admitted lattices stay resident and are advanced together, one graph replay
+per step (continuous batching: requests that arrive while others run join
+the next replay).  A request completes when its last diagnostics record is
+on the host; time-to-completion (TTC) runs from arrival to that moment.
+
+`python -m paper_2005_14454_amd.serve --requests 500` runs the full stream;
+the function `run_stream` is what bench.py calls.
+"""
+import argparse
+import json
+import math
+import sys
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Params, Pool, pool_footprint
+
+
+@dataclass
+class Request:
+    rid: int
+    params: Params
+    seed: int
+    nsteps: int
+    measure_every: int
+    arrival: float
+    pair_of: int = -1          # index of the FP32 request this FP64 rerun checks
+    admitted: float = math.nan
+    done: float = math.nan
+    pool_id: int = -1
+    series: list = field(default_factory=list)
+
+
+def steps_to_half_light_crossing(N: int, dx: float = 0.5, deta: float = 0.1, eta0: float = 1.0) -> int:
+    """Steps from eta0 until the horizon reaches half the box, eta = dx N / 2."""
+    return int(round((0.5 * dx * N - eta0) / deta))
+
+
+def make_stream(n: int, rate: float, seed: int = 5, nmin: int = 64, nmax: int = 512, fp64_every: int = 10,
+                measure_every: int = 10):
+    """n FP32 requests with N log-uniform on [nmin, nmax], m in {1, 2}, s in
+    {0, 1}, random seeds, Poisson arrivals at `rate` per second; every
+    fp64_every-th request is followed by an FP64 rerun of the same lattice
+    arriving at the same time."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    t = 0.0
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        N = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        m = float(rng.choice([1.0, 2.0]))
+        s = float(rng.choice([0.0, 1.0]))
+        lat_seed = int(rng.integers(0, 2 ** 63 - 1))
+        p = Params(N=N, precision="fp32", m=m, s_early=s, s_late=s)
+        nsteps = steps_to_half_light_crossing(N)
+        reqs.append(Request(len(reqs), p, lat_seed, nsteps, measure_every, t))
+        if fp64_every > 0 and i % fp64_every == 0:
+            p64 = Params(N=N, precision="fp64", m=m, s_early=s, s_late=s)
+            reqs.append(Request(len(reqs), p64, lat_seed, nsteps, measure_every, t, pair_of=len(reqs) - 1))
+    return reqs
+
+
+def run_stream(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 2, log=None):
+    """Serve the requests; returns a summary dict and fills the Request records."""
+    pool = Pool(hbm_budget, max_slots)
+    future = deque(sorted(reqs, key=lambda r: r.arrival))
+    waiting = []
+    by_pool = {}
+    done = 0
+    site_updates = 0
+    t0 = time.perf_counter()
+    try:
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while future and future[0].arrival <= now:
+                waiting.append(future.popleft())
+            # first-fit admission in arrival order
+            still = []
+            for r in waiting:
+                pid = pool.submit(r.params, r.seed, r.nsteps, r.measure_every)
+                if pid is None:
+                    still.append(r)
+                    continue
+                r.admitted = time.perf_counter() - t0
+                r.pool_id = pid
+                by_pool[pid] = r
+            waiting = still
+            if by_pool:
+                pool.advance(chunk)
+                for pid in pool.poll():
+                    r = by_pool.pop(pid)
+                    r.series = pool.results(pid)
+                    r.done = time.perf_counter() - t0
+                    site_updates += r.params.N ** 3 * r.nsteps
+                    done += 1
+                    if log:
+                        log(f"done {r.rid} N={r.params.N} {r.params.precision} ttc={r.done - r.arrival:.3f}s")
+            elif future:
+                time.sleep(max(0.0, min(0.05, future[0].arrival - (time.perf_counter() - t0))))
+            elif waiting:
+                raise RuntimeError("a waiting request can never be admitted (budget too small)")
+        wall = time.perf_counter() - t0
+    finally:
+        pool.close()
+    ttc = np.array([r.done - r.arrival for r in reqs])
+    dev = []
+    for r in reqs:
+        if r.pair_of >= 0:
+            a = reqs[r.pair_of].series[-1]["L_W"]
+            b = r.series[-1]["L_W"]
+            dev.append(abs(a - b) / b if b else 0.0)
+    return {
+        "requests": len(reqs),
+        "wall_s": wall,
+        "site_updates": site_updates,
+        "throughput_su_per_s": site_updates / wall,
+        "ttc_p50_s": float(np.percentile(ttc, 50)),
+        "ttc_p99_s": float(np.percentile(ttc, 99)),
+        "ttc_mean_s": float(ttc.mean()),
+        "fp32_vs_fp64_LW_rel_dev_max": max(dev) if dev else None,
+        "fp32_vs_fp64_LW_rel_dev_mean": float(np.mean(dev)) if dev else None,
+        "fp64_spot_checks": len(dev),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--requests", type=int, default=500)
+    ap.add_argument("--rate", type=float, default=0.0, help="arrivals per second; 0 = 0.7 x measured capacity")
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--nmin", type=int, default=64)
+    ap.add_argument("--nmax", type=int, default=512)
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--capacity-su", type=float, default=3.0e10, help="site-updates/s used to set the rate")
+    args = ap.parse_args(argv)
+    probe = make_stream(args.requests, 1.0, args.seed, args.nmin, args.nmax)
+    work = np.mean([r.params.N ** 3 * r.nsteps for r in probe])
+    rate = args.rate if args.rate > 0 else 0.7 * args.capacity_su / work
+    reqs = make_stream(args.requests, rate, args.seed, args.nmin, args.nmax)
+    out = run_stream(reqs, int(args.budget_gb * 1e9), log=lambda s: print(s, file=sys.stderr, flush=True))
+    out["arrival_rate_per_s"] = rate
+    out["mean_site_updates_per_request"] = float(work)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

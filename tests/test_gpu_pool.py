@@ -1,0 +1,147 @@
+"""The lattice pool (batched persistent step, continuous batching).
+
+- every lattice advanced in the pool is bitwise identical, fields and
+  diagnostics series, to the same lattice run alone through ah_step/ah_measure
+  with the same tile shape;
+- a pool lattice matches the oracle;
+- admission by footprint: requests that do not fit now are refused with
+  AH_E_AGAIN (submit returns None), requests larger than the budget raise;
+- lattices of different lengths finish at different steps and are reported
+  once each; memory returns to the pool.
+"""
+import numpy as np
+import pytest
+
+from helpers import both_params, field_scaled_error
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ah():
+    import paper_2005_14454_amd as ah
+    return ah
+
+
+def same_record(a, b):
+    """Bitwise equality of two measurement dicts (NaN equals NaN)."""
+    if a.keys() != b.keys():
+        return False
+    for k in a:
+        x, y = a[k], b[k]
+        if isinstance(x, float) and isinstance(y, float):
+            if not (x == y or (np.isnan(x) and np.isnan(y))):
+                return False
+        elif x != y:
+            return False
+    return True
+
+
+def _alone(ah, gp, seed, nsteps, every, tile):
+    """Run one lattice alone: fields after nsteps and the diagnostics series."""
+    series = []
+    with ah.Lattice(gp) as lat:
+        lat.set_step_config("tile", tile, 0)
+        lat.init(seed)
+        for k in range(nsteps + 1):
+            if k == nsteps or (every > 0 and k % every == 0):
+                series.append(lat.measure())
+            if k < nsteps:
+                lat.step(1)
+        return lat.get_state(), series
+
+
+def test_pool_alone_vs_mix_bitwise(ah):
+    from paper_2005_14454_amd import Params
+    reqs = [
+        (Params(N=16, precision="fp32", m=1.0), 11, 25, 5),
+        (Params(N=40, precision="fp64", m=2.0), 12, 18, 6),
+        (Params(N=24, precision="fp32", m=2.0, s_early=1.0, s_late=1.0), 13, 30, 10),
+        (Params(N=64, precision="fp32", m=1.0), 14, 12, 4),
+        (Params(N=20, precision="fp64", m=1.0), 15, 22, 0),
+    ]
+    with ah.Pool(hbm_budget=1 << 30, max_slots=16) as pool:
+        ids = [pool.submit(p, seed, n, every) for p, seed, n, every in reqs]
+        assert all(i is not None for i in ids)
+        states, series = {}, {}
+        finished = []
+        for step in range(40):
+            pool.advance(1)
+            for rid in pool.poll():
+                finished.append(rid)
+                k = ids.index(rid)
+                states[rid] = pool.get_state(rid, reqs[k][0].N)
+                series[rid] = pool.results(rid)
+        assert sorted(finished) == sorted(ids)
+        assert pool.stats()["active"] == 0 and pool.stats()["bytes_in_use"] == 0
+    for (p, seed, n, every), rid in zip(reqs, ids):
+        st, ser = _alone(ah, p, seed, n, every, (64, 8))
+        assert np.array_equal(states[rid], st), (p, seed)
+        assert len(series[rid]) == len(ser)
+        for a, b in zip(series[rid], ser):
+            assert same_record(a, b), (p.N, a["step"], b["step"])
+
+
+def test_pool_matches_oracle(oracle_mod, ah):
+    op, gp = both_params(oracle_mod, 20, "fp64", m=2.0)
+    with ah.Pool(hbm_budget=256 << 20, max_slots=4) as pool:
+        rid = pool.submit(gp, 3, 30, 10)
+        pool.advance(31)
+        assert pool.poll() == [rid]
+        st = pool.get_state(rid, 20)
+        ser = pool.results(rid)
+    ref = oracle_mod.step(op, oracle_mod.init(op, 3), 0, 30)
+    assert max(field_scaled_error(st, ref).values()) <= 1e-10
+    assert [m["step"] for m in ser] == [0, 10, 20, 30]
+    om = oracle_mod.measure(op, st, 30)
+    assert ser[-1]["winding_sum_abs"] == om["winding_sum_abs"]
+    assert abs(ser[-1]["energy"] - om["energy"]) <= 1e-10 * abs(om["energy"])
+
+
+def test_pool_admission_by_footprint(ah):
+    from paper_2005_14454_amd import Params, pool_footprint, AHError
+    p = Params(N=32, precision="fp32")
+    fp = pool_footprint(p, 10, 5)
+    assert fp >= 15 * 4 * 32 ** 3
+    with ah.Pool(hbm_budget=int(2.5 * fp), max_slots=8) as pool:
+        a = pool.submit(p, 1, 10, 5)
+        b = pool.submit(p, 2, 10, 5)
+        assert a is not None and b is not None
+        assert pool.submit(p, 3, 10, 5) is None          # does not fit now
+        with pytest.raises(AHError):
+            pool.submit(Params(N=64, precision="fp64"), 4, 10, 5)  # larger than the budget
+        assert pool.stats()["bytes_in_use"] <= pool.stats()["budget"]
+        pool.advance(11)
+        assert sorted(pool.poll()) == sorted([a, b])
+        pool.results(a)
+        c = pool.submit(p, 3, 10, 5)                       # fits once memory is back
+        assert c is not None
+        pool.advance(11)
+        assert pool.poll() == [c]
+        assert len(pool.results(c)) == 3
+    with ah.Pool(hbm_budget=1 << 28, max_slots=1) as pool:
+        assert pool.submit(p, 1, 5, 0) is not None
+        assert pool.submit(p, 2, 5, 0) is None             # no free slot
+
+
+def test_pool_staggered_completion_and_progress(ah):
+    from paper_2005_14454_amd import Params
+    with ah.Pool(hbm_budget=512 << 20, max_slots=8) as pool:
+        ids = [pool.submit(Params(N=16, precision="fp32"), s, n, 0) for s, n in ((1, 3), (2, 7), (3, 12))]
+        done_at = {}
+        for step in range(1, 16):
+            pool.advance(1)
+            for rid in pool.poll():
+                done_at[rid] = step
+        assert done_at == {ids[0]: 4, ids[1]: 8, ids[2]: 13}
+        # a lattice admitted while others run joins the same graph
+        late = pool.submit(Params(N=24, precision="fp64"), 9, 5, 2)
+        assert pool.progress(late) == (0, 5)
+        pool.advance(2)
+        assert pool.progress(late) == (2, 5)
+        pool.advance(4)
+        assert pool.poll() == [late]
+        ser = pool.results(late)
+        assert [m["step"] for m in ser] == [0, 2, 4, 5]
+        for rid in ids:
+            assert len(pool.results(rid)) == 1
