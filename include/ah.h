@@ -141,10 +141,25 @@ int ah_get_step(const ah_handle* h, int64_t* step);
  * AH_E_STATE before ah_init/ah_set_state. */
 int ah_step(ah_handle* h, int64_t nsteps);
 
-/* All diagnostics of the current snapshot, reduced in FP64 in a fixed order
- * (bitwise reproducible for a given handle configuration).  Windings are
- * computed in FP64 from the stored values even for FP32 lattices.  The
- * snapshot is not modified.  Synchronous. */
+/* Advance nsteps steps; the snapshots n with n % measure_every == 0 among
+ * the ones stepped from (current .. current+nsteps-1) get their diagnostics
+ * in the same pass as their step (the diagnostics read what the step reads).
+ * Writes those records to series (cap >= their number, else AH_E_INVAL) and
+ * their count to *n.  The records equal what ah_measure returns on the same
+ * snapshots.  Compact action only.  Synchronous at the end. */
+int ah_step_measured(ah_handle* h, int64_t nsteps, int32_t measure_every, ah_measurement* series, int32_t cap,
+                     int32_t* n);
+
+/* The part of ah_get_timing that belongs to launches which also formed
+ * diagnostics (ah_step_measured): their summed time (ms) and number, so
+ * that callers can separate plain and measured steps.  Synchronises. */
+int ah_get_timing_split(ah_handle* h, double* measured_ms, int64_t* measured_launches);
+
+/* All diagnostics of the current snapshot, summed in FP64 in a fixed order
+ * (bitwise reproducible for a given handle configuration).  Site densities
+ * are formed in the storage precision; link phases, plaquette angles and
+ * windings in FP64 from the stored values, so windings are exact for FP32
+ * lattices too.  The snapshot is not modified.  Synchronous. */
 int ah_measure(ah_handle* h, ah_measurement* out);
 
 /* Per-plaquette windings of the current snapshot: 3*N^3 int8 values,
@@ -163,7 +178,7 @@ int ah_get_winding(ah_handle* h, int8_t* host_w);
 typedef struct ah_step_config {
     int32_t kernel;         /* AH_KERNEL_* */
     int32_t tile_x, tile_y; /* tiled kernel: (64,8), (64,4), (32,8) (FP32 also (64,16)); 0,0 = default */
-    int32_t zchunk;         /* x2-planes per workgroup of the tiled kernel; 0 = automatic */
+    int32_t zchunk;         /* x2-planes per workgroup of the tiled kernel; 0 = automatic, else >= min(8, N) */
 } ah_step_config;
 
 /* Select the step kernel; AH_E_INVAL for an unsupported combination. */

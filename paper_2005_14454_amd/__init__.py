@@ -140,6 +140,17 @@ class Lattice:
         self._call(self._lib.ah_measure, ctypes.byref(m), what="ah_measure")
         return _meas_dict(m)
 
+    def step_measured(self, nsteps: int, measure_every: int) -> list:
+        """Advance nsteps; snapshots with step % measure_every == 0 that are
+        stepped from get their diagnostics in the same pass (list of dicts)."""
+        cur = self.step_index
+        due = sum(1 for k in range(nsteps) if (cur + k) % measure_every == 0)
+        arr = (_lib.ah_measurement * max(due, 1))()
+        n = ctypes.c_int32()
+        self._call(self._lib.ah_step_measured, nsteps, measure_every, arr, due, ctypes.byref(n),
+                   what="ah_step_measured")
+        return [_meas_dict(arr[k]) for k in range(n.value)]
+
     def synchronize(self):
         self._call(self._lib.ah_synchronize, what="ah_synchronize")
 
@@ -190,6 +201,13 @@ class Lattice:
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         self._call(self._lib.ah_get_timing, ctypes.byref(ms), ctypes.byref(n), what="ah_get_timing")
+        return ms.value, n.value
+
+    def get_timing_split(self):
+        """(ms, launches) of the timed launches that also formed diagnostics."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._call(self._lib.ah_get_timing_split, ctypes.byref(ms), ctypes.byref(n), what="ah_get_timing_split")
         return ms.value, n.value
 
 

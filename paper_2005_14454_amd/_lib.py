@@ -90,6 +90,9 @@ def load():
         "ah_get_step": ([vp, P(i64)], ctypes.c_int),
         "ah_step": ([vp, i64], ctypes.c_int),
         "ah_measure": ([vp, P(ah_measurement)], ctypes.c_int),
+        "ah_step_measured": ([vp, i64, ctypes.c_int32, P(ah_measurement), ctypes.c_int32, P(ctypes.c_int32)],
+                             ctypes.c_int),
+        "ah_get_timing_split": ([vp, P(ctypes.c_double), P(i64)], ctypes.c_int),
         "ah_get_winding": ([vp, P(ctypes.c_int8)], ctypes.c_int),
         "ah_set_step_config": ([vp, P(ah_step_config)], ctypes.c_int),
         "ah_get_step_config": ([vp, P(ah_step_config)], ctypes.c_int),

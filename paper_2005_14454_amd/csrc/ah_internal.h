@@ -62,8 +62,6 @@ enum MeasSlot {
 constexpr int kMeasStride = 16;        // doubles per partial record
 constexpr int kMeasBlocks = 2048;      // fixed grid of the measurement kernel
 constexpr int kMeasThreads = 256;
-constexpr int kMeasTileX = 64;         // tile of the tiled diagnostics pass
-constexpr int kMeasTileY = 8;
 
 struct MeasConst {
     double inv_2e2f;   // 1 / (2 e0^2 f)
@@ -93,6 +91,7 @@ struct PoolLattice {
     int64_t series_cap;
     int N, tiles_x, tiles_y, zchunk;     // step tiling
     int meas_zchunk, meas_blocks, measure_every, precision;
+    int gauss_blocks, pad1;  // Gauss records follow the meas_blocks step records
     int compact, pad0;
     double dx, deta, sigma2;
 };
@@ -109,13 +108,27 @@ template <typename R>
 hipError_t launch_step(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2,
                        const LatticeConst& L, const StepCoef& c, hipStream_t s);
 
+// Tiled step; with mc != nullptr also the diagnostics of the snapshot read
+// (one record per workgroup into partials, in tile order); write = false
+// leaves the fields untouched (diagnostics only).
 template <typename R>
 hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2, const LatticeConst& L,
-                            const StepCoef& c, const TileConfig& tc, hipStream_t s);
+                            const StepCoef& c, const TileConfig& tc, const MeasConst* mc, double* partials,
+                            bool write, hipStream_t s);
+
+// workgroups (= diagnostics records) of one tiled launch
+int step_tile_blocks(int N, const TileConfig& tc);
+
+// Gauss-residual pass: gauss_blocks(N) records (Gauss slots only) into partials
+int gauss_blocks(int N);
+template <typename R>
+hipError_t launch_gauss(const Fields<R>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s);
+template <typename R>
+hipError_t launch_gauss_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int grid, hipStream_t s);
 
 template <typename R>
 hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,
-                             hipStream_t s);
+                             bool measured, hipStream_t s);
 
 template <typename R>
 hipError_t launch_measure(const Fields<R>& f, const LatticeConst& L, const StepCoef& c,
@@ -124,15 +137,6 @@ hipError_t launch_measure(const Fields<R>& f, const LatticeConst& L, const StepC
 // second-stage fold of nblocks per-workgroup records into result[M_COUNT]
 hipError_t launch_measure_final(const double* partials, int nblocks, double* result, hipStream_t s);
 
-// number of workgroups (= partial records) of the tiled diagnostics pass
-int measure_tile_blocks(int N, int zchunk);
-
-template <typename R>
-hipError_t launch_measure_tile(const Fields<R>& f, const LatticeConst& L, const StepCoef& c, const MeasConst& mc,
-                               int zchunk, double* partials, double* result, hipStream_t s);
-
-template <typename R>
-hipError_t launch_measure_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int grid, hipStream_t s);
 hipError_t launch_fold_batch(const PoolLattice* lat, int nlat, hipStream_t s);
 hipError_t launch_advance_batch(const PoolLattice* lat, int nlat, hipStream_t s);
 

@@ -31,7 +31,6 @@ namespace ah {
 int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_config* out, std::string* why);
 int validate_params(const ah_params* p, std::string* why);
 void coef_row(const ah_params& p, int64_t n, double* row);
-int meas_zchunk_for(int N);
 void to_measurement(const ah_params& p, int64_t step, const double* r, int64_t V, ah_measurement* out);
 bool tuned_config(const ah_params& p, ah_step_config* out);
 }  // namespace ah
@@ -55,19 +54,20 @@ struct Slot {
 
 struct Footprint {
     size_t field, fields, partials, coef, series, total;
-    int meas_blocks, meas_zc;
+    int meas_blocks, meas_zc, gauss_blocks;
     int64_t series_cap;
 };
 
-Footprint footprint(const ah_params& p, int64_t nsteps, int measure_every)
+Footprint footprint(const ah_params& p, const ah_step_config& cfg, int64_t nsteps, int measure_every)
 {
     Footprint f{};
     const size_t V = (size_t)p.N * p.N * p.N;
     f.field = align_up(V * (p.precision == AH_FP64 ? 8 : 4));
     f.fields = 15 * f.field;
-    f.meas_zc = meas_zchunk_for(p.N);
-    f.meas_blocks = measure_tile_blocks(p.N, f.meas_zc);
-    f.partials = align_up((size_t)f.meas_blocks * kMeasStride * sizeof(double));
+    f.meas_zc = cfg.zchunk;
+    f.meas_blocks = step_tile_blocks(p.N, TileConfig{cfg.tile_x, cfg.tile_y, cfg.zchunk});
+    f.gauss_blocks = gauss_blocks(p.N);
+    f.partials = align_up((size_t)(f.meas_blocks + f.gauss_blocks) * kMeasStride * sizeof(double));
     f.coef = align_up((size_t)(nsteps + 1) * kCoefStride * sizeof(double));
     f.series_cap = (measure_every > 0 ? nsteps / measure_every + 1 : 0) + 1;
     f.series = align_up((size_t)f.series_cap * kSeriesStride * sizeof(double));
@@ -176,22 +176,23 @@ int rebuild(ah_pool* P)
             desc[i].counter = P->d_counters + 2 * i;
         }
     }
-    // work lists: measurement per precision, step per (precision, tile shape)
+    // work lists: one per (precision, tile shape); the measured-step node and
+    // the plain-step node of a group share it
     struct Group {
         int precision, tx, ty;
         size_t off, n;
     };
     std::vector<WorkItem> work;
-    std::vector<Group> meas_groups, step_groups;
+    std::vector<Group> step_groups, gauss_groups;
     for (int prec : {AH_FP32, AH_FP64}) {
         Group g{prec, 0, 0, work.size(), 0};
         for (int i = 0; i < nslot; ++i) {
             const Slot& s = P->slots[i];
             if (!s.used || s.p.precision != prec) continue;
-            for (int t = 0; t < s.d.meas_blocks; ++t) work.push_back({i, t});
+            for (int t = 0; t < s.d.gauss_blocks; ++t) work.push_back({i, t});
         }
         g.n = work.size() - g.off;
-        if (g.n) meas_groups.push_back(g);
+        if (g.n) gauss_groups.push_back(g);
     }
     std::map<std::tuple<int, int, int>, std::vector<int>> by_shape;
     for (int i = 0; i < nslot; ++i)
@@ -231,19 +232,25 @@ int rebuild(ah_pool* P)
     e = hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return phip(P, e, "pool graph capture begin");
     hipError_t le = hipSuccess;
-    for (auto& g : meas_groups) {
-        const int grid = (int)std::min<size_t>(g.n, 1024);
-        le = g.precision == AH_FP64 ? launch_measure_batch<double>(P->d_lat, P->d_work + g.off, (int)g.n, grid, P->stream)
-                                    : launch_measure_batch<float>(P->d_lat, P->d_work + g.off, (int)g.n, grid, P->stream);
-        if (le != hipSuccess) break;
-    }
-    if (le == hipSuccess) le = launch_fold_batch(P->d_lat, nslot, P->stream);
-    for (auto& g : step_groups) {
+    // Gauss residual of the due snapshots (read-only, before anything is
+    // overwritten), measured steps of the due lattices, their fold, the plain
+    // steps of all others, the counter update
+    for (auto& g : gauss_groups) {
         if (le != hipSuccess) break;
         const int grid = (int)std::min<size_t>(g.n, 2048);
-        le = g.precision == AH_FP64
-                 ? launch_step_batch<double>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx, g.ty, grid, P->stream)
-                 : launch_step_batch<float>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx, g.ty, grid, P->stream);
+        le = g.precision == AH_FP64 ? launch_gauss_batch<double>(P->d_lat, P->d_work + g.off, (int)g.n, grid, P->stream)
+                                    : launch_gauss_batch<float>(P->d_lat, P->d_work + g.off, (int)g.n, grid, P->stream);
+    }
+    for (int measured = 1; measured >= 0; --measured) {
+        for (auto& g : step_groups) {
+            if (le != hipSuccess) break;
+            const int grid = (int)std::min<size_t>(g.n, measured ? 1024 : 2048);
+            le = g.precision == AH_FP64 ? launch_step_batch<double>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx,
+                                                                    g.ty, grid, measured != 0, P->stream)
+                                        : launch_step_batch<float>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx, g.ty,
+                                                                   grid, measured != 0, P->stream);
+        }
+        if (measured && le == hipSuccess) le = launch_fold_batch(P->d_lat, nslot, P->stream);
     }
     if (le == hipSuccess) le = launch_advance_batch(P->d_lat, nslot, P->stream);
     e = hipStreamEndCapture(P->stream, &P->graph);
@@ -308,11 +315,30 @@ int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_po
     return AH_OK;
 }
 
+// Tile configuration of a pool lattice: the tuned (or default) tile shape,
+// with whole-column z-chunks of at least 64 planes (the pool supplies the
+// parallelism that small z-chunks buy a lattice run alone).
+static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why)
+{
+    if (!tuned_config(p, cfg)) {
+        int rc = resolve_step_config(p, ah_step_config{AH_KERNEL_TILE, 0, 0, 0}, cfg, why);
+        if (rc != AH_OK) return rc;
+    }
+    if (cfg->tile_y == 16) cfg->tile_y = 8;  // 512-thread tiles: the measured node does not spill
+    int zc = cfg->zchunk < 64 ? 64 : cfg->zchunk;
+    if (zc > p.N) zc = p.N;
+    cfg->zchunk = zc;
+    return AH_OK;
+}
+
 int ah_pool_footprint(const ah_params* p, int64_t nsteps, int32_t measure_every, size_t* bytes)
 {
     std::string why;
     if (validate_params(p, &why) != AH_OK || nsteps < 0 || measure_every < 0 || !bytes) return AH_E_INVAL;
-    *bytes = footprint(*p, nsteps, measure_every).total;
+    if (p->gauge_action != AH_COMPACT) return AH_E_INVAL;
+    ah_step_config cfg;
+    if (pool_config(*p, &cfg, &why) != AH_OK) return AH_E_INVAL;
+    *bytes = footprint(*p, cfg, nsteps, measure_every).total;
     return AH_OK;
 }
 
@@ -325,11 +351,9 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
     if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
     ah_step_config cfg{AH_KERNEL_TILE, 0, 0, 0};
     if (p->gauge_action != AH_COMPACT) return pfail(P, AH_E_INVAL, "ah_pool_submit: the pool runs the compact action");
-    if (!tuned_config(*p, &cfg)) {
-        rc = resolve_step_config(*p, ah_step_config{AH_KERNEL_TILE, 0, 0, 0}, &cfg, &why);
-        if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
-    }
-    const Footprint fp = footprint(*p, nsteps, measure_every);
+    rc = pool_config(*p, &cfg, &why);
+    if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
+    const Footprint fp = footprint(*p, cfg, nsteps, measure_every);
     if (fp.total > P->budget) return pfail(P, AH_E_NOMEM, "ah_pool_submit: request larger than the pool budget");
     int slot = -1;
     for (int i = 0; i < (int)P->slots.size(); ++i)
@@ -379,6 +403,7 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
     d.zchunk = cfg.zchunk;
     d.meas_zchunk = fp.meas_zc;
     d.meas_blocks = fp.meas_blocks;
+    d.gauss_blocks = fp.gauss_blocks;
     d.measure_every = measure_every;
     d.precision = p->precision;
     d.compact = 1;

@@ -29,7 +29,9 @@ struct ah_handle {
     void* mom[5] = {};
     double* partials = nullptr;
     double* result = nullptr;
+    double* series = nullptr;       // kSeriesCap folded records (ah_step_measured)
     double* host_result = nullptr;  // pinned
+    double* host_series = nullptr;  // pinned, kSeriesCap records
     int cur = 0;
     int64_t step = 0;
     bool ready = false;
@@ -37,6 +39,8 @@ struct ah_handle {
     std::vector<hipEvent_t> ev;  // start/stop pairs
     size_t ev_used = 0;
     ah_step_config cfg{AH_KERNEL_AUTO, 0, 0, 0};
+    int64_t measured_launches = 0;  // timed launches that also formed diagnostics
+    std::vector<char> ev_measured;  // per event pair: 1 if that launch formed diagnostics
     std::string err;
 };
 
@@ -164,34 +168,32 @@ size_t field_bytes(const ah_params& p)
     return align_up(V * (p.precision == AH_FP64 ? 8 : 4));
 }
 
-}  // namespace
+// smallest z-chunk the tiled kernels accept for a lattice of side N
+int min_zchunk(int N) { return N < 8 ? N : 8; }
 
-namespace ah {
-// x2-planes per workgroup of the tiled diagnostics pass: about 2048 workgroups
-int meas_zchunk_for(int N)
-{
-    const int64_t tiles = (int64_t)((N + kMeasTileX - 1) / kMeasTileX) * ((N + kMeasTileY - 1) / kMeasTileY);
-    int64_t zc = (int64_t)N * tiles / 2048;
-    if (zc < 8) zc = 8;
-    if (zc > N) zc = N;
-    return (int)zc;
-}
-
-}  // namespace ah
-
-namespace {
-int meas_zchunk(int N) { return meas_zchunk_for(N); }
-
+// Diagnostics records a handle can hold: the largest number of workgroups
+// of any supported tile shape at the smallest z-chunk.
 size_t partial_records(const ah_params& p)
 {
-    const int nb = measure_tile_blocks(p.N, meas_zchunk(p.N));
-    return (size_t)(nb > kMeasBlocks ? nb : kMeasBlocks);
+    const int N = p.N;
+    const int zc = min_zchunk(N);
+    const int64_t tz = (N + zc - 1) / zc;
+    int64_t best = 0;
+    const int shapes[4][2] = {{64, 8}, {64, 4}, {32, 8}, {64, 16}};
+    for (auto& s : shapes) {
+        const int64_t t = (int64_t)((N + s[0] - 1) / s[0]) * ((N + s[1] - 1) / s[1]) * tz;
+        if (t > best) best = t;
+    }
+    best += gauss_blocks(N);
+    return (size_t)(best > kMeasBlocks ? best : kMeasBlocks);
 }
+
+constexpr int kSeriesCap = 1024;  // device measurement records per ah_step_measured batch
 
 size_t required_bytes(const ah_params& p)
 {
     return 15 * field_bytes(p) + align_up(partial_records(p) * kMeasStride * sizeof(double)) +
-           align_up(kMeasStride * sizeof(double));
+           align_up(kMeasStride * sizeof(double)) + align_up((size_t)kSeriesCap * kMeasStride * sizeof(double));
 }
 
 template <typename R>
@@ -288,8 +290,8 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
         *why = "unsupported tile shape";
         return AH_E_INVAL;
     }
-    if (c.zchunk < 0) {
-        *why = "zchunk must be >= 0";
+    if (c.zchunk < 0 || (c.zchunk > 0 && c.zchunk < min_zchunk(p.N))) {
+        *why = "zchunk must be 0 (automatic) or at least min(8, N)";
         return AH_E_INVAL;
     }
     if (c.zchunk == 0) {
@@ -367,6 +369,77 @@ int resolve_config(const ah_params& p, const ah_step_config& in, ah_step_config*
     return resolve_step_config(p, in, out, why);
 }
 
+MeasConst meas_const(const ah_params& p, int64_t n)
+{
+    const Scalars sc = scalars_at(p, n);
+    MeasConst mc;
+    mc.inv_2e2f = 1.0 / (2.0 * p.e0 * p.e0 * sc.f);
+    mc.lam_quarter = 0.25 * p.lambda0 * sc.f;
+    mc.gauss_c = gauss_coupling(p, n);
+    return mc;
+}
+
+// Tile configuration used for the diagnostics of a compact-action handle:
+// the step's own when the step is tiled, the default tile otherwise.
+TileConfig meas_tiles(const ah_handle* h)
+{
+    // the 1024-thread tile spills registers when it also forms diagnostics;
+    // its 512-thread half computes the same fields bit for bit
+    if (h->cfg.kernel == AH_KERNEL_TILE && h->cfg.tile_y == 16) return TileConfig{64, 8, h->cfg.zchunk};
+    if (h->cfg.kernel == AH_KERNEL_TILE) return TileConfig{h->cfg.tile_x, h->cfg.tile_y, h->cfg.zchunk};
+    ah_step_config d;
+    std::string why;
+    (void)resolve_step_config(h->p, ah_step_config{AH_KERNEL_TILE, 0, 0, 0}, &d, &why);
+    return TileConfig{d.tile_x, d.tile_y, d.zchunk};
+}
+
+// Diagnostics of the current snapshot folded into dst[M_COUNT] (device), and
+// with `advance` the step of that snapshot in the same pass.
+template <typename R>
+hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
+{
+    const ah_params& p = h->p;
+    const StepCoef c = coef_at(p, h->step);
+    const MeasConst mc = meas_const(p, h->step);
+    const TileConfig tc = meas_tiles(h);
+    const Fields<R> in = fields_of<R>(h, h->cur);
+    const Fields<R> out = fields_of<R>(h, h->cur ^ 1);
+    hipError_t e;
+    if (advance && h->timing) {
+        if (h->ev_used + 2 > h->ev.size()) {
+            for (int k = 0; k < 2; ++k) {
+                hipEvent_t ev;
+                e = hipEventCreate(&ev);
+                if (e != hipSuccess) return e;
+                h->ev.push_back(ev);
+            }
+        }
+        e = hipEventRecord(h->ev[h->ev_used], h->stream);
+        if (e != hipSuccess) return e;
+    }
+    // the Gauss residual reads the snapshot before the step overwrites E
+    const int nb = step_tile_blocks(p.N, tc);
+    e = launch_gauss<R>(in, lconst(p), mc.gauss_c, h->partials + (size_t)nb * kMeasStride, h->stream);
+    if (e != hipSuccess) return e;
+    e = launch_step_tile<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(p), c, tc, &mc, h->partials, advance,
+                            h->stream);
+    if (e != hipSuccess) return e;
+    if (advance && h->timing) {
+        e = hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+        if (e != hipSuccess) return e;
+        h->ev_used += 2;
+        h->measured_launches += 1;
+        h->ev_measured.push_back(1);
+    }
+    e = launch_measure_final(h->partials, nb + gauss_blocks(p.N), dst, h->stream);
+    if (e != hipSuccess) return e;
+    if (advance) {
+        h->cur ^= 1;
+        h->step += 1;
+    }
+    return hipSuccess;
+}
+
 template <typename R>
 hipError_t do_step(ah_handle* h)
 {
@@ -388,7 +461,8 @@ hipError_t do_step(ah_handle* h)
     }
     if (h->cfg.kernel == AH_KERNEL_TILE) {
         const TileConfig tc{h->cfg.tile_x, h->cfg.tile_y, h->cfg.zchunk};
-        e = launch_step_tile<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, tc, h->stream);
+        e = launch_step_tile<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, tc, nullptr, nullptr,
+                                true, h->stream);
     } else {
         e = launch_step<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, h->stream);
     }
@@ -397,6 +471,7 @@ hipError_t do_step(ah_handle* h)
         e = hipEventRecord(h->ev[h->ev_used + 1], h->stream);
         if (e != hipSuccess) return e;
         h->ev_used += 2;
+        h->ev_measured.push_back(0);
     }
     h->cur ^= 1;
     h->step += 1;
@@ -492,8 +567,14 @@ int ah_create(const ah_params* p, void* dev_arena, size_t arena_bytes, void* hip
     h->partials = (double*)base;
     base += align_up(partial_records(*p) * kMeasStride * sizeof(double));
     h->result = (double*)base;
+    base += align_up(kMeasStride * sizeof(double));
+    h->series = (double*)base;
     e = hipHostMalloc((void**)&h->host_result, kMeasStride * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&h->host_series, (size_t)kSeriesCap * kMeasStride * sizeof(double),
+                          hipHostMallocDefault);
     if (e != hipSuccess) {
+        if (h->host_result) (void)hipHostFree(h->host_result);
         if (h->owns_arena) (void)hipFree(h->arena);
         delete h;
         return AH_E_NOMEM;
@@ -616,26 +697,85 @@ int ah_step(ah_handle* h, int64_t nsteps)
     return AH_OK;
 }
 
+int ah_step_measured(ah_handle* h, int64_t nsteps, int32_t measure_every, ah_measurement* series, int32_t cap,
+                     int32_t* n)
+{
+    if (!h || nsteps < 0 || measure_every <= 0 || !n || (cap > 0 && !series))
+        return fail(h, AH_E_INVAL, "ah_step_measured: bad argument");
+    if (!h->ready) return fail(h, AH_E_STATE, "ah_step_measured before ah_init/ah_set_state");
+    if (h->p.gauge_action != AH_COMPACT)
+        return fail(h, AH_E_INVAL, "ah_step_measured: fused diagnostics need the compact action");
+    int64_t due = 0;
+    for (int64_t k = 0; k < nsteps; ++k)
+        if ((h->step + k) % measure_every == 0) ++due;
+    if (due > cap) return fail(h, AH_E_INVAL, "ah_step_measured: more due snapshots than cap");
+    DeviceGuard g(h->device);
+    int32_t written = 0;
+    std::vector<int64_t> steps;
+    auto flush = [&]() -> hipError_t {
+        if (steps.empty()) return hipSuccess;
+        hipError_t e = hipMemcpyAsync(h->host_series, h->series, steps.size() * kMeasStride * sizeof(double),
+                                      hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return e;
+        for (size_t j = 0; j < steps.size(); ++j)
+            to_measurement(h->p, steps[j], h->host_series + j * kMeasStride, h->V, &series[written++]);
+        steps.clear();
+        return hipSuccess;
+    };
+    for (int64_t k = 0; k < nsteps; ++k) {
+        hipError_t e;
+        if (h->step % measure_every == 0) {
+            if ((int)steps.size() == kSeriesCap) {
+                e = flush();
+                if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured copy");
+            }
+            steps.push_back(h->step);
+            double* dst = h->series + (steps.size() - 1) * kMeasStride;
+            e = h->p.precision == AH_FP64 ? measured_pass<double>(h, dst, true) : measured_pass<float>(h, dst, true);
+        } else {
+            e = h->p.precision == AH_FP64 ? do_step<double>(h) : do_step<float>(h);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured launch");
+    }
+    hipError_t e = flush();
+    if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured copy");
+    *n = written;
+    return AH_OK;
+}
+
+int ah_get_timing_split(ah_handle* h, double* measured_ms, int64_t* measured_launches)
+{
+    if (!h || !measured_ms || !measured_launches) return fail(h, AH_E_INVAL, "ah_get_timing_split: bad argument");
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing_split sync");
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+        if (!h->ev_measured[k / 2]) continue;
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing_split elapsed");
+        tot += ms;
+    }
+    *measured_ms = tot;
+    *measured_launches = h->measured_launches;
+    return AH_OK;
+}
+
 int ah_measure(ah_handle* h, ah_measurement* out)
 {
     if (!h || !out) return fail(h, AH_E_INVAL, "ah_measure: bad argument");
     if (!h->ready) return fail(h, AH_E_STATE, "ah_measure before ah_init/ah_set_state");
     DeviceGuard g(h->device);
     const ah_params& p = h->p;
-    const Scalars sc = scalars_at(p, h->step);
-    MeasConst mc;
-    mc.inv_2e2f = 1.0 / (2.0 * p.e0 * p.e0 * sc.f);
-    mc.lam_quarter = 0.25 * p.lambda0 * sc.f;
-    mc.gauss_c = gauss_coupling(p, h->step);
-    const StepCoef c = coef_at(p, h->step);
     hipError_t e;
     if (p.gauge_action == AH_COMPACT) {
-        const int zc = meas_zchunk(p.N);
-        e = p.precision == AH_FP64 ? launch_measure_tile<double>(fields_of<double>(h, h->cur), lconst(p), c, mc, zc,
-                                                                 h->partials, h->result, h->stream)
-                                   : launch_measure_tile<float>(fields_of<float>(h, h->cur), lconst(p), c, mc, zc,
-                                                                h->partials, h->result, h->stream);
+        e = p.precision == AH_FP64 ? measured_pass<double>(h, h->result, false)
+                                   : measured_pass<float>(h, h->result, false);
     } else {
+        const StepCoef c = coef_at(p, h->step);
+        const MeasConst mc = meas_const(p, h->step);
         e = p.precision == AH_FP64 ? launch_measure<double>(fields_of<double>(h, h->cur), lconst(p), c, mc,
                                                             h->partials, h->result, h->stream)
                                    : launch_measure<float>(fields_of<float>(h, h->cur), lconst(p), c, mc,
@@ -686,6 +826,8 @@ int ah_set_timing(ah_handle* h, int enable)
     if (!h) return AH_E_INVAL;
     h->timing = enable != 0;
     h->ev_used = 0;
+    h->measured_launches = 0;
+    h->ev_measured.clear();
     return AH_OK;
 }
 
@@ -714,6 +856,7 @@ int ah_destroy(ah_handle* h)
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t ev : h->ev) (void)hipEventDestroy(ev);
     if (h->host_result) (void)hipHostFree(h->host_result);
+    if (h->host_series) (void)hipHostFree(h->host_series);
     if (h->owns_arena && h->arena) (void)hipFree(h->arena);
     delete h;
     return AH_OK;

@@ -1,4 +1,5 @@
-// Tiled, z-marching leapfrog step for gfx950 (compact gauge action).
+// Tiled, z-marching leapfrog step and diagnostics for gfx950 (compact gauge
+// action), for one lattice and for a pool of lattices.
 //
 // One workgroup owns a TX x TY tile of the (x0, x1) plane and a chunk of
 // x2-planes ("z").  It walks the chunk plane by plane.  For every incoming
@@ -21,6 +22,7 @@
 // is written out, so each site is computed by the same sequence of roundings
 // whatever the tile shape, z-chunk or template instance: results are
 // bitwise reproducible across launch configurations.
+#include "ah_device.h"
 #include "ah_internal.h"
 
 #pragma clang fp contract(off)
@@ -107,6 +109,14 @@ struct StepArgs {
     R dx, sigma2, cP1, cP2, cE1, cE2, lamh, kappa, deta;
 };
 
+// Constants of the diagnostics of the snapshot a measured march reads.
+struct MeasArgs {
+    double dx;          // lattice spacing (FP64, for plaquette angles and links)
+    double inv_2e2f;    // 1 / (2 e0^2 f)
+    double lam_quarter; // lambda0 f / 4
+    double gauss_c;     // coupling of the Gauss residual
+};
+
 template <typename R, int TX, int TY>
 struct TileShared {
     static constexpr int RS = TileGeom<R, TX, TY>::RS;
@@ -114,14 +124,88 @@ struct TileShared {
     Cx<R> Phi[RS];      // phi of plane z
 };
 
+template <int TX, int TY>
+struct MeasShared {
+    static constexpr int RS = (TX + 2) * (TY + 2);
+    float Y[2][3][RS];                  // link phases of planes z (ring of two)
+    double red[TX * TY / 64][M_COUNT];  // block reduction
+};
+
+// FP64 link for the windings of FP32 lattices (the stored value, exactly widened)
+__device__ inline Cx<double> link64(double dx, double a)
+{
+    double s, c;
+    sincos(dx * a, &s, &c);
+    return {c, -s};
+}
+
+// Link phase arg(conj(phi^x) U phi^{x+j}) in (-pi, pi].  z is formed in FP64
+// with plain products and sums; its sign decides the branch exactly as an
+// FP64 atan2 would (-0 -> +0), and the angle itself is evaluated in FP32 on the
+// exactly rescaled z: the windings only need it to well below pi.
+__device__ inline float link_phase(double pr, double pim, Cx<double> U, double vr, double vi)
+{
+    const double wr = U.r * vr - U.i * vi;
+    const double wi = U.r * vi + U.i * vr;
+    const double zr = pr * wr + pim * wi;
+    double zi = pr * wi - pim * wr;
+    zi = (zi == 0.0) ? 0.0 : zi;
+    const double mz = fmax(fabs(zr), fabs(zi));
+    if (mz == 0.0) return signbit(zr) ? 3.14159265358979f : 0.0f;
+    const int e = ilogb(mz);
+    return atan2f((float)ldexp(zi, -e), (float)ldexp(zr, -e));
+}
+
+// Winding of a plaquette from its four link phases and its angle (FP64): the
+// angle is wrapped to (-pi, pi] with the same division and rounding as the
+// definition; the total is then within ~1e-6 of a multiple of 2 pi.
+__device__ inline int winding_of(float y1, float y2, float y3, float y4, double th)
+{
+    const double two_pi = 6.283185307179586;
+    const double thw = th - two_pi * rint(th / two_pi);
+    const double sum = ((((double)y1 + (double)y2) - (double)y3) - (double)y4) + thw;
+    return (int)rint(sum * (1.0 / two_pi));
+}
+
+// 1 - cos(Theta) of a plaquette from its four links, without cancellation
+template <typename R>
+__device__ inline R plaq_omc(Cx<R> ui_x, Cx<R> uj_xi, Cx<R> ui_xj, Cx<R> uj_x, R* sn)
+{
+    const Cx<R> p = cmul(ui_x, uj_xi);
+    const Cx<R> q = cmul(ui_xj, uj_x);
+    const R c = fm(p.r, q.r, p.i * q.i);
+    const R s = fm(p.r, q.i, -(p.i * q.r));
+    *sn = s;
+    return c > R(0) ? (s * s) / (R(1) + c) : R(1) - c;
+}
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 // Walk planes [z0, z1) of the tile whose lower corner is (x0, y0): kick and
-// drift every own site.  All threads of the workgroup must call this with
-// the same arguments; it synchronises the workgroup internally.
-template <typename R, int TX, int TY>
-__device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int x0, int y0, int z0, int z1)
+// drift every own site (if `write`), and with MEAS also form the diagnostics of
+// the snapshot being read (section 2 estimators, energy split, windings),
+// writing the workgroup's fixed-order sums to `record`.  The Gauss residual
+// reads E at the -x and -y neighbours, which neighbouring workgroups of the
+// same pass overwrite in place, so it has a read-only pass of its own
+// (k_gauss) that runs first.
+// All threads of the workgroup call this with the same arguments; it
+// synchronises the workgroup internally.
+template <typename R, int TX, int TY, bool MEAS>
+__device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, const StepArgs<R>& a,
+                           const MeasArgs& ma, double* __restrict__ record, bool write, int x0, int y0, int z0,
+                           int z1)
 {
     using G = TileGeom<R, TX, TY>;
-    constexpr int RW = G::RW, H = G::H;
+    constexpr int RW = G::RW, H = G::H, NT = G::NT;
     static_assert(G::HPT == 1, "halo must fit one extra site per thread");
     auto& sU = sh.U;
     auto& sPhi = sh.Phi;
@@ -143,35 +227,41 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int 
     const int lx = tid % TX, ly = tid / TX;
     const int gx = x0 + lx, gy = y0 + ly;
     const bool active = gx < N && gy < N;
-    const int64_t own_xy = (int64_t)wrapi(gx, N) + (int64_t)N * wrapi(gy, N);
+    const int gxw = wrapi(gx, N), gyw = wrapi(gy, N);
+    const int64_t own_xy = (int64_t)gxw + (int64_t)N * gyw;
     const int ro = (ly + 1) * RW + (lx + 1);  // own region slot
 
     // halo ring site of this thread (if any)
     const bool has_halo = tid < H;
-    int rh = 0;
+    int rh = 0, hrx = 0, hry = 0;
     int64_t halo_xy = 0;
     if (has_halo) {
-        int rx, ry;
         if (tid < RW) {
-            rx = tid;
-            ry = 0;
+            hrx = tid;
+            hry = 0;
         } else if (tid < 2 * RW) {
-            rx = tid - RW;
-            ry = TY + 1;
+            hrx = tid - RW;
+            hry = TY + 1;
         } else if (tid < 2 * RW + TY) {
-            rx = 0;
-            ry = 1 + (tid - 2 * RW);
+            hrx = 0;
+            hry = 1 + (tid - 2 * RW);
         } else {
-            rx = TX + 1;
-            ry = 1 + (tid - 2 * RW - TY);
+            hrx = TX + 1;
+            hry = 1 + (tid - 2 * RW - TY);
         }
-        rh = ry * RW + rx;
-        halo_xy = (int64_t)wrapi(x0 - 1 + rx, N) + (int64_t)N * wrapi(y0 - 1 + ry, N);
+        rh = hry * RW + hrx;
+        halo_xy = (int64_t)wrapi(x0 - 1 + hrx, N) + (int64_t)N * wrapi(y0 - 1 + hry, N);
     }
+    // halo sites whose link phases the windings of the tile read
+    const bool halo_top = has_halo && hry == TY + 1 && hrx >= 1 && hrx <= TX;    // Y_x, Y_z
+    const bool halo_right = has_halo && hrx == TX + 1 && hry >= 1 && hry <= TY;  // Y_y, Y_z
 
     // neighbour slots in the region
     const int rxm = ro - 1, rxp = ro + 1, rym = ro - RW, ryp = ro + RW;
     const int rxm_yp = ro - 1 + RW, rxp_ym = ro + 1 - RW;
+    // neighbour sites in the plane (diagnostics only)
+    const int64_t xp_xy = (int64_t)wrapi(gxw + 1, N) + (int64_t)N * gyw;
+    const int64_t yp_xy = (int64_t)gxw + (int64_t)N * wrapi(gyw + 1, N);
 
     auto plane_of = [&](int z) -> int64_t { return (int64_t)wrapi(z, N) * NN; };
 
@@ -182,6 +272,13 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int 
     Cx<R> phi_m, phi_c, phi_p;
     Cx<R> uz_m;
     R fxz_m, fyz_m;
+    // diagnostics state (MEAS): FP64 links of the own column, own link phases
+    // Y_x, Y_y of the current plane, FP64 sums
+    Cx<double> W64c[3] = {}, W64p[3] = {};
+    float yx_c = 0.f, yy_c = 0.f;
+    double acc[M_COUNT];
+    if constexpr (MEAS)
+        for (int k = 0; k < M_COUNT; ++k) acc[k] = 0.0;
     {
         const int64_t pm = plane_of(z0 - 1), p0 = plane_of(z0);
         const R* A[3] = {f.a0, f.a1, f.a2};
@@ -203,10 +300,23 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int 
         sPhi[ro] = phi_c;
         if (has_halo) sPhi[rh] = Cx<R>{f.phr[p0 + halo_xy], f.phi[p0 + halo_xy]};
         uz_m = um[2];
+        if constexpr (MEAS) {
+            for (int d = 0; d < 3; ++d) {
+                if constexpr (sizeof(R) == 8)
+                    W64c[d] = Cx<double>{(double)Uc[d].r, (double)Uc[d].i};
+                else
+                    W64c[d] = link64(ma.dx, (double)Ac[d]);
+            }
+        }
         __syncthreads();
         // F_xz, F_yz of the own column at plane z0-1
         fxz_m = plaq_sin(um[0], sU[1][2][rxp], Uc[0], um[2]) * inv_dx2;
         fyz_m = plaq_sin(um[1], sU[1][2][ryp], Uc[1], um[2]) * inv_dx2;
+        if constexpr (MEAS) {
+            const Cx<R> px = sPhi[rxp], py = sPhi[ryp];
+            yx_c = link_phase(phi_c.r, phi_c.i, W64c[0], px.r, px.i);
+            yy_c = link_phase(phi_c.r, phi_c.i, W64c[1], py.r, py.i);
+        }
         __syncthreads();
         // U(z0+1) into slot 1
         const int64_t p1 = plane_of(z0 + 1);
@@ -228,6 +338,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int 
     for (int z = z0; z < z1; ++z) {
         const int nxt = cur ^ 1;
         const bool more = z + 1 < z1;  // is there a next iteration?
+        const int zs = (z - z0) & 1;   // link-phase slot of plane z
         // ---- 0. issue loads for the preparation of the next plane and the
         //         own values of the next iteration
         R rA[3] = {0, 0, 0}, hA[3] = {0, 0, 0};
@@ -250,10 +361,64 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int 
             n_e[0] = f.e0[pn + own_xy];
             n_e[1] = f.e1[pn + own_xy];
             n_e[2] = f.e2[pn + own_xy];
+        } else if constexpr (MEAS) {
+            if (has_halo) {
+                const int64_t p1 = plane_of(z + 1);
+                hphi = {f.phr[p1 + halo_xy], f.phi[p1 + halo_xy]};
+            }
         }
         rphi = phi_p;
+        // diagnostics loads: A of the +x / +y neighbours (never written by
+        // this pass) and the halo links of this plane (FP32 lattices)
+        R ay_xp = 0, ax_yp = 0, az_xp = 0, az_yp = 0;
+        R hz[3] = {0, 0, 0};
+        if constexpr (MEAS) {
+            const int64_t pz = (int64_t)z * NN;
+            ay_xp = f.a1[pz + xp_xy];
+            ax_yp = f.a0[pz + yp_xy];
+            az_xp = f.a2[pz + xp_xy];
+            az_yp = f.a2[pz + yp_xy];
+            if constexpr (sizeof(R) == 4) {
+                if (halo_top || halo_right) {
+                    hz[0] = f.a0[pz + halo_xy];
+                    hz[1] = f.a1[pz + halo_xy];
+                    hz[2] = f.a2[pz + halo_xy];
+                }
+            }
+        }
+        float yz_c = 0.f;
+        if constexpr (MEAS) {
+            // ---- link phases of plane z: own and the +x / +y halo
+            yz_c = link_phase(phi_c.r, phi_c.i, W64c[2], phi_p.r, phi_p.i);
+            auto& sY = mx->Y[zs];
+            sY[0][ro] = yx_c;
+            sY[1][ro] = yy_c;
+            sY[2][ro] = yz_c;
+            if (halo_top || halo_right) {
+                const Cx<R> ph = sPhi[rh];
+                Cx<double> hl[3];
+                for (int d = 0; d < 3; ++d) {
+                    if constexpr (sizeof(R) == 8)
+                        hl[d] = Cx<double>{(double)sU[cur][d][rh].r, (double)sU[cur][d][rh].i};
+                    else
+                        hl[d] = link64(ma.dx, (double)hz[d]);
+                }
+                if (halo_top) {
+                    const Cx<R> pn = sPhi[rh + 1];
+                    sY[0][rh] = link_phase(ph.r, ph.i, hl[0], pn.r, pn.i);
+                }
+                if (halo_right) {
+                    const Cx<R> pn = sPhi[rh + RW];
+                    sY[1][rh] = link_phase(ph.r, ph.i, hl[1], pn.r, pn.i);
+                }
+                sY[2][rh] = link_phase(ph.r, ph.i, hl[2], hphi.r, hphi.i);
+            }
+        }
 
         // ---- 1. update of the own site at plane z
+        R fxz_w = 0, fyz_w = 0;  // own plaquette sines (diagnostics reuse)
+        (void)fxz_w;
+        (void)fyz_w;
         {
             const Cx<R> ph_xm = sPhi[rxm], ph_xp = sPhi[rxp], ph_ym = sPhi[rym], ph_yp = sPhi[ryp];
             const Cx<R> ux_xm = sU[cur][0][rxm];  // U_x^{x-kx}
@@ -270,9 +435,19 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int 
             // plaquettes at x (F_ij^x, i<j)
             const Cx<R> uy_xp = sU[cur][1][rxp], ux_yp = sU[cur][0][ryp];
             const Cx<R> uz_xp = sU[cur][2][rxp], uz_yp = sU[cur][2][ryp];
-            const R fxy = plaq_sin(Uc[0], uy_xp, ux_yp, Uc[1]) * inv_dx2;
-            const R fxz = plaq_sin(Uc[0], uz_xp, Up[0], Uc[2]) * inv_dx2;
-            const R fyz = plaq_sin(Uc[1], uz_yp, Up[1], Uc[2]) * inv_dx2;
+            R sxy, sxz, syz, oxy = 0, oxz = 0, oyz = 0;
+            if constexpr (MEAS) {
+                oxy = plaq_omc(Uc[0], uy_xp, ux_yp, Uc[1], &sxy);
+                oxz = plaq_omc(Uc[0], uz_xp, Up[0], Uc[2], &sxz);
+                oyz = plaq_omc(Uc[1], uz_yp, Up[1], Uc[2], &syz);
+            } else {
+                sxy = plaq_sin(Uc[0], uy_xp, ux_yp, Uc[1]);
+                sxz = plaq_sin(Uc[0], uz_xp, Up[0], Uc[2]);
+                syz = plaq_sin(Uc[1], uz_yp, Up[1], Uc[2]);
+            }
+            const R fxy = sxy * inv_dx2;
+            const R fxz = sxz * inv_dx2;
+            const R fyz = syz * inv_dx2;
             // plaquettes at x - kx and x - ky
             const Cx<R> ux_xm_yp = sU[cur][0][rxm_yp], uy_xm = sU[cur][1][rxm], uz_xm = sU[cur][2][rxm];
             const Cx<R> ux_ym = sU[cur][0][rym], uy_xp_ym = sU[cur][1][rxp_ym], uz_ym = sU[cur][2][rym];
@@ -286,13 +461,14 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int 
             const R cy = ((fyz - fyz_m) - (fxy - fxy_xm)) * inv_dx;
             const R cz = -((fxz - fxz_xm) + (fyz - fyz_ym)) * inv_dx;
             // Crank-Nicolson kick, drift
-            const R pot = lamh * fm(phi_c.r, phi_c.r, fm(phi_c.i, phi_c.i, -sigma2));
+            const R m2 = fm(phi_c.r, phi_c.r, fm(phi_c.i, phi_c.i, -sigma2));
+            const R pot = lamh * m2;
             const R npr = fm(cP1, pr_c, cP2 * fm(lr, inv_dx2, -(pot * phi_c.r)));
             const R npi = fm(cP1, pi_c, cP2 * fm(li, inv_dx2, -(pot * phi_c.i)));
             const R ne0 = fm(cE1, e_c[0], cE2 * fm(kappa, jx, -cx));
             const R ne1 = fm(cE1, e_c[1], cE2 * fm(kappa, jy, -cy));
             const R ne2 = fm(cE1, e_c[2], cE2 * fm(kappa, jz, -cz));
-            if (active) {
+            if (write && active) {
                 const int64_t o = (int64_t)z * NN + own_xy;
                 f.pir[o] = npr;
                 f.pii[o] = npi;
@@ -305,24 +481,94 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int 
                 oa1[o] = fm(deta, ne1, Ac[1]);
                 oa2[o] = fm(deta, ne2, Ac[2]);
             }
+            if constexpr (MEAS) {
+                if (active) {
+                    // site densities with centred momenta (average of the stored
+                    // half step and the kick), summed in FP64
+                    const R v[10] = {phi_c.r, phi_c.i, pr_c, pi_c, Ac[0], Ac[1], Ac[2], e_c[0], e_c[1], e_c[2]};
+                    bool bad = false;
+                    for (int k = 0; k < 10; ++k) bad |= !isfinite(v[k]);
+                    acc[M_NONFIN] += bad ? 1.0 : 0.0;
+                    const R pbr = R(0.5) * (pr_c + npr), pbi = R(0.5) * (pi_c + npi);
+                    const double kin = (double)fm(pbr, pbr, pbi * pbi);
+                    const R d0r = fx.r - phi_c.r, d0i = fx.i - phi_c.i;
+                    const R d1r = fy.r - phi_c.r, d1i = fy.i - phi_c.i;
+                    const R d2r = fz.r - phi_c.r, d2i = fz.i - phi_c.i;
+                    const double grad =
+                        (double)(((d0r * d0r + d0i * d0i) + (d1r * d1r + d1i * d1i) + (d2r * d2r + d2i * d2i)) *
+                                 inv_dx2);
+                    const double pot_e = ma.lam_quarter * (double)m2 * (double)m2;
+                    const R eb0 = R(0.5) * (e_c[0] + ne0), eb1 = R(0.5) * (e_c[1] + ne1),
+                            eb2 = R(0.5) * (e_c[2] + ne2);
+                    const double el = (double)(eb0 * eb0 + eb1 * eb1 + eb2 * eb2) * ma.inv_2e2f;
+                    const double mag = (double)(R(2) * (oxy + oxz + oyz) * (inv_dx2 * inv_dx2)) * ma.inv_2e2f;
+                    const double L = kin - grad - pot_e + el - mag;
+                    acc[M_KIN] += kin;
+                    acc[M_GRAD] += grad;
+                    acc[M_POT] += pot_e;
+                    acc[M_EL] += el;
+                    acc[M_MAG] += mag;
+                    acc[M_L] += L;
+                    acc[M_KINL] += kin * L;
+                    acc[M_GRADL] += grad * L;
+                }
+            }
             fxz_m = fxz;
             fyz_m = fyz;
         }
-        if (!more) break;
+        if (!MEAS && !more) break;
         __syncthreads();  // all reads of slot cur and of sPhi (plane z) are done
+
+        if constexpr (MEAS) {
+            // winding of the (x, y) plaquette at x, plane z
+            if (active) {
+                const auto& sY = mx->Y[zs];
+                const double th = ma.dx * ((((double)Ac[0] + (double)ay_xp) - (double)ax_yp) - (double)Ac[1]);
+                acc[M_WABS] += (double)abs(winding_of(yx_c, sY[1][rxp], sY[0][ryp], yy_c, th));
+            }
+        }
 
         // ---- 3. plane z+2 links into slot cur, plane z+1 phi into sPhi
         Cx<R> Upp[3];
-        for (int d = 0; d < 3; ++d) {
-            Upp[d] = link(dx, rA[d]);
-            sU[cur][d][ro] = Upp[d];
+        if (more) {
+            for (int d = 0; d < 3; ++d) {
+                Upp[d] = link(dx, rA[d]);
+                sU[cur][d][ro] = Upp[d];
+            }
+            if (has_halo) {
+                for (int d = 0; d < 3; ++d) sU[cur][d][rh] = link(dx, hA[d]);
+                sPhi[rh] = hphi;
+            }
+            sPhi[ro] = rphi;
+        } else if constexpr (MEAS) {
+            if (has_halo) sPhi[rh] = hphi;
+            sPhi[ro] = rphi;
         }
-        if (has_halo) {
-            for (int d = 0; d < 3; ++d) sU[cur][d][rh] = link(dx, hA[d]);
-            sPhi[rh] = hphi;
-        }
-        sPhi[ro] = rphi;
         __syncthreads();
+
+        if constexpr (MEAS) {
+            // own link phases of plane z+1 and the (x, z), (y, z) windings of plane z
+            for (int d = 0; d < 3; ++d) {
+                if constexpr (sizeof(R) == 8)
+                    W64p[d] = Cx<double>{(double)Up[d].r, (double)Up[d].i};
+                else
+                    W64p[d] = link64(ma.dx, (double)Ap[d]);
+            }
+            const Cx<R> px = sPhi[rxp], py = sPhi[ryp];
+            const float yx_n = link_phase(phi_p.r, phi_p.i, W64p[0], px.r, px.i);
+            const float yy_n = link_phase(phi_p.r, phi_p.i, W64p[1], py.r, py.i);
+            if (active) {
+                const auto& sY = mx->Y[zs];
+                const double thxz = ma.dx * ((((double)Ac[0] + (double)az_xp) - (double)Ap[0]) - (double)Ac[2]);
+                const double thyz = ma.dx * ((((double)Ac[1] + (double)az_yp) - (double)Ap[1]) - (double)Ac[2]);
+                acc[M_WABS] += (double)(abs(winding_of(yx_c, sY[2][rxp], yx_n, yz_c, thxz)) +
+                                        abs(winding_of(yy_c, sY[2][ryp], yy_n, yz_c, thyz)));
+            }
+            yx_c = yx_n;
+            yy_c = yy_n;
+            for (int d = 0; d < 3; ++d) W64c[d] = W64p[d];
+        }
+        if (!more) break;
 
         // ---- 5. rotate the own-column registers
         uz_m = Uc[2];
@@ -340,37 +586,74 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, const StepArgs<R>& a, int 
         pi_c = n_pi;
         cur = nxt;
     }
+
+    if constexpr (MEAS) {
+        // fixed-order block reduction of the diagnostics into one record
+        auto& red = mx->red;
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int k = 0; k < M_COUNT; ++k) {
+            const double r = (k == M_GMAX) ? wave_max(acc[k]) : wave_sum(acc[k]);
+            if (lane == 0) red[wv][k] = r;
+        }
+        __syncthreads();
+        if (tid < M_COUNT) {
+            double r = red[0][tid];
+            for (int w = 1; w < NT / 64; ++w) r = (tid == M_GMAX) ? fmax(r, red[w][tid]) : r + red[w][tid];
+            record[tid] = r;
+        }
+    }
 }
 
-// One lattice: block b owns tile xcd_tile(b) (tx fastest, then ty, then z-chunk).
-template <typename R, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) k_step_tile(StepArgs<R> a, int zchunk, int tiles_x, int tiles_y)
+// One lattice: block b owns tile t = xcd_tile(b) (tx fastest, then ty, then
+// z-chunk); with MEAS it writes diagnostics record t, so the records are in
+// tile order whatever the launch geometry.
+template <typename R, int TX, int TY, bool MEAS>
+__global__ void __launch_bounds__(TX* TY) k_step_tile(StepArgs<R> a, MeasArgs ma, double* partials, int write,
+                                                      int zchunk, int tiles_x, int tiles_y)
 {
     __shared__ TileShared<R, TX, TY> sh;
-    int t = xcd_tile(blockIdx.x, gridDim.x);
+    __shared__ MeasShared<TX, MEAS ? TY : 8> mxs;
+    const int t0 = xcd_tile(blockIdx.x, gridDim.x);
+    int t = t0;
     const int tx = t % tiles_x;
     t /= tiles_x;
     const int ty = t % tiles_y;
     const int tz = t / tiles_y;
     const int z0 = tz * zchunk;
     const int z1 = (z0 + zchunk < a.N) ? z0 + zchunk : a.N;
-    march_step<R, TX, TY>(sh, a, tx * TX, ty * TY, z0, z1);
+    if constexpr (MEAS)
+        march_step<R, TX, TY, true>(sh, &mxs, a, ma, partials + (int64_t)t0 * kMeasStride, write != 0, tx * TX,
+                                    ty * TY, z0, z1);
+    else
+        march_step<R, TX, TY, false>(sh, nullptr, a, ma, nullptr, true, tx * TX, ty * TY, z0, z1);
+}
+
+__device__ inline bool measure_due(const PoolLattice& L, int64_t k)
+{
+    if (k > L.nsteps) return false;
+    if (k == L.nsteps) return true;
+    return L.measure_every > 0 && (k % L.measure_every) == 0;
 }
 
 // Many lattices in one launch: blocks stride over a work list of
-// (lattice, tile) items; each lattice reads its own step counter, skips the
-// work once it has run its steps, and takes the coefficients of its current
-// step from its own FP64 table.
-template <typename R, int TX, int TY>
+// (lattice, tile) items; each lattice reads its own step counter k, takes the
+// coefficients of step k from its own FP64 table, and is skipped once it has
+// run its steps.  MEAS: only lattices whose snapshot k is due for diagnostics
+// (measured step, or measurement alone for the final snapshot); otherwise
+// only lattices that are not due.
+template <typename R, int TX, int TY, bool MEAS>
 __global__ void __launch_bounds__(TX* TY) k_step_batch(const PoolLattice* __restrict__ lat,
                                                        const WorkItem* __restrict__ work, int nwork)
 {
     __shared__ TileShared<R, TX, TY> sh;
+    __shared__ MeasShared<TX, MEAS ? TY : 8> mxs;
     for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
         const WorkItem it = work[w];
         const PoolLattice& L = lat[it.lattice];
         const int64_t k = *L.counter;
-        if (k >= L.nsteps) continue;  // uniform across the block
+        const bool due = measure_due(L, k);
+        if (MEAS != due) continue;                   // uniform across the block
+        if (!MEAS && k >= L.nsteps) continue;
         const double* row = L.coef + k * kCoefStride;
         const int cur = (int)(k & 1);
         StepArgs<R> a;
@@ -391,6 +674,7 @@ __global__ void __launch_bounds__(TX* TY) k_step_batch(const PoolLattice* __rest
         a.lamh = (R)row[C_LAMH];
         a.kappa = (R)row[C_KAPPA];
         a.deta = (R)L.deta;
+        const MeasArgs ma{L.dx, row[C_INV2E2F], row[C_LAMQ], row[C_GAUSS]};
         int t = it.tile;
         const int tx = t % L.tiles_x;
         t /= L.tiles_x;
@@ -398,16 +682,123 @@ __global__ void __launch_bounds__(TX* TY) k_step_batch(const PoolLattice* __rest
         const int tz = t / L.tiles_y;
         const int z0 = tz * L.zchunk;
         const int z1 = (z0 + L.zchunk < L.N) ? z0 + L.zchunk : L.N;
-        march_step<R, TX, TY>(sh, a, tx * TX, ty * TY, z0, z1);
+        if constexpr (MEAS)
+            march_step<R, TX, TY, true>(sh, &mxs, a, ma, L.partials + (int64_t)it.tile * kMeasStride, k < L.nsteps,
+                                        tx * TX, ty * TY, z0, z1);
+        else
+            march_step<R, TX, TY, false>(sh, nullptr, a, ma, nullptr, true, tx * TX, ty * TY, z0, z1);
         __syncthreads();  // LDS is reused by the next item
     }
+}
+
+
+// ------------------------------------------------------------ Gauss residual
+
+// Discrete Gauss law of the snapshot: G^x = sum_i (E_i^x - E_i^{x-i})/dx
+// - c Im[conj(phi^x) Pi^x] on the stored half-step fields, in FP64 from the
+// exactly widened stored values.  Each workgroup walks a fixed grid-stride
+// set of sites of the lattice and writes one record (Gauss slots only).
+template <typename R>
+__device__ void gauss_block(const Fields<R>& f, int N, double inv_dx, double gc, int block, int nblocks,
+                            double* __restrict__ record, double* red)
+{
+    const int64_t V = (int64_t)N * N * N;
+    const int64_t NN = (int64_t)N * N;
+    double g2 = 0.0, d2 = 0.0, c2 = 0.0, gmax = 0.0;
+    for (int64_t s = (int64_t)block * 256 + threadIdx.x; s < V; s += (int64_t)nblocks * 256) {
+        const int x = (int)(s % N), y = (int)((s / N) % N);
+        const int64_t sxm = s + (x == 0 ? N - 1 : -1);
+        const int64_t sym = s + (y == 0 ? NN - N : -(int64_t)N);
+        const int64_t szm = s >= NN ? s - NN : s + V - NN;
+        const double dv = (((double)f.e0[s] - (double)f.e0[sxm]) * inv_dx +
+                           ((double)f.e1[s] - (double)f.e1[sym]) * inv_dx) +
+                          ((double)f.e2[s] - (double)f.e2[szm]) * inv_dx;
+        const double crho = gc * ((double)f.phr[s] * (double)f.pii[s] - (double)f.phi[s] * (double)f.pir[s]);
+        const double G = dv - crho;
+        g2 += G * G;
+        d2 += dv * dv;
+        c2 += crho * crho;
+        gmax = fmax(gmax, fabs(G));
+    }
+    // fixed-order block reduction
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double v[4] = {wave_sum(g2), wave_sum(d2), wave_sum(c2), wave_max(gmax)};
+    if (lane == 0)
+        for (int k = 0; k < 4; ++k) red[wv * 4 + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < kMeasStride) {
+        const int k = threadIdx.x;
+        double r = 0.0;
+        const int slot = k == M_G2 ? 0 : k == M_DIV2 ? 1 : k == M_CRHO2 ? 2 : k == M_GMAX ? 3 : -1;
+        if (slot >= 0) {
+            r = red[slot];
+            for (int w = 1; w < 4; ++w) r = (slot == 3) ? fmax(r, red[w * 4 + slot]) : r + red[w * 4 + slot];
+        }
+        record[k] = r;
+    }
+    __syncthreads();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_gauss(Fields<R> f, int N, double inv_dx, double gc, double* partials)
+{
+    __shared__ double red[16];
+    gauss_block<R>(f, N, inv_dx, gc, blockIdx.x, gridDim.x, partials + (int64_t)blockIdx.x * kMeasStride, red);
+}
+
+// Gauss residual of every pool lattice whose snapshot is due, before it is stepped.
+template <typename R>
+__global__ void __launch_bounds__(256) k_gauss_batch(const PoolLattice* __restrict__ lat,
+                                                     const WorkItem* __restrict__ work, int nwork)
+{
+    __shared__ double red[16];
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const WorkItem it = work[w];
+        const PoolLattice& L = lat[it.lattice];
+        const int64_t k = *L.counter;
+        if (!measure_due(L, k)) continue;
+        const int cur = (int)(k & 1);
+        const Fields<R> f{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[0], (R*)L.mom[1], (R*)L.pp[cur][2],
+                          (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[2], (R*)L.mom[3], (R*)L.mom[4]};
+        const double* row = L.coef + k * kCoefStride;
+        gauss_block<R>(f, L.N, 1.0 / L.dx, row[C_GAUSS], it.tile, L.gauss_blocks,
+                       L.partials + (int64_t)(L.meas_blocks + it.tile) * kMeasStride, red);
+    }
+}
+
+// Fold the records of every due lattice into its measurement series (one
+// block per lattice, the same fixed order as the single-lattice fold).
+__global__ void __launch_bounds__(256) k_fold_batch(const PoolLattice* __restrict__ lat, int nlat)
+{
+    __shared__ double red[256];
+    const PoolLattice& L = lat[blockIdx.x];
+    const int64_t k = L.counter[0];
+    if (!measure_due(L, k)) return;
+    const int64_t slot = L.counter[1];
+    if (slot >= L.series_cap) return;
+    double* out = L.series + slot * kSeriesStride;
+    fold_records(L.partials, L.meas_blocks + L.gauss_blocks, out, red);
+    if (threadIdx.x == 0) {
+        out[M_COUNT] = (double)k;
+        L.counter[1] = slot + 1;
+    }
+}
+
+// Advance the step counter of every pool lattice that is not finished.
+__global__ void k_advance_batch(const PoolLattice* __restrict__ lat, int nlat)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nlat) return;
+    const int64_t k = lat[i].counter[0];
+    if (k <= lat[i].nsteps) lat[i].counter[0] = k + 1;
 }
 
 }  // namespace
 
 template <typename R>
 hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2, const LatticeConst& L,
-                            const StepCoef& c, const TileConfig& tc, hipStream_t s)
+                            const StepCoef& c, const TileConfig& tc, const MeasConst* mc, double* partials,
+                            bool write, hipStream_t s)
 {
     const int N = L.N;
     StepArgs<R> a;
@@ -427,14 +818,24 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
     a.lamh = (R)c.lam_half;
     a.kappa = (R)c.kappa;
     a.deta = (R)L.deta;
-#define AH_TILE_CASE(TXv, TYv)                                                                                   \
-    if (tc.tx == TXv && tc.ty == TYv) {                                                                          \
-        const int tiles_x = (N + TXv - 1) / TXv, tiles_y = (N + TYv - 1) / TYv;                                 \
-        const int zc = tc.zchunk > 0 ? tc.zchunk : N;                                                           \
-        const int tiles_z = (N + zc - 1) / zc;                                                                  \
-        const int nb = tiles_x * tiles_y * tiles_z;                                                             \
-        hipLaunchKernelGGL((k_step_tile<R, TXv, TYv>), dim3(nb), dim3(TXv * TYv), 0, s, a, zc, tiles_x, tiles_y);  \
-        return hipGetLastError();                                                                               \
+    MeasArgs ma{L.dx, 0.0, 0.0, 0.0};
+    if (mc) {
+        ma.inv_2e2f = mc->inv_2e2f;
+        ma.lam_quarter = mc->lam_quarter;
+        ma.gauss_c = mc->gauss_c;
+    }
+    const int zc = tc.zchunk > 0 ? tc.zchunk : N;
+#define AH_TILE_CASE(TXv, TYv)                                                                                     \
+    if (tc.tx == TXv && tc.ty == TYv) {                                                                            \
+        const int tiles_x = (N + TXv - 1) / TXv, tiles_y = (N + TYv - 1) / TYv;                                   \
+        const int nb = tiles_x * tiles_y * ((N + zc - 1) / zc);                                                   \
+        if (mc)                                                                                                    \
+            hipLaunchKernelGGL((k_step_tile<R, TXv, TYv, true>), dim3(nb), dim3(TXv * TYv), 0, s, a, ma, partials, \
+                               write ? 1 : 0, zc, tiles_x, tiles_y);                                              \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_step_tile<R, TXv, TYv, false>), dim3(nb), dim3(TXv * TYv), 0, s, a, ma, partials, \
+                               1, zc, tiles_x, tiles_y);                                                          \
+        return hipGetLastError();                                                                                 \
     }
     AH_TILE_CASE(64, 8)
     AH_TILE_CASE(64, 4)
@@ -446,14 +847,23 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
     return hipErrorInvalidValue;
 }
 
+int step_tile_blocks(int N, const TileConfig& tc)
+{
+    const int zc = tc.zchunk > 0 ? tc.zchunk : N;
+    return ((N + tc.tx - 1) / tc.tx) * ((N + tc.ty - 1) / tc.ty) * ((N + zc - 1) / zc);
+}
+
 template <typename R>
 hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,
-                             hipStream_t s)
+                             bool measured, hipStream_t s)
 {
-#define AH_BATCH_CASE(TXv, TYv)                                                                               \
-    if (tx == TXv && ty == TYv) {                                                                             \
-        hipLaunchKernelGGL((k_step_batch<R, TXv, TYv>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work, nwork); \
-        return hipGetLastError();                                                                            \
+#define AH_BATCH_CASE(TXv, TYv)                                                                                      \
+    if (tx == TXv && ty == TYv) {                                                                                    \
+        if (measured)                                                                                                \
+            hipLaunchKernelGGL((k_step_batch<R, TXv, TYv, true>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work, nwork); \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_step_batch<R, TXv, TYv, false>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work, nwork); \
+        return hipGetLastError();                                                                                   \
     }
     AH_BATCH_CASE(64, 8)
     AH_BATCH_CASE(64, 4)
@@ -465,12 +875,54 @@ hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int n
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_step_batch<double>(const PoolLattice*, const WorkItem*, int, int, int, int, hipStream_t);
-template hipError_t launch_step_batch<float>(const PoolLattice*, const WorkItem*, int, int, int, int, hipStream_t);
+int gauss_blocks(int N)
+{
+    const int64_t V = (int64_t)N * N * N;
+    int64_t nb = (V + 2047) / 2048;
+    if (nb > 1024) nb = 1024;
+    return (int)(nb < 1 ? 1 : nb);
+}
+
+template <typename R>
+hipError_t launch_gauss(const Fields<R>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gauss<R>, dim3(gauss_blocks(L.N)), dim3(256), 0, s, f, L.N, 1.0 / L.dx, gc, partials);
+    return hipGetLastError();
+}
+template hipError_t launch_gauss<double>(const Fields<double>&, const LatticeConst&, double, double*, hipStream_t);
+template hipError_t launch_gauss<float>(const Fields<float>&, const LatticeConst&, double, double*, hipStream_t);
+
+template <typename R>
+hipError_t launch_gauss_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gauss_batch<R>, dim3(grid), dim3(256), 0, s, lat, work, nwork);
+    return hipGetLastError();
+}
+template hipError_t launch_gauss_batch<double>(const PoolLattice*, const WorkItem*, int, int, hipStream_t);
+template hipError_t launch_gauss_batch<float>(const PoolLattice*, const WorkItem*, int, int, hipStream_t);
+
+hipError_t launch_fold_batch(const PoolLattice* lat, int nlat, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold_batch, dim3(nlat), dim3(256), 0, s, lat, nlat);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_batch(const PoolLattice* lat, int nlat, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance_batch, dim3((nlat + 63) / 64), dim3(64), 0, s, lat, nlat);
+    return hipGetLastError();
+}
+
+template hipError_t launch_step_batch<double>(const PoolLattice*, const WorkItem*, int, int, int, int, bool,
+                                              hipStream_t);
+template hipError_t launch_step_batch<float>(const PoolLattice*, const WorkItem*, int, int, int, int, bool,
+                                             hipStream_t);
 
 template hipError_t launch_step_tile<double>(const Fields<double>&, double*, double*, double*, double*, double*,
-                                             const LatticeConst&, const StepCoef&, const TileConfig&, hipStream_t);
+                                             const LatticeConst&, const StepCoef&, const TileConfig&, const MeasConst*,
+                                             double*, bool, hipStream_t);
 template hipError_t launch_step_tile<float>(const Fields<float>&, float*, float*, float*, float*, float*,
-                                            const LatticeConst&, const StepCoef&, const TileConfig&, hipStream_t);
+                                            const LatticeConst&, const StepCoef&, const TileConfig&, const MeasConst*,
+                                            double*, bool, hipStream_t);
 
 }  // namespace ah

@@ -37,11 +37,11 @@ def same_record(a, b):
     return True
 
 
-def _alone(ah, gp, seed, nsteps, every, tile):
+def _alone(ah, gp, seed, nsteps, every, tile, zchunk):
     """Run one lattice alone: fields after nsteps and the diagnostics series."""
     series = []
     with ah.Lattice(gp) as lat:
-        lat.set_step_config("tile", tile, 0)
+        lat.set_step_config("tile", tile, zchunk)
         lat.init(seed)
         for k in range(nsteps + 1):
             if k == nsteps or (every > 0 and k % every == 0):
@@ -74,8 +74,10 @@ def test_pool_alone_vs_mix_bitwise(ah):
                 series[rid] = pool.results(rid)
         assert sorted(finished) == sorted(ids)
         assert pool.stats()["active"] == 0 and pool.stats()["bytes_in_use"] == 0
+    # the pool runs whole-column z-chunks (>= 64 planes); alone with the same
+    # tiling the diagnostics records are summed in the same order
     for (p, seed, n, every), rid in zip(reqs, ids):
-        st, ser = _alone(ah, p, seed, n, every, (64, 8))
+        st, ser = _alone(ah, p, seed, n, every, (64, 8), min(p.N, 64))
         assert np.array_equal(states[rid], st), (p, seed)
         assert len(series[rid]) == len(ser)
         for a, b in zip(series[rid], ser):
