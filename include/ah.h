@@ -177,7 +177,7 @@ int ah_get_winding(ah_handle* h, int8_t* host_w);
  * z-chunk; the site kernel agrees with it to rounding. */
 typedef struct ah_step_config {
     int32_t kernel;         /* AH_KERNEL_* */
-    int32_t tile_x, tile_y; /* tiled kernel: (64,8), (64,4), (32,8) (FP32 also (64,16)); 0,0 = default */
+    int32_t tile_x, tile_y; /* tiled kernel: (64,8), (64,4), (32,8), (128,4) (FP32 also (64,16), (128,8)); 0,0 = default */
     int32_t zchunk;         /* x2-planes per workgroup of the tiled kernel; 0 = automatic, else >= min(8, N) */
 } ah_step_config;
 

@@ -324,7 +324,7 @@ static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why
         int rc = resolve_step_config(p, ah_step_config{AH_KERNEL_TILE, 0, 0, 0}, cfg, why);
         if (rc != AH_OK) return rc;
     }
-    if (cfg->tile_y == 16) cfg->tile_y = 8;  // 512-thread tiles: the measured node does not spill
+    if (cfg->tile_x * cfg->tile_y == 1024) cfg->tile_y /= 2;  // 512-thread tiles: the measured node does not spill
     int zc = cfg->zchunk < 64 ? 64 : cfg->zchunk;
     if (zc > p.N) zc = p.N;
     cfg->zchunk = zc;

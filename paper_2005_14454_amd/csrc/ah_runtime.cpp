@@ -179,7 +179,7 @@ size_t partial_records(const ah_params& p)
     const int zc = min_zchunk(N);
     const int64_t tz = (N + zc - 1) / zc;
     int64_t best = 0;
-    const int shapes[4][2] = {{64, 8}, {64, 4}, {32, 8}, {64, 16}};
+    const int shapes[6][2] = {{64, 8}, {64, 4}, {32, 8}, {64, 16}, {128, 4}, {128, 8}};
     for (auto& s : shapes) {
         const int64_t t = (int64_t)((N + s[0] - 1) / s[0]) * ((N + s[1] - 1) / s[1]) * tz;
         if (t > best) best = t;
@@ -257,7 +257,8 @@ bool tile_supported(int precision, int tx, int ty)
 {
     if (tx == 64 && (ty == 8 || ty == 4)) return true;
     if (tx == 32 && ty == 8) return true;
-    if (tx == 64 && ty == 16) return precision == AH_FP32;
+    if (tx == 128 && ty == 4) return true;
+    if ((tx == 64 && ty == 16) || (tx == 128 && ty == 8)) return precision == AH_FP32;
     return false;
 }
 
@@ -383,9 +384,10 @@ MeasConst meas_const(const ah_params& p, int64_t n)
 // the step's own when the step is tiled, the default tile otherwise.
 TileConfig meas_tiles(const ah_handle* h)
 {
-    // the 1024-thread tile spills registers when it also forms diagnostics;
-    // its 512-thread half computes the same fields bit for bit
-    if (h->cfg.kernel == AH_KERNEL_TILE && h->cfg.tile_y == 16) return TileConfig{64, 8, h->cfg.zchunk};
+    // 1024-thread tiles spill registers when they also form diagnostics;
+    // their 512-thread halves compute the same fields bit for bit
+    if (h->cfg.kernel == AH_KERNEL_TILE && h->cfg.tile_x * h->cfg.tile_y == 1024)
+        return TileConfig{h->cfg.tile_x, h->cfg.tile_y / 2, h->cfg.zchunk};
     if (h->cfg.kernel == AH_KERNEL_TILE) return TileConfig{h->cfg.tile_x, h->cfg.tile_y, h->cfg.zchunk};
     ah_step_config d;
     std::string why;

@@ -33,6 +33,21 @@ namespace {
 __device__ inline float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Streaming accesses: Pi and E are read and written once per step at their
+// own site, phi and A are written once into the other ping-pong buffer; none
+// of it is reused from cache within a step, so they bypass it and leave L2 to
+// the phi / A halo lines that neighbouring tiles read again.
+template <typename R>
+__device__ inline R ld_stream(const R* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+template <typename R>
+__device__ inline void st_stream(R* p, R v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 template <typename R>
 struct Cx {
     R r, i;
@@ -331,8 +346,9 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
         __syncthreads();
     }
 
-    R pr_c = f.pir[(int64_t)z0 * NN + own_xy], pi_c = f.pii[(int64_t)z0 * NN + own_xy];
-    R e_c[3] = {f.e0[(int64_t)z0 * NN + own_xy], f.e1[(int64_t)z0 * NN + own_xy], f.e2[(int64_t)z0 * NN + own_xy]};
+    const int64_t pz0 = (int64_t)z0 * NN + own_xy;
+    R pr_c = ld_stream(f.pir + pz0), pi_c = ld_stream(f.pii + pz0);
+    R e_c[3] = {ld_stream(f.e0 + pz0), ld_stream(f.e1 + pz0), ld_stream(f.e2 + pz0)};
 
     int cur = 0;
     for (int z = z0; z < z1; ++z) {
@@ -356,11 +372,11 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
                 hphi = {f.phr[p1 + halo_xy], f.phi[p1 + halo_xy]};
             }
             phi_pp = {f.phr[p2 + own_xy], f.phi[p2 + own_xy]};
-            n_pr = f.pir[pn + own_xy];
-            n_pi = f.pii[pn + own_xy];
-            n_e[0] = f.e0[pn + own_xy];
-            n_e[1] = f.e1[pn + own_xy];
-            n_e[2] = f.e2[pn + own_xy];
+            n_pr = ld_stream(f.pir + pn + own_xy);
+            n_pi = ld_stream(f.pii + pn + own_xy);
+            n_e[0] = ld_stream(f.e0 + pn + own_xy);
+            n_e[1] = ld_stream(f.e1 + pn + own_xy);
+            n_e[2] = ld_stream(f.e2 + pn + own_xy);
         } else if constexpr (MEAS) {
             if (has_halo) {
                 const int64_t p1 = plane_of(z + 1);
@@ -470,16 +486,16 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
             const R ne2 = fm(cE1, e_c[2], cE2 * fm(kappa, jz, -cz));
             if (write && active) {
                 const int64_t o = (int64_t)z * NN + own_xy;
-                f.pir[o] = npr;
-                f.pii[o] = npi;
-                f.e0[o] = ne0;
-                f.e1[o] = ne1;
-                f.e2[o] = ne2;
-                ophr[o] = fm(deta, npr, phi_c.r);
-                ophi[o] = fm(deta, npi, phi_c.i);
-                oa0[o] = fm(deta, ne0, Ac[0]);
-                oa1[o] = fm(deta, ne1, Ac[1]);
-                oa2[o] = fm(deta, ne2, Ac[2]);
+                st_stream(f.pir + o, npr);
+                st_stream(f.pii + o, npi);
+                st_stream(f.e0 + o, ne0);
+                st_stream(f.e1 + o, ne1);
+                st_stream(f.e2 + o, ne2);
+                st_stream(ophr + o, fm(deta, npr, phi_c.r));
+                st_stream(ophi + o, fm(deta, npi, phi_c.i));
+                st_stream(oa0 + o, fm(deta, ne0, Ac[0]));
+                st_stream(oa1 + o, fm(deta, ne1, Ac[1]));
+                st_stream(oa2 + o, fm(deta, ne2, Ac[2]));
             }
             if constexpr (MEAS) {
                 if (active) {
@@ -840,8 +856,10 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
     AH_TILE_CASE(64, 8)
     AH_TILE_CASE(64, 4)
     AH_TILE_CASE(32, 8)
+    AH_TILE_CASE(128, 4)
     if constexpr (sizeof(R) == 4) {
         AH_TILE_CASE(64, 16)
+        AH_TILE_CASE(128, 8)
     }
 #undef AH_TILE_CASE
     return hipErrorInvalidValue;
@@ -868,9 +886,7 @@ hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int n
     AH_BATCH_CASE(64, 8)
     AH_BATCH_CASE(64, 4)
     AH_BATCH_CASE(32, 8)
-    if constexpr (sizeof(R) == 4) {
-        AH_BATCH_CASE(64, 16)
-    }
+    AH_BATCH_CASE(128, 4)
 #undef AH_BATCH_CASE
     return hipErrorInvalidValue;
 }

@@ -46,8 +46,11 @@ int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double*
     int rc = ah_create(p, nullptr, 0, nullptr, &h);
     if (rc != AH_OK) return rc;
     rc = ah_init(h, 0);
-    std::vector<std::pair<int, int>> tiles = {{64, 8}, {64, 4}, {32, 8}};
-    if (p->precision == AH_FP32) tiles.push_back({64, 16});
+    std::vector<std::pair<int, int>> tiles = {{64, 8}, {64, 4}, {32, 8}, {128, 4}};
+    if (p->precision == AH_FP32) {
+        tiles.push_back({64, 16});
+        tiles.push_back({128, 8});
+    }
     std::vector<int> zcs = {0, p->N};
     for (int div : {2, 4, 8})
         if (p->N / div >= 8) zcs.push_back(p->N / div);

@@ -25,8 +25,9 @@ def ah():
     return ah
 
 
-KERNELS = [("site", (0, 0), 0), ("tile", (64, 8), 0), ("tile", (64, 4), 8), ("tile", (32, 8), 9)]
-KERNEL_IDS = ["site", "tile64x8", "tile64x4z8", "tile32x8z9"]
+KERNELS = [("site", (0, 0), 0), ("tile", (64, 8), 0), ("tile", (64, 4), 8), ("tile", (32, 8), 9),
+           ("tile", (128, 4), 16)]
+KERNEL_IDS = ["site", "tile64x8", "tile64x4z8", "tile32x8z9", "tile128x4z16"]
 
 
 def _run_gpu(ah, gp, state, step0, nsteps, kernel=None):
@@ -77,7 +78,8 @@ def test_one_step_gauge_actions(oracle_mod, ah, gauge):
     assert max_field_error(got, ref) <= 1e-13
 
 
-@pytest.mark.parametrize("kernel", KERNELS + [("tile", (64, 16), 0)], ids=KERNEL_IDS + ["tile64x16"])
+@pytest.mark.parametrize("kernel", KERNELS + [("tile", (64, 16), 0), ("tile", (128, 8), 0)],
+                         ids=KERNEL_IDS + ["tile64x16", "tile128x8"])
 @pytest.mark.parametrize("N", [24, 70])
 def test_one_step_fp32(oracle_mod, ah, N, kernel):
     op, gp = both_params(oracle_mod, N, "fp32")
@@ -230,9 +232,9 @@ def test_tile_shapes_bitwise_identical(ah, precision):
     N = 40
     gp = Params(N=N, precision=precision, m=2.0)
     st = random_state(N, seed=9)
-    shapes = [((64, 8), 0), ((64, 4), 8), ((32, 8), 9), ((64, 8), 40), ((32, 8), 13)]
+    shapes = [((64, 8), 0), ((64, 4), 8), ((32, 8), 9), ((64, 8), 40), ((32, 8), 13), ((128, 4), 8)]
     if precision == "fp32":
-        shapes.append(((64, 16), 11))
+        shapes += [((64, 16), 11), ((128, 8), 10)]
     outs = [_run_gpu(ah, gp, st, 0, 12, ("tile", t, z)) for t, z in shapes]
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
