@@ -28,7 +28,7 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_512cubed_hbm_traff
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2005_14454_amd", "csrc", "ah_step_tile.hip")
 
 
-def measured_traffic(precision, N):
+def measured_traffic(precision, N, tile):
     """HBM bytes per plain-step launch at 512^3 from the committed rocprofv3
     PMC summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None
     when the kernel source has changed since the counters were taken."""
@@ -39,7 +39,8 @@ def measured_traffic(precision, N):
     cur = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
     if f"sha256[:16] = {cur}" not in text:
         return None
-    name = "k_step_tile<float, 64, 8, false>" if precision == "fp32" else "k_step_tile<double, 64, 8, false>"
+    real = "float" if precision == "fp32" else "double"
+    name = f"k_step_tile<{real}, {tile[0]}, {tile[1]}, false>"
     for line in text.splitlines():
         if line.startswith(name):
             total_gb = float(line[len(name):].split()[4])
@@ -53,7 +54,9 @@ def run_gpu(precision, N, steps, warmup, measure_every, seed):
     import paper_2005_14454_amd as ah
 
     p = ah.Params(N=N, precision=precision, m=1.0)
+    tuned = ah.autotune(p, steps=5)  # tile shape and z-chunk for this (precision, N)
     lat = ah.Lattice(p)
+    cfg = lat.get_step_config()
     lat.init(seed)
     lat.step(warmup)
     lat.measure()
@@ -79,11 +82,12 @@ def run_gpu(precision, N, steps, warmup, measure_every, seed):
     achieved = BYTES_PER_SITE[precision] * V / avg_kernel_s / 1e9
     return {
         "value": V * steps / sec,
+        "tuned": tuned,
         "ms_per_step": 1e3 * sec / steps,
         "kernel_ms": 1e3 * avg_kernel_s,
         "measured_step_ms": 1e3 * avg_measured_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(precision, N),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(precision, N, cfg["tile"]),
                      "traffic_unit": "bytes per launch", "algorithmic_bytes": BYTES_PER_SITE[precision] * V},
         "last_measurement": {k: last[k] for k in ("step", "winding_sum_abs", "xi_W", "xi_L", "v2_phi",
                                                   "energy", "gauss_rel", "nonfinite")},
@@ -106,7 +110,9 @@ def batched_ensemble(nlat=64, measure_every=20, chunk=16):
     """64 independent FP32 lattices, N uniform on {64, 96, 128, 192, 256}, m on
     {1, 2} (PCG64 seed 4), seeds 100..163, s = 0, each to eta = dx N / 2, in one
     pool: one graph replay per step advances every unfinished lattice; tile
-    shape and z-chunk autotuned per size class."""
+    shape and z-chunk autotuned per size class.  Reported beside the same 64
+    lattices run one after another through the single-lattice path (each with
+    its own launches, same diagnostics cadence)."""
     import numpy as np
     import torch
     import paper_2005_14454_amd as ah
@@ -138,12 +144,22 @@ def batched_ensemble(nlat=64, measure_every=20, chunk=16):
                 left.discard(rid)
         t1 = time.perf_counter()
         finals = [pool.results(rid)[-1] for rid in ids]
-    # the same lattices one after another through the single-lattice step
+    # the same lattices one after another through the single-lattice path,
+    # with the same diagnostics cadence (fused into the step) and final record
     rate = {N: single_rate(N) for N in sorted(set(Ns))}
-    sequential_s = sum(p.N ** 3 * n / rate[p.N] for p, _, n in reqs)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    for p, seed, n in reqs:
+        with ah.Lattice(p) as lat:
+            lat.init(seed)
+            lat.step_measured(n, measure_every)
+            lat.measure()
+    torch.cuda.synchronize()
+    sequential_s = time.perf_counter() - s0
     sec = t1 - t0
     return {"lattices": nlat, "site_updates": su, "wall_s": sec, "value": su / sec, "unit": "site-updates/s",
-            "graph_replays": steps, "sequential_kernel_s": sequential_s, "speedup_vs_sequential": sequential_s / sec,
+            "graph_replays": steps, "sequential_wall_s": sequential_s, "sequential_value": su / sequential_s,
+            "speedup_vs_sequential": sequential_s / sec,
             "tuned": {str(k): v for k, v in tuned.items()},
             "single_lattice_su_per_s": {str(k): v for k, v in rate.items()},
             "nonfinite": sum(m["nonfinite"] for m in finals)}
@@ -264,7 +280,8 @@ def main():
         "batched": batched,
         "served": serv,
         "fp64": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
-                                           "roofline": fp64["roofline"], "dtype": "f64"},
+                                           "roofline": fp64["roofline"], "dtype": "f64", "tuned": fp64["tuned"]},
+        "tuned": fp32["tuned"],
         "kernel_ms": {"fp32": fp32["kernel_ms"], "fp64": None if fp64 is None else fp64["kernel_ms"]},
         "measured_step_ms": {"fp32": fp32["measured_step_ms"],
                              "fp64": None if fp64 is None else fp64["measured_step_ms"]},

@@ -107,6 +107,13 @@ typedef struct ah_measurement {
 
 typedef struct ah_handle ah_handle;
 
+/* Leapfrog stability margin of snapshot `step` (host arithmetic only, no
+ * device work): mu = deta * sqrt(max(lambda0, 2 e0^2) f sigma^2 + 12/dx^2),
+ * the largest angular frequency of the linearised update times deta.  The
+ * explicit scheme is stable for mu < 2; ah_measure sets AH_FLAG_UNSTABLE when
+ * mu >= 2.  AH_E_INVAL on bad parameters or step < 0. */
+int ah_stability_margin(const ah_params* p, int64_t step, double* mu);
+
 /* Device bytes one lattice needs: 15 field arrays (10 state + phi/A ping-pong)
  * of N^3 reals each, plus reduction scratch.  AH_E_INVAL on bad params. */
 int ah_required_bytes(const ah_params* p, size_t* bytes);
@@ -133,6 +140,13 @@ int ah_set_state(ah_handle* h, const double* host_soa, int64_t step);
 /* Download the current snapshot as FP64 SoA (10*N^3 doubles) and its step
  * index (step may be NULL).  Synchronous. */
 int ah_get_state(ah_handle* h, double* host_soa, int64_t* step);
+
+/* Values of the current snapshot at `count` listed site indices (each in
+ * [0, N^3), else AH_E_INVAL before any device work): host_out[10*k + c] is
+ * component c (state order) of site sites[k], widened to FP64.  For
+ * spot-checking lattices too large to download.  Allocates two temporary
+ * device buffers (count*8 and count*10*sizeof(real) bytes).  Synchronous. */
+int ah_gather(ah_handle* h, const int64_t* sites, int64_t count, double* host_out);
 
 /* Current snapshot index (host-side counter; no synchronisation). */
 int ah_get_step(const ah_handle* h, int64_t* step);

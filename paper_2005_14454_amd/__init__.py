@@ -15,7 +15,7 @@ from ._lib import AHError, AH_FP32, AH_FP64, AH_COMPACT, AH_NONCOMPACT, AH_FLAG_
 
 __all__ = ["Params", "Lattice", "Pool", "AHError", "AH_FP32", "AH_FP64", "AH_COMPACT", "AH_NONCOMPACT",
            "AH_FLAG_NONFINITE", "AH_FLAG_UNSTABLE", "required_bytes", "autotune", "tune_lookup", "tune_set",
-           "tune_clear", "tune_save", "tune_load", "pool_footprint"]
+           "tune_clear", "tune_save", "tune_load", "pool_footprint", "stability_margin"]
 
 
 @dataclass
@@ -62,6 +62,14 @@ def required_bytes(p: Params) -> int:
     n = ctypes.c_size_t()
     _lib.check(lib.ah_required_bytes(ctypes.byref(p.to_c()), ctypes.byref(n)), what="ah_required_bytes")
     return n.value
+
+
+def stability_margin(p: Params, step: int) -> float:
+    """deta * sqrt(max(lambda0, 2 e0^2) f sigma^2 + 12/dx^2) of snapshot `step`; stable below 2."""
+    mu = ctypes.c_double()
+    _lib.check(_lib.load().ah_stability_margin(ctypes.byref(p.to_c()), step, ctypes.byref(mu)),
+               what="ah_stability_margin")
+    return mu.value
 
 
 def _meas_dict(m: _lib.ah_measurement) -> dict:
@@ -174,6 +182,14 @@ class Lattice:
         self._call(self._lib.ah_get_state, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(s),
                    what="ah_get_state")
         return st
+
+    def gather(self, sites) -> np.ndarray:
+        """(len(sites), 10) FP64 values of the current snapshot at the listed site indices."""
+        s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+        out = np.empty((len(s), 10), dtype=np.float64)
+        self._call(self._lib.ah_gather, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(s),
+                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), what="ah_gather")
+        return out
 
     def winding(self) -> np.ndarray:
         w = np.empty((3, self.V), dtype=np.int8)

@@ -83,11 +83,13 @@ def load():
     sig = {
         "ah_params_default": ([P(ah_params)], ctypes.c_int),
         "ah_required_bytes": ([P(ah_params), P(ctypes.c_size_t)], ctypes.c_int),
+        "ah_stability_margin": ([P(ah_params), i64, P(ctypes.c_double)], ctypes.c_int),
         "ah_create": ([P(ah_params), vp, ctypes.c_size_t, vp, P(vp)], ctypes.c_int),
         "ah_init": ([vp, ctypes.c_uint64], ctypes.c_int),
         "ah_set_state": ([vp, P(ctypes.c_double), i64], ctypes.c_int),
         "ah_get_state": ([vp, P(ctypes.c_double), P(i64)], ctypes.c_int),
         "ah_get_step": ([vp, P(i64)], ctypes.c_int),
+        "ah_gather": ([vp, P(i64), i64, P(ctypes.c_double)], ctypes.c_int),
         "ah_step": ([vp, i64], ctypes.c_int),
         "ah_measure": ([vp, P(ah_measurement)], ctypes.c_int),
         "ah_step_measured": ([vp, i64, ctypes.c_int32, P(ah_measurement), ctypes.c_int32, P(ctypes.c_int32)],

@@ -141,6 +141,9 @@ hipError_t launch_fold_batch(const PoolLattice* lat, int nlat, hipStream_t s);
 hipError_t launch_advance_batch(const PoolLattice* lat, int nlat, hipStream_t s);
 
 template <typename R>
+hipError_t launch_gather(const Fields<R>& f, const int64_t* sites, int64_t count, int64_t V, R* out, hipStream_t s);
+
+template <typename R>
 hipError_t launch_winding(const Fields<R>& f, const LatticeConst& L, int8_t* w, hipStream_t s);
 
 }  // namespace ah

@@ -331,9 +331,34 @@ __global__ void __launch_bounds__(256) k_measure_final(const double* __restrict_
     fold_records(partials, nblocks, result, red);
 }
 
+// Values of the 10 state components at listed sites: out[10*k + c].
+template <typename R>
+__global__ void __launch_bounds__(256) k_gather(Fields<R> f, const int64_t* __restrict__ sites, int64_t count,
+                                                int64_t V, R* __restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int64_t s = sites[k];
+    if (s < 0 || s >= V) return;  // rejected on the host; never read out of bounds
+    const R* comps[10] = {f.phr, f.phi, f.pir, f.pii, f.a0, f.a1, f.a2, f.e0, f.e1, f.e2};
+    for (int c = 0; c < 10; ++c) out[10 * k + c] = comps[c][s];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+
+template <typename R>
+hipError_t launch_gather(const Fields<R>& f, const int64_t* sites, int64_t count, int64_t V, R* out, hipStream_t s)
+{
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(k_gather<R>, dim3((unsigned)blocks), dim3(256), 0, s, f, sites, count, V, out);
+    return hipGetLastError();
+}
+template hipError_t launch_gather<double>(const Fields<double>&, const int64_t*, int64_t, int64_t, double*,
+                                          hipStream_t);
+template hipError_t launch_gather<float>(const Fields<float>&, const int64_t*, int64_t, int64_t, float*,
+                                         hipStream_t);
 
 template <typename R>
 hipError_t launch_init(const Fields<R>& f, int N, double sigma, uint64_t seed, hipStream_t s)

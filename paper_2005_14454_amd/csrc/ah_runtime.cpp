@@ -106,12 +106,14 @@ double gauss_coupling(const ah_params& p, int64_t n)
     return 2.0 * p.e0 * p.e0 * s.f * (1.0 + s.delta) / (1.0 + s.omega);
 }
 
-bool unstable_at(const ah_params& p, int64_t n)
+double stability_margin(const ah_params& p, int64_t n)
 {
     const Scalars s = scalars_at(p, n);
     const double g = std::fmax(p.lambda0, 2.0 * p.e0 * p.e0) * s.f * p.sigma * p.sigma + 12.0 / (p.dx * p.dx);
-    return p.deta * std::sqrt(g) >= 2.0;
+    return p.deta * std::sqrt(g);
 }
+
+bool unstable_at(const ah_params& p, int64_t n) { return stability_margin(p, n) >= 2.0; }
 
 }  // namespace
 
@@ -284,7 +286,9 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
         return AH_E_INVAL;
     }
     if (c.tile_x == 0 && c.tile_y == 0) {
-        c.tile_x = 64;
+        // FP32: 128-wide rows halve the x-halo line fetches per site; FP64
+        // keeps 64-wide rows (its 1024-thread tiles would spill)
+        c.tile_x = (p.precision == AH_FP32 && p.N >= 128) ? 128 : 64;
         c.tile_y = 8;
     }
     if (!tile_supported(p.precision, c.tile_x, c.tile_y)) {
@@ -296,9 +300,12 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
         return AH_E_INVAL;
     }
     if (c.zchunk == 0) {
-        // enough workgroups to fill 256 CUs a few times over
+        // enough workgroups to cover the chip: about 1024 of 512 threads, or
+        // one resident round (256) of 1024-thread workgroups, whose z-chunks
+        // are then as long as possible
         const int64_t per_chunk = (int64_t)((p.N + c.tile_x - 1) / c.tile_x) * ((p.N + c.tile_y - 1) / c.tile_y);
-        int64_t zc = (int64_t)p.N * per_chunk / 1024;
+        const int64_t target = c.tile_x * c.tile_y >= 1024 ? 256 : 1024;
+        int64_t zc = (int64_t)p.N * per_chunk / target;
         if (zc < 8) zc = 8;
         if (zc > p.N) zc = p.N;
         c.zchunk = (int32_t)zc;
@@ -506,6 +513,14 @@ int ah_params_default(ah_params* p)
     return AH_OK;
 }
 
+int ah_stability_margin(const ah_params* p, int64_t step, double* mu)
+{
+    std::string why;
+    if (validate(p, &why) != AH_OK || step < 0 || !mu) return AH_E_INVAL;
+    *mu = stability_margin(*p, step);
+    return AH_OK;
+}
+
 int ah_required_bytes(const ah_params* p, size_t* bytes)
 {
     std::string why;
@@ -677,6 +692,43 @@ int ah_get_state(ah_handle* h, double* host_soa, int64_t* step)
             for (size_t i = 0; i < V; ++i) dst[i] = (double)tmp[i];
     }
     if (step) *step = h->step;
+    return AH_OK;
+}
+
+int ah_gather(ah_handle* h, const int64_t* sites, int64_t count, double* host_out)
+{
+    if (!h || count < 0 || (count > 0 && (!sites || !host_out))) return fail(h, AH_E_INVAL, "ah_gather: bad argument");
+    if (!h->ready) return fail(h, AH_E_STATE, "ah_gather before ah_init/ah_set_state");
+    for (int64_t k = 0; k < count; ++k)
+        if (sites[k] < 0 || sites[k] >= h->V) return fail(h, AH_E_INVAL, "ah_gather: site index out of range");
+    if (count == 0) return AH_OK;
+    DeviceGuard g(h->device);
+    void* d_sites = nullptr;
+    void* d_out = nullptr;
+    const size_t rb = h->real_bytes;
+    hipError_t e = hipMalloc(&d_sites, count * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&d_out, count * 10 * rb);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (d_sites) (void)hipFree(d_sites);
+        return fail(h, AH_E_NOMEM, "ah_gather: cannot allocate the temporary buffers");
+    }
+    std::vector<float> tmp(rb == 4 ? count * 10 : 0);
+    e = hipMemcpyAsync(d_sites, sites, count * sizeof(int64_t), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = rb == 8 ? launch_gather<double>(fields_of<double>(h, h->cur), (const int64_t*)d_sites, count, h->V,
+                                            (double*)d_out, h->stream)
+                    : launch_gather<float>(fields_of<float>(h, h->cur), (const int64_t*)d_sites, count, h->V,
+                                           (float*)d_out, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(rb == 8 ? (void*)host_out : (void*)tmp.data(), d_out, count * 10 * rb,
+                           hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d_sites);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_fail(h, e, "ah_gather");
+    if (rb == 4)
+        for (int64_t q = 0; q < count * 10; ++q) host_out[q] = (double)tmp[q];
     return AH_OK;
 }
 

@@ -291,9 +291,12 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
     // Y_x, Y_y of the current plane, FP64 sums
     Cx<double> W64c[3] = {}, W64p[3] = {};
     float yx_c = 0.f, yy_c = 0.f;
-    double acc[M_COUNT];
+    // sums of the march: M_KIN .. M_GRADL (8 slots, FP64) and the exact
+    // counts M_WABS, M_NONFIN (integers); the Gauss slots belong to k_gauss
+    double acc[8];
+    int wabs = 0, nonfin = 0;
     if constexpr (MEAS)
-        for (int k = 0; k < M_COUNT; ++k) acc[k] = 0.0;
+        for (int k = 0; k < 8; ++k) acc[k] = 0.0;
     {
         const int64_t pm = plane_of(z0 - 1), p0 = plane_of(z0);
         const R* A[3] = {f.a0, f.a1, f.a2};
@@ -504,7 +507,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
                     const R v[10] = {phi_c.r, phi_c.i, pr_c, pi_c, Ac[0], Ac[1], Ac[2], e_c[0], e_c[1], e_c[2]};
                     bool bad = false;
                     for (int k = 0; k < 10; ++k) bad |= !isfinite(v[k]);
-                    acc[M_NONFIN] += bad ? 1.0 : 0.0;
+                    nonfin += bad ? 1 : 0;
                     const R pbr = R(0.5) * (pr_c + npr), pbi = R(0.5) * (pi_c + npi);
                     const double kin = (double)fm(pbr, pbr, pbi * pbi);
                     const R d0r = fx.r - phi_c.r, d0i = fx.i - phi_c.i;
@@ -540,7 +543,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
             if (active) {
                 const auto& sY = mx->Y[zs];
                 const double th = ma.dx * ((((double)Ac[0] + (double)ay_xp) - (double)ax_yp) - (double)Ac[1]);
-                acc[M_WABS] += (double)abs(winding_of(yx_c, sY[1][rxp], sY[0][ryp], yy_c, th));
+                wabs += abs(winding_of(yx_c, sY[1][rxp], sY[0][ryp], yy_c, th));
             }
         }
 
@@ -577,8 +580,8 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
                 const auto& sY = mx->Y[zs];
                 const double thxz = ma.dx * ((((double)Ac[0] + (double)az_xp) - (double)Ap[0]) - (double)Ac[2]);
                 const double thyz = ma.dx * ((((double)Ac[1] + (double)az_yp) - (double)Ap[1]) - (double)Ac[2]);
-                acc[M_WABS] += (double)(abs(winding_of(yx_c, sY[2][rxp], yx_n, yz_c, thxz)) +
-                                        abs(winding_of(yy_c, sY[2][ryp], yy_n, yz_c, thyz)));
+                wabs += abs(winding_of(yx_c, sY[2][rxp], yx_n, yz_c, thxz)) +
+                        abs(winding_of(yy_c, sY[2][ryp], yy_n, yz_c, thyz));
             }
             yx_c = yx_n;
             yy_c = yy_n;
@@ -605,16 +608,25 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
 
     if constexpr (MEAS) {
         // fixed-order block reduction of the diagnostics into one record
+        static_assert(M_KIN == 0 && M_GRADL == 7, "march sums occupy slots 0..7");
         auto& red = mx->red;
         const int lane = tid & 63, wv = tid >> 6;
-        for (int k = 0; k < M_COUNT; ++k) {
-            const double r = (k == M_GMAX) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        for (int k = 0; k < 8; ++k) {
+            const double r = wave_sum(acc[k]);
             if (lane == 0) red[wv][k] = r;
         }
+        const double rw = wave_sum((double)wabs), rn = wave_sum((double)nonfin);
+        if (lane == 0) {
+            red[wv][M_WABS] = rw;
+            red[wv][M_NONFIN] = rn;
+        }
         __syncthreads();
-        if (tid < M_COUNT) {
-            double r = red[0][tid];
-            for (int w = 1; w < NT / 64; ++w) r = (tid == M_GMAX) ? fmax(r, red[w][tid]) : r + red[w][tid];
+        if (tid < kMeasStride) {
+            double r = 0.0;
+            if (tid < 8 || tid == M_WABS || tid == M_NONFIN) {
+                r = red[0][tid];
+                for (int w = 1; w < NT / 64; ++w) r += red[w][tid];
+            }
             record[tid] = r;
         }
     }

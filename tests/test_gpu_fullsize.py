@@ -56,3 +56,47 @@ def test_fullsize_one_step_sampled(oracle_mod, precision, tol):
     assert meas["nonfinite"] == 0
     assert meas["gauss_rel"] < (1e-12 if precision == "fp64" else 1e-5)
     assert meas["winding_sum_abs"] > 0
+
+
+def cube(N, site):
+    """The 27 site indices of the 3x3x3 cube centred on `site`, in the index
+    order of a 3^3 lattice (a + 3 (b + 3 c) for offsets a, b, c in 0..2)."""
+    x0, x1, x2 = site % N, (site // N) % N, site // (N * N)
+    out = []
+    for c in range(3):
+        for b in range(3):
+            for a in range(3):
+                out.append((x0 + a - 1) % N + N * (((x1 + b - 1) % N) + N * ((x2 + c - 1) % N)))
+    return out
+
+
+def test_fullsize_1024_matter_era_switch_sampled(oracle_mod):
+    """1024^3 FP32, matter era (m = 2), s switching from 0 to 1 (moved to eta = 1.25
+    so that the switch is inside the checked steps), a(eta_end = 256) = 1, seed 2:
+    one GPU step after the switch against the oracle on sampled sites.  Each
+    site's update reads only its 3x3x3 neighbourhood, which is gathered from the
+    device and evaluated by the oracle as a 3^3 lattice (no wrap at its centre)."""
+    import paper_2005_14454_amd as ah
+    N = 1024
+    gp = ah.Params(N=N, precision="fp32", m=2.0, s_early=0.0, s_late=1.0, eta_switch=1.25)
+    op = oracle_mod.params(N=3, m=2.0, s_early=0.0, s_late=1.0, eta_switch=1.25, eta_ref=0.5 * 0.5 * N)
+    rng = np.random.default_rng(31)
+    centres = np.unique(np.concatenate([rng.integers(0, N ** 3, 300),
+                                        [0, N - 1, N * N - 1, N ** 3 - 1, 127 + N * 7, 128 + N * 8]]))
+    with ah.Lattice(gp) as lat:
+        lat.init(2)
+        lat.step(5)                          # eta = 1.5: s = 1, f = (1.5/256)^4
+        cubes = np.array([cube(N, int(s)) for s in centres])
+        before = lat.gather(cubes.reshape(-1)).reshape(len(centres), 27, 10)
+        lat.step(1)
+        after = lat.gather(centres)
+        meas = lat.measure()
+    ref = np.empty_like(after)
+    for k in range(len(centres)):
+        mini = np.ascontiguousarray(before[k].T)  # (10, 27)
+        ref[k] = oracle_mod.step_sites(op, mini, 5, [13])[0]
+    err = field_scaled_error(after.T, ref.T)
+    print("1024^3 FP32 sampled one-step error", err)
+    assert max(err.values()) <= 2e-6, err
+    assert meas["nonfinite"] == 0 and meas["step"] == 6
+    assert meas["winding_sum_abs"] > 0

@@ -1,0 +1,94 @@
+"""Host-side logic of the library that needs no GPU: parameter validation,
+footprints, the stability margin behind AH_FLAG_UNSTABLE (checked against a
+blow-up forced in the oracle), and the serving stream's request recipe."""
+import math
+
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def ah():
+    import os
+    import paper_2005_14454_amd as ah
+    from paper_2005_14454_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2005_14454_amd import build
+        build.build()
+    return ah
+
+
+def test_stability_margin_formula(ah):
+    p = ah.Params(N=32)
+    mu = ah.stability_margin(p, 0)
+    assert abs(mu - 0.1 * math.sqrt(2.0 + 12.0 / 0.25)) < 1e-15
+    # the paper's choices are stable; a large time step is not
+    assert mu < 2.0
+    assert ah.stability_margin(ah.Params(N=32, deta=0.29), 0) >= 2.0
+    with pytest.raises(ah.AHError):
+        ah.stability_margin(p, -1)
+
+
+def test_stability_margin_predicts_blow_up(ah, oracle_mod):
+    """Coupling f = a^(2s) grown past the margin makes the homogeneous mode of
+    the oracle blow up; just below it, it stays bounded."""
+    N = 4
+    for f_scale, should_blow in ((150.0, False), (200.0, True)):
+        # s = 1, slow expansion m = 0.01: f = (eta/eta_ref)^(2 m) equals f_scale at eta0
+        # and grows by 8% over the 400 steps (eta from 1 to 41); damping is negligible
+        m = 0.01
+        eta_ref = f_scale ** (-1.0 / (2 * m))
+        p = ah.Params(N=N, m=m, s_early=1.0, s_late=1.0, eta_ref=eta_ref)
+        mu = ah.stability_margin(p, 0)
+        assert (mu >= 2.0) == should_blow, (f_scale, mu)
+        op = oracle_mod.params(N=N, m=m, s_early=1.0, s_late=1.0, eta_ref=eta_ref)
+        st = np.zeros((10, N ** 3))
+        st[0] = 1.0 + 1e-3 * np.cos(2 * np.pi * np.arange(N ** 3) / N)
+        out = oracle_mod.step(op, st, 0, 400)
+        blew = not np.all(np.isfinite(out)) or np.max(np.abs(out)) > 1e3
+        assert blew == should_blow, (f_scale, mu, np.max(np.abs(out)))
+
+
+def test_parameter_validation(ah):
+    import ctypes
+    from paper_2005_14454_amd import _lib
+    lib = _lib.load()
+    n = ctypes.c_size_t()
+    good = ah.Params(N=16).to_c()
+    assert lib.ah_required_bytes(ctypes.byref(good), ctypes.byref(n)) == 0
+    for field, value in (("N", 3), ("precision", 7), ("gauge_action", 5), ("reserved", 1), ("dx", 0.0),
+                         ("deta", -0.1), ("eta0", 0.0), ("e0", 0.0), ("lambda0", float("nan"))):
+        bad = ah.Params(N=16).to_c()
+        setattr(bad, field, value)
+        assert lib.ah_required_bytes(ctypes.byref(bad), ctypes.byref(n)) == _lib.AH_E_INVAL, field
+
+
+def test_pool_footprint_accounts_for_everything(ah):
+    p32 = ah.Params(N=64, precision="fp32")
+    p64 = ah.Params(N=64, precision="fp64")
+    f32 = ah.pool_footprint(p32, 100, 10)
+    f64 = ah.pool_footprint(p64, 100, 10)
+    assert 15 * 4 * 64 ** 3 < f32 < 15 * 4 * 64 ** 3 * 1.2
+    assert 15 * 8 * 64 ** 3 < f64 < 15 * 8 * 64 ** 3 * 1.2
+    assert ah.pool_footprint(p32, 1000, 10) > f32  # coefficient table and series grow with steps
+    with pytest.raises(ah.AHError):
+        ah.pool_footprint(ah.Params(N=64, gauge_action="noncompact"), 10, 1)
+
+
+def test_request_stream_recipe(ah):
+    from paper_2005_14454_amd.serve import make_stream, steps_to_half_light_crossing
+    reqs = make_stream(200, rate=2.0, seed=5)
+    fp32 = [r for r in reqs if r.params.precision == "fp32"]
+    fp64 = [r for r in reqs if r.params.precision == "fp64"]
+    assert len(fp32) == 200 and len(fp64) == 20
+    Ns = np.array([r.params.N for r in fp32])
+    assert Ns.min() >= 64 and Ns.max() <= 512
+    # log-uniform: the median of N is near sqrt(64 * 512) = 181
+    assert 140 < np.median(Ns) < 230
+    assert {r.params.m for r in fp32} == {1.0, 2.0} and {r.params.s_early for r in fp32} == {0.0, 1.0}
+    arr = np.array([r.arrival for r in fp32])
+    assert np.all(np.diff(arr) > 0) and abs(np.mean(np.diff(arr)) - 0.5) < 0.1
+    for r in fp64:
+        twin = reqs[r.pair_of]
+        assert twin.params.precision == "fp32" and twin.seed == r.seed and twin.params.N == r.params.N
+    assert steps_to_half_light_crossing(256) == 630 and steps_to_half_light_crossing(512) == 1270
