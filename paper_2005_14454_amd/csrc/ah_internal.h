@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "ah.h"
+
 namespace ah {
 
 // Structure-of-arrays field pointers of one lattice snapshot.  phi and A come
@@ -74,6 +76,39 @@ struct MeasConst {
 struct TileConfig {
     int tx, ty, zchunk;
 };
+
+// Tile shapes the tiled kernels are built for (the 1024-thread ones for FP32 only).
+inline bool tile_supported(int precision, int tx, int ty)
+{
+    if (tx == 64 && (ty == 8 || ty == 4)) return true;
+    if (tx == 32 && ty == 8) return true;
+    if (tx == 128 && ty == 4) return true;
+    if ((tx == 64 && ty == 16) || (tx == 128 && ty == 8)) return precision == AH_FP32;
+    return false;
+}
+
+// Smallest z-chunk the tiled kernels accept for a lattice of side N.
+inline int min_zchunk(int N) { return N < 8 ? N : 8; }
+
+// Replace a tile shape whose measured march would spill registers by the
+// fastest one that does not (FP32: 1024-thread tiles -> 64 x 8; FP64:
+// 512-thread tiles -> 32 x 8).  Returns whether it changed.
+inline bool measured_tile(int precision, int* tx, int* ty)
+{
+    const int nt = *tx * *ty;
+    int mx = *tx, my = *ty;
+    if (precision == AH_FP32 && nt == 1024) {
+        mx = 64;
+        my = 8;
+    } else if (precision == AH_FP64 && nt == 512) {
+        mx = 32;
+        my = 8;
+    }
+    const bool changed = mx != *tx || my != *ty;
+    *tx = mx;
+    *ty = my;
+    return changed;
+}
 
 // ---- lattice pool (many independent lattices advanced by one launch) ------
 // Row layout of a lattice's per-step FP64 coefficient table.

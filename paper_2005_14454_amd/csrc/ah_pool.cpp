@@ -320,11 +320,15 @@ int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_po
 // parallelism that small z-chunks buy a lattice run alone).
 static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why)
 {
-    if (!tuned_config(p, cfg)) {
-        int rc = resolve_step_config(p, ah_step_config{AH_KERNEL_TILE, 0, 0, 0}, cfg, why);
-        if (rc != AH_OK) return rc;
-    }
-    if (cfg->tile_x * cfg->tile_y == 1024) cfg->tile_y /= 2;  // 512-thread tiles: the measured node does not spill
+    ah_step_config t{AH_KERNEL_TILE, 0, 0, 0};
+    (void)tuned_config(p, &t);
+    const int rc = resolve_step_config(p, t, cfg, why);
+    if (rc != AH_OK) return rc;
+    // one tile shape serves both nodes, so it must be one whose measured march
+    // keeps its registers: FP32 1024-thread tiles are halved in y, FP64
+    // 512-thread tiles become 32 x 8
+    if (p.precision == AH_FP32 && cfg->tile_x * cfg->tile_y == 1024) cfg->tile_y /= 2;
+    if (p.precision == AH_FP64) (void)measured_tile(p.precision, &cfg->tile_x, &cfg->tile_y);
     int zc = cfg->zchunk < 64 ? 64 : cfg->zchunk;
     if (zc > p.N) zc = p.N;
     cfg->zchunk = zc;

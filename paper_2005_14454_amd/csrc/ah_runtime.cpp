@@ -170,8 +170,6 @@ size_t field_bytes(const ah_params& p)
     return align_up(V * (p.precision == AH_FP64 ? 8 : 4));
 }
 
-// smallest z-chunk the tiled kernels accept for a lattice of side N
-int min_zchunk(int N) { return N < 8 ? N : 8; }
 
 // Diagnostics records a handle can hold: the largest number of workgroups
 // of any supported tile shape at the smallest z-chunk.
@@ -255,14 +253,6 @@ struct DeviceGuard {
     }
 };
 
-bool tile_supported(int precision, int tx, int ty)
-{
-    if (tx == 64 && (ty == 8 || ty == 4)) return true;
-    if (tx == 32 && ty == 8) return true;
-    if (tx == 128 && ty == 4) return true;
-    if ((tx == 64 && ty == 16) || (tx == 128 && ty == 8)) return precision == AH_FP32;
-    return false;
-}
 
 }  // namespace
 
@@ -286,9 +276,10 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
         return AH_E_INVAL;
     }
     if (c.tile_x == 0 && c.tile_y == 0) {
-        // FP32: 128-wide rows halve the x-halo line fetches per site; FP64
-        // keeps 64-wide rows (its 1024-thread tiles would spill)
-        c.tile_x = (p.precision == AH_FP32 && p.N >= 128) ? 128 : 64;
+        // FP32: 128-wide rows halve the x-halo line fetches per site.  FP64:
+        // 32 x 8, as fast as 64 x 8 for the plain step, and its measured
+        // march, unlike that of 512-thread tiles, does not spill
+        c.tile_x = p.precision == AH_FP32 ? (p.N >= 128 ? 128 : 64) : 32;
         c.tile_y = 8;
     }
     if (!tile_supported(p.precision, c.tile_x, c.tile_y)) {
@@ -371,9 +362,10 @@ namespace {
 
 int resolve_config(const ah_params& p, const ah_step_config& in, ah_step_config* out, std::string* why)
 {
+    ah_step_config tuned;
     if (in.kernel == AH_KERNEL_AUTO && in.tile_x == 0 && in.tile_y == 0 && in.zchunk == 0 &&
-        p.gauge_action == AH_COMPACT && tuned_config(p, out))
-        return AH_OK;
+        p.gauge_action == AH_COMPACT && tuned_config(p, &tuned))
+        return resolve_step_config(p, tuned, out, why);
     return resolve_step_config(p, in, out, why);
 }
 
@@ -389,16 +381,27 @@ MeasConst meas_const(const ah_params& p, int64_t n)
 
 // Tile configuration used for the diagnostics of a compact-action handle:
 // the step's own when the step is tiled, the default tile otherwise.
+// Tile of the measured march.  Any tile shape computes the same fields bit
+// for bit, so the measured step may use another shape than the plain one: the
+// step's own, unless its measured march would spill registers (FP32
+// 1024-thread tiles, FP64 512-thread tiles), in which case
+// the fastest shape that does not (FP32 64 x 8, FP64 32 x 8), with the
+// automatic z-chunk of that shape.  The site kernel's lattices (and
+// ah_measure on them) use the automatic tile configuration.
 TileConfig meas_tiles(const ah_handle* h)
 {
-    // 1024-thread tiles spill registers when they also form diagnostics;
-    // their 512-thread halves compute the same fields bit for bit
-    if (h->cfg.kernel == AH_KERNEL_TILE && h->cfg.tile_x * h->cfg.tile_y == 1024)
-        return TileConfig{h->cfg.tile_x, h->cfg.tile_y / 2, h->cfg.zchunk};
-    if (h->cfg.kernel == AH_KERNEL_TILE) return TileConfig{h->cfg.tile_x, h->cfg.tile_y, h->cfg.zchunk};
     ah_step_config d;
     std::string why;
+    if (h->cfg.kernel == AH_KERNEL_TILE) {
+        int tx = h->cfg.tile_x, ty = h->cfg.tile_y;
+        if (!measured_tile(h->p.precision, &tx, &ty)) return TileConfig{tx, ty, h->cfg.zchunk};
+        (void)resolve_step_config(h->p, ah_step_config{AH_KERNEL_TILE, tx, ty, 0}, &d, &why);
+        return TileConfig{d.tile_x, d.tile_y, d.zchunk};
+    }
     (void)resolve_step_config(h->p, ah_step_config{AH_KERNEL_TILE, 0, 0, 0}, &d, &why);
+    int tx = d.tile_x, ty = d.tile_y;
+    if (measured_tile(h->p.precision, &tx, &ty))
+        (void)resolve_step_config(h->p, ah_step_config{AH_KERNEL_TILE, tx, ty, 0}, &d, &why);
     return TileConfig{d.tile_x, d.tile_y, d.zchunk};
 }
 

@@ -139,9 +139,10 @@ struct TileShared {
     Cx<R> Phi[RS];      // phi of plane z
 };
 
-template <int TX, int TY>
+template <typename R, int TX, int TY>
 struct MeasShared {
     static constexpr int RS = (TX + 2) * (TY + 2);
+    R A[2][3][RS];                      // stored A of the link planes held in the U ring
     float Y[2][3][RS];                  // link phases of planes z (ring of two)
     double red[TX * TY / 64][M_COUNT];  // block reduction
 };
@@ -171,15 +172,46 @@ __device__ inline float link_phase(double pr, double pim, Cx<double> U, double v
     return atan2f((float)ldexp(zi, -e), (float)ldexp(zr, -e));
 }
 
+// The FP64 evaluation for an FP32 lattice's link near the cut.  It runs for a
+// few links in a million, so it is kept out of line: inlined, its FP64 sincos
+// raises the register count of the whole measured march.
+__device__ __attribute__((noinline)) float link_phase_near_cut(Cx<float> ph, Cx<float> pn, float a, double dx)
+{
+    return link_phase((double)ph.r, (double)ph.i, link64(dx, (double)a), (double)pn.r, (double)pn.i);
+}
+
+// Link phase of an FP32 lattice from z = conj(ph) (U pn), formed in FP32 from
+// the link the step itself uses; its angle, taken in FP32, is within
+//   |dx A| 2^-22 (rounding of dx A, in the link's phase)
+//   + 1e-5        (sincosf, the two complex products, atan2f; all a few ulp)
+// of the FP64 value, so unless it lies that close to the cut at +-pi it is on
+// the same side of it.  Near the cut, and where |z| leaves the range in which
+// FP32 keeps its relative precision (or is not finite), the FP64 evaluation
+// above decides from the stored A.
+__device__ inline float link_phase_f(Cx<float> z, Cx<float> ph, Cx<float> pn, float a, double dx)
+{
+    const float y = atan2f(z.i, z.r);
+    const float mz = fmaxf(fabsf(z.r), fabsf(z.i));
+    const float tol = 1e-5f + 2.4e-7f * fabsf((float)dx * a);
+    if (mz > 1e-30f && mz < 1e30f && 3.14159265f - fabsf(y) > tol) return y;
+    return link_phase_near_cut(ph, pn, a, dx);
+}
+
 // Winding of a plaquette from its four link phases and its angle (FP64): the
-// angle is wrapped to (-pi, pi] with the same division and rounding as the
-// definition; the total is then within ~1e-6 of a multiple of 2 pi.
+// angle is wrapped to (-pi, pi] by the nearest multiple of 2 pi that the
+// division th / 2 pi rounds to (a product with 1 / 2 pi gives the same
+// multiple unless the quotient is close to a half turn, where the division
+// itself is taken); the total is then within ~1e-5 of a multiple of 2 pi.
 __device__ inline int winding_of(float y1, float y2, float y3, float y4, double th)
 {
     const double two_pi = 6.283185307179586;
-    const double thw = th - two_pi * rint(th / two_pi);
+    const double inv_two_pi = 1.0 / two_pi;
+    const double q = th * inv_two_pi;
+    double r = rint(q);
+    if (!(fabs(q - r) < 0.49 && fabs(q) < 1e12)) r = rint(th / two_pi);
+    const double thw = th - two_pi * r;
     const double sum = ((((double)y1 + (double)y2) - (double)y3) - (double)y4) + thw;
-    return (int)rint(sum * (1.0 / two_pi));
+    return (int)rint(sum * inv_two_pi);
 }
 
 // 1 - cos(Theta) of a plaquette from its four links, without cancellation
@@ -215,7 +247,7 @@ __device__ inline double wave_max(double v)
 // All threads of the workgroup call this with the same arguments; it
 // synchronises the workgroup internally.
 template <typename R, int TX, int TY, bool MEAS>
-__device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, const StepArgs<R>& a,
+__device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx, const StepArgs<R>& a,
                            const MeasArgs& ma, double* __restrict__ record, bool write, int x0, int y0, int z0,
                            int z1)
 {
@@ -274,9 +306,6 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
     // neighbour slots in the region
     const int rxm = ro - 1, rxp = ro + 1, rym = ro - RW, ryp = ro + RW;
     const int rxm_yp = ro - 1 + RW, rxp_ym = ro + 1 - RW;
-    // neighbour sites in the plane (diagnostics only)
-    const int64_t xp_xy = (int64_t)wrapi(gxw + 1, N) + (int64_t)N * gyw;
-    const int64_t yp_xy = (int64_t)gxw + (int64_t)N * wrapi(gyw + 1, N);
 
     auto plane_of = [&](int z) -> int64_t { return (int64_t)wrapi(z, N) * NN; };
 
@@ -287,10 +316,18 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
     Cx<R> phi_m, phi_c, phi_p;
     Cx<R> uz_m;
     R fxz_m, fyz_m;
-    // diagnostics state (MEAS): FP64 links of the own column, own link phases
-    // Y_x, Y_y of the current plane, FP64 sums
-    Cx<double> W64c[3] = {}, W64p[3] = {};
-    float yx_c = 0.f, yy_c = 0.f;
+    // diagnostics state (MEAS): the (x, z) and (y, z) windings of plane z need
+    // Y_x, Y_y of plane z+1, so they are completed one plane later from the own
+    // link phases of plane z (_b) and the two plaquette angles of plane z
+    float yx_b = 0.f, yy_b = 0.f, yz_b = 0.f;
+    double thxz_b = 0.0, thyz_b = 0.0;
+    // link phase of a link U = exp(-i dx a) between phi values ph and pn
+    auto phase = [&](Cx<R> ph, Cx<R> U, Cx<R> pn, R av) -> float {
+        if constexpr (sizeof(R) == 8)
+            return link_phase(ph.r, ph.i, U, pn.r, pn.i);
+        else
+            return link_phase_f(cmulc(ph, cmul(U, pn)), ph, pn, av, ma.dx);
+    };
     // sums of the march: M_KIN .. M_GRADL (8 slots, FP64) and the exact
     // counts M_WABS, M_NONFIN (integers); the Gauss slots belong to k_gauss
     double acc[8];
@@ -311,30 +348,21 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
         if (has_halo)
             for (int d = 0; d < 3; ++d) {
                 sU[1][d][rh] = link(dx, A[d][pm + halo_xy]);
-                sU[0][d][rh] = link(dx, A[d][p0 + halo_xy]);
+                const R ah = A[d][p0 + halo_xy];
+                sU[0][d][rh] = link(dx, ah);
+                if constexpr (MEAS) mx->A[0][d][rh] = ah;
             }
+        if constexpr (MEAS)
+            for (int d = 0; d < 3; ++d) mx->A[0][d][ro] = Ac[d];
         phi_m = {f.phr[pm + own_xy], f.phi[pm + own_xy]};
         phi_c = {f.phr[p0 + own_xy], f.phi[p0 + own_xy]};
         sPhi[ro] = phi_c;
         if (has_halo) sPhi[rh] = Cx<R>{f.phr[p0 + halo_xy], f.phi[p0 + halo_xy]};
         uz_m = um[2];
-        if constexpr (MEAS) {
-            for (int d = 0; d < 3; ++d) {
-                if constexpr (sizeof(R) == 8)
-                    W64c[d] = Cx<double>{(double)Uc[d].r, (double)Uc[d].i};
-                else
-                    W64c[d] = link64(ma.dx, (double)Ac[d]);
-            }
-        }
         __syncthreads();
         // F_xz, F_yz of the own column at plane z0-1
         fxz_m = plaq_sin(um[0], sU[1][2][rxp], Uc[0], um[2]) * inv_dx2;
         fyz_m = plaq_sin(um[1], sU[1][2][ryp], Uc[1], um[2]) * inv_dx2;
-        if constexpr (MEAS) {
-            const Cx<R> px = sPhi[rxp], py = sPhi[ryp];
-            yx_c = link_phase(phi_c.r, phi_c.i, W64c[0], px.r, px.i);
-            yy_c = link_phase(phi_c.r, phi_c.i, W64c[1], py.r, py.i);
-        }
         __syncthreads();
         // U(z0+1) into slot 1
         const int64_t p1 = plane_of(z0 + 1);
@@ -344,7 +372,13 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
             sU[1][d][ro] = Up[d];
         }
         if (has_halo)
-            for (int d = 0; d < 3; ++d) sU[1][d][rh] = link(dx, A[d][p1 + halo_xy]);
+            for (int d = 0; d < 3; ++d) {
+                const R ah = A[d][p1 + halo_xy];
+                sU[1][d][rh] = link(dx, ah);
+                if constexpr (MEAS) mx->A[1][d][rh] = ah;
+            }
+        if constexpr (MEAS)
+            for (int d = 0; d < 3; ++d) mx->A[1][d][ro] = Ap[d];
         phi_p = {f.phr[p1 + own_xy], f.phi[p1 + own_xy]};
         __syncthreads();
     }
@@ -353,84 +387,67 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
     R pr_c = ld_stream(f.pir + pz0), pi_c = ld_stream(f.pii + pz0);
     R e_c[3] = {ld_stream(f.e0 + pz0), ld_stream(f.e1 + pz0), ld_stream(f.e2 + pz0)};
 
+    // Operands prefetched for iteration t: A of plane t+2 (own and halo), phi
+    // of plane t+1 (halo) and t+2 (own), Pi and E of plane t+1 (own).  The
+    // plain march loads them one iteration ahead.  The measured march of FP32
+    // lattices holds fewer waves per SIMD (it needs more registers), so it
+    // loads them two iterations ahead to keep as many loads in flight (FP64
+    // has no registers to spare for that); it loads every iteration's
+    // operands, the last ones of a chunk from wrapped planes that it does not
+    // use.
+    constexpr bool D2 = MEAS && sizeof(R) == 4;
+    struct Pre {
+        R a[3], ha[3];
+        Cx<R> hphi, phi2;
+        R pr, pi, e[3];
+    };
+    auto prefetch = [&](int t, Pre& q) {
+        const int64_t p2 = plane_of(t + 2), p1 = plane_of(t + 1);
+        q.a[0] = f.a0[p2 + own_xy];
+        q.a[1] = f.a1[p2 + own_xy];
+        q.a[2] = f.a2[p2 + own_xy];
+        if (has_halo) {
+            q.ha[0] = f.a0[p2 + halo_xy];
+            q.ha[1] = f.a1[p2 + halo_xy];
+            q.ha[2] = f.a2[p2 + halo_xy];
+            q.hphi = {f.phr[p1 + halo_xy], f.phi[p1 + halo_xy]};
+        }
+        q.phi2 = {f.phr[p2 + own_xy], f.phi[p2 + own_xy]};
+        q.pr = ld_stream(f.pir + p1 + own_xy);
+        q.pi = ld_stream(f.pii + p1 + own_xy);
+        q.e[0] = ld_stream(f.e0 + p1 + own_xy);
+        q.e[1] = ld_stream(f.e1 + p1 + own_xy);
+        q.e[2] = ld_stream(f.e2 + p1 + own_xy);
+    };
+    Pre q1, q2;
+    if constexpr (D2) prefetch(z0, q1);
+
     int cur = 0;
     for (int z = z0; z < z1; ++z) {
         const int nxt = cur ^ 1;
         const bool more = z + 1 < z1;  // is there a next iteration?
         const int zs = (z - z0) & 1;   // link-phase slot of plane z
-        // ---- 0. issue loads for the preparation of the next plane and the
-        //         own values of the next iteration
-        R rA[3] = {0, 0, 0}, hA[3] = {0, 0, 0};
-        Cx<R> rphi{0, 0}, hphi{0, 0}, phi_pp{0, 0};
-        R n_pr = 0, n_pi = 0, n_e[3] = {0, 0, 0};
-        if (more) {
-            const int64_t p2 = plane_of(z + 2), p1 = plane_of(z + 1), pn = (int64_t)(z + 1) * NN;
-            rA[0] = f.a0[p2 + own_xy];
-            rA[1] = f.a1[p2 + own_xy];
-            rA[2] = f.a2[p2 + own_xy];
-            if (has_halo) {
-                hA[0] = f.a0[p2 + halo_xy];
-                hA[1] = f.a1[p2 + halo_xy];
-                hA[2] = f.a2[p2 + halo_xy];
-                hphi = {f.phr[p1 + halo_xy], f.phi[p1 + halo_xy]};
-            }
-            phi_pp = {f.phr[p2 + own_xy], f.phi[p2 + own_xy]};
-            n_pr = ld_stream(f.pir + pn + own_xy);
-            n_pi = ld_stream(f.pii + pn + own_xy);
-            n_e[0] = ld_stream(f.e0 + pn + own_xy);
-            n_e[1] = ld_stream(f.e1 + pn + own_xy);
-            n_e[2] = ld_stream(f.e2 + pn + own_xy);
-        } else if constexpr (MEAS) {
-            if (has_halo) {
-                const int64_t p1 = plane_of(z + 1);
-                hphi = {f.phr[p1 + halo_xy], f.phi[p1 + halo_xy]};
-            }
-        }
-        rphi = phi_p;
-        // diagnostics loads: A of the +x / +y neighbours (never written by
-        // this pass) and the halo links of this plane (FP32 lattices)
-        R ay_xp = 0, ax_yp = 0, az_xp = 0, az_yp = 0;
-        R hz[3] = {0, 0, 0};
+        // ---- 0. issue the loads of the operands prefetched for the coming
+        //         iterations (q1 holds those of this one)
+        if constexpr (D2)
+            prefetch(z + 1, q2);
+        else if (more || MEAS)
+            prefetch(z, q1);
+        const R* rA = q1.a;
+        const R* hA = q1.ha;
+        const Cx<R> hphi = q1.hphi;
+        const Cx<R> rphi = phi_p;
+        float yx_c = 0.f, yy_c = 0.f, yz_c = 0.f;
+        double th_xy = 0.0;
         if constexpr (MEAS) {
-            const int64_t pz = (int64_t)z * NN;
-            ay_xp = f.a1[pz + xp_xy];
-            ax_yp = f.a0[pz + yp_xy];
-            az_xp = f.a2[pz + xp_xy];
-            az_yp = f.a2[pz + yp_xy];
-            if constexpr (sizeof(R) == 4) {
-                if (halo_top || halo_right) {
-                    hz[0] = f.a0[pz + halo_xy];
-                    hz[1] = f.a1[pz + halo_xy];
-                    hz[2] = f.a2[pz + halo_xy];
-                }
-            }
-        }
-        float yz_c = 0.f;
-        if constexpr (MEAS) {
-            // ---- link phases of plane z: own and the +x / +y halo
-            yz_c = link_phase(phi_c.r, phi_c.i, W64c[2], phi_p.r, phi_p.i);
+            // ---- link phases of plane z on the +x / +y halo
             auto& sY = mx->Y[zs];
-            sY[0][ro] = yx_c;
-            sY[1][ro] = yy_c;
-            sY[2][ro] = yz_c;
             if (halo_top || halo_right) {
                 const Cx<R> ph = sPhi[rh];
-                Cx<double> hl[3];
-                for (int d = 0; d < 3; ++d) {
-                    if constexpr (sizeof(R) == 8)
-                        hl[d] = Cx<double>{(double)sU[cur][d][rh].r, (double)sU[cur][d][rh].i};
-                    else
-                        hl[d] = link64(ma.dx, (double)hz[d]);
-                }
-                if (halo_top) {
-                    const Cx<R> pn = sPhi[rh + 1];
-                    sY[0][rh] = link_phase(ph.r, ph.i, hl[0], pn.r, pn.i);
-                }
-                if (halo_right) {
-                    const Cx<R> pn = sPhi[rh + RW];
-                    sY[1][rh] = link_phase(ph.r, ph.i, hl[1], pn.r, pn.i);
-                }
-                sY[2][rh] = link_phase(ph.r, ph.i, hl[2], hphi.r, hphi.i);
+                const auto& sA = mx->A[cur];
+                if (halo_top) sY[0][rh] = phase(ph, sU[cur][0][rh], sPhi[rh + 1], sA[0][rh]);
+                if (halo_right) sY[1][rh] = phase(ph, sU[cur][1][rh], sPhi[rh + RW], sA[1][rh]);
+                sY[2][rh] = phase(ph, sU[cur][2][rh], hphi, sA[2][rh]);
             }
         }
 
@@ -451,6 +468,35 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
             const R jx = fm(phi_c.r, fx.i, -(phi_c.i * fx.r)) * inv_dx;
             const R jy = fm(phi_c.r, fy.i, -(phi_c.i * fy.r)) * inv_dx;
             const R jz = fm(phi_c.r, fz.i, -(phi_c.i * fz.r)) * inv_dx;
+            if constexpr (MEAS) {
+                // own link phases of plane z (FP32 lattices: z = conj(phi) U phi^{x+j}
+                // is the forward product of the Laplacian)
+                if constexpr (sizeof(R) == 8) {
+                    yx_c = link_phase(phi_c.r, phi_c.i, Uc[0], ph_xp.r, ph_xp.i);
+                    yy_c = link_phase(phi_c.r, phi_c.i, Uc[1], ph_yp.r, ph_yp.i);
+                    yz_c = link_phase(phi_c.r, phi_c.i, Uc[2], phi_p.r, phi_p.i);
+                } else {
+                    yx_c = link_phase_f(cmulc(phi_c, fx), phi_c, ph_xp, Ac[0], ma.dx);
+                    yy_c = link_phase_f(cmulc(phi_c, fy), phi_c, ph_yp, Ac[1], ma.dx);
+                    yz_c = link_phase_f(cmulc(phi_c, fz), phi_c, phi_p, Ac[2], ma.dx);
+                }
+                auto& sY = mx->Y[zs];
+                sY[0][ro] = yx_c;
+                sY[1][ro] = yy_c;
+                sY[2][ro] = yz_c;
+                // the (x, z), (y, z) windings at x, plane z-1, now that Y_x, Y_y
+                // of plane z are known
+                if (active && z > z0) {
+                    const auto& sYb = mx->Y[zs ^ 1];
+                    wabs += abs(winding_of(yx_b, sYb[2][rxp], yx_c, yz_b, thxz_b)) +
+                            abs(winding_of(yy_b, sYb[2][ryp], yy_c, yz_b, thyz_b));
+                }
+                // plaquette angles at x, plane z, from the stored A
+                const auto& sA = mx->A[cur];
+                th_xy = ma.dx * ((((double)Ac[0] + (double)sA[1][rxp]) - (double)sA[0][ryp]) - (double)Ac[1]);
+                thxz_b = ma.dx * ((((double)Ac[0] + (double)sA[2][rxp]) - (double)Ap[0]) - (double)Ac[2]);
+                thyz_b = ma.dx * ((((double)Ac[1] + (double)sA[2][ryp]) - (double)Ap[1]) - (double)Ac[2]);
+            }
             // plaquettes at x (F_ij^x, i<j)
             const Cx<R> uy_xp = sU[cur][1][rxp], ux_yp = sU[cur][0][ryp];
             const Cx<R> uz_xp = sU[cur][2][rxp], uz_yp = sU[cur][2][ryp];
@@ -542,9 +588,11 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
             // winding of the (x, y) plaquette at x, plane z
             if (active) {
                 const auto& sY = mx->Y[zs];
-                const double th = ma.dx * ((((double)Ac[0] + (double)ay_xp) - (double)ax_yp) - (double)Ac[1]);
-                wabs += abs(winding_of(yx_c, sY[1][rxp], sY[0][ryp], yy_c, th));
+                wabs += abs(winding_of(yx_c, sY[1][rxp], sY[0][ryp], yy_c, th_xy));
             }
+            yx_b = yx_c;
+            yy_b = yy_c;
+            yz_b = yz_c;
         }
 
         // ---- 3. plane z+2 links into slot cur, plane z+1 phi into sPhi
@@ -553,9 +601,13 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
             for (int d = 0; d < 3; ++d) {
                 Upp[d] = link(dx, rA[d]);
                 sU[cur][d][ro] = Upp[d];
+                if constexpr (MEAS) mx->A[cur][d][ro] = rA[d];
             }
             if (has_halo) {
-                for (int d = 0; d < 3; ++d) sU[cur][d][rh] = link(dx, hA[d]);
+                for (int d = 0; d < 3; ++d) {
+                    sU[cur][d][rh] = link(dx, hA[d]);
+                    if constexpr (MEAS) mx->A[cur][d][rh] = hA[d];
+                }
                 sPhi[rh] = hphi;
             }
             sPhi[ro] = rphi;
@@ -565,29 +617,21 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
         }
         __syncthreads();
 
-        if constexpr (MEAS) {
-            // own link phases of plane z+1 and the (x, z), (y, z) windings of plane z
-            for (int d = 0; d < 3; ++d) {
-                if constexpr (sizeof(R) == 8)
-                    W64p[d] = Cx<double>{(double)Up[d].r, (double)Up[d].i};
-                else
-                    W64p[d] = link64(ma.dx, (double)Ap[d]);
+        if (!more) {
+            if constexpr (MEAS) {
+                // own Y_x, Y_y of plane z1 complete the (x, z), (y, z) windings
+                // of the chunk's last plane
+                const Cx<R> px = sPhi[rxp], py = sPhi[ryp];
+                const float yx_n = phase(phi_p, Up[0], px, Ap[0]);
+                const float yy_n = phase(phi_p, Up[1], py, Ap[1]);
+                if (active) {
+                    const auto& sYb = mx->Y[zs];
+                    wabs += abs(winding_of(yx_b, sYb[2][rxp], yx_n, yz_b, thxz_b)) +
+                            abs(winding_of(yy_b, sYb[2][ryp], yy_n, yz_b, thyz_b));
+                }
             }
-            const Cx<R> px = sPhi[rxp], py = sPhi[ryp];
-            const float yx_n = link_phase(phi_p.r, phi_p.i, W64p[0], px.r, px.i);
-            const float yy_n = link_phase(phi_p.r, phi_p.i, W64p[1], py.r, py.i);
-            if (active) {
-                const auto& sY = mx->Y[zs];
-                const double thxz = ma.dx * ((((double)Ac[0] + (double)az_xp) - (double)Ap[0]) - (double)Ac[2]);
-                const double thyz = ma.dx * ((((double)Ac[1] + (double)az_yp) - (double)Ap[1]) - (double)Ac[2]);
-                wabs += abs(winding_of(yx_c, sY[2][rxp], yx_n, yz_c, thxz)) +
-                        abs(winding_of(yy_c, sY[2][ryp], yy_n, yz_c, thyz));
-            }
-            yx_c = yx_n;
-            yy_c = yy_n;
-            for (int d = 0; d < 3; ++d) W64c[d] = W64p[d];
+            break;
         }
-        if (!more) break;
 
         // ---- 5. rotate the own-column registers
         uz_m = Uc[2];
@@ -595,14 +639,15 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<TX, TY>* mx, co
             Uc[d] = Up[d];
             Up[d] = Upp[d];
             Ac[d] = Ap[d];
-            Ap[d] = rA[d];
-            e_c[d] = n_e[d];
+            Ap[d] = q1.a[d];
+            e_c[d] = q1.e[d];
         }
         phi_m = phi_c;
         phi_c = phi_p;
-        phi_p = phi_pp;
-        pr_c = n_pr;
-        pi_c = n_pi;
+        phi_p = q1.phi2;
+        pr_c = q1.pr;
+        pi_c = q1.pi;
+        if constexpr (D2) q1 = q2;
         cur = nxt;
     }
 
@@ -640,7 +685,7 @@ __global__ void __launch_bounds__(TX* TY) k_step_tile(StepArgs<R> a, MeasArgs ma
                                                       int zchunk, int tiles_x, int tiles_y)
 {
     __shared__ TileShared<R, TX, TY> sh;
-    __shared__ MeasShared<TX, MEAS ? TY : 8> mxs;
+    __shared__ MeasShared<R, TX, MEAS ? TY : 8> mxs;
     const int t0 = xcd_tile(blockIdx.x, gridDim.x);
     int t = t0;
     const int tx = t % tiles_x;
@@ -674,7 +719,7 @@ __global__ void __launch_bounds__(TX* TY) k_step_batch(const PoolLattice* __rest
                                                        const WorkItem* __restrict__ work, int nwork)
 {
     __shared__ TileShared<R, TX, TY> sh;
-    __shared__ MeasShared<TX, MEAS ? TY : 8> mxs;
+    __shared__ MeasShared<R, TX, MEAS ? TY : 8> mxs;
     for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
         const WorkItem it = work[w];
         const PoolLattice& L = lat[it.lattice];

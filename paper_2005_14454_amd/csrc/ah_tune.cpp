@@ -25,6 +25,15 @@ std::map<std::pair<int, int>, Entry> g_table;  // (precision, N) -> choice
 }  // namespace
 
 namespace ah {
+// A table entry names a supported tile shape for its precision and a z-chunk
+// that is automatic (0) or at least the minimum.
+static bool valid_entry(int precision, int N, const ah_step_config& c)
+{
+    return (precision == AH_FP32 || precision == AH_FP64) && N >= 4 && c.kernel == AH_KERNEL_TILE &&
+           tile_supported(precision, c.tile_x, c.tile_y) && c.zchunk >= 0 &&
+           (c.zchunk == 0 || c.zchunk >= min_zchunk(N));
+}
+
 bool tuned_config(const ah_params& p, ah_step_config* out)
 {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -94,7 +103,7 @@ int ah_tune_lookup(const ah_params* p, ah_step_config* out)
 int ah_tune_set(const ah_params* p, const ah_step_config* c)
 {
     if (!p || !c) return AH_E_INVAL;
-    if (c->kernel != AH_KERNEL_TILE) return AH_E_INVAL;
+    if (!ah::valid_entry(p->precision, p->N, *c)) return AH_E_INVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_table[{p->precision, p->N}] = Entry{*c, 0.0};
     return AH_OK;
@@ -130,22 +139,34 @@ int ah_tune_load(const char* path)
     if (!path) return AH_E_INVAL;
     FILE* f = std::fopen(path, "r");
     if (!f) return AH_E_INVAL;
+    // every entry line is checked before any is taken: a file with a bad
+    // entry changes nothing
     char line[512];
-    int loaded = 0;
+    std::vector<std::pair<std::pair<int, int>, Entry>> got;
+    bool bad = false;
     while (std::fgets(line, sizeof(line), f)) {
+        if (!std::strstr(line, "\"precision\"")) continue;
         char prec[8] = {0};
         int N, tx, ty, zc;
         double ms;
         if (std::sscanf(line, " {\"precision\": \"%7[a-z0-9]\", \"N\": %d, \"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, \"ms\": %lf",
-                        prec, &N, &tx, &ty, &zc, &ms) == 6) {
-            const int pr = std::strcmp(prec, "fp64") == 0 ? AH_FP64 : AH_FP32;
-            std::lock_guard<std::mutex> lk(g_mu);
-            g_table[{pr, N}] = Entry{ah_step_config{AH_KERNEL_TILE, tx, ty, zc}, ms};
-            ++loaded;
+                        prec, &N, &tx, &ty, &zc, &ms) != 6) {
+            bad = true;
+            continue;
         }
+        const int pr = std::strcmp(prec, "fp64") == 0 ? AH_FP64 : (std::strcmp(prec, "fp32") == 0 ? AH_FP32 : -1);
+        const ah_step_config c{AH_KERNEL_TILE, tx, ty, zc};
+        if (!ah::valid_entry(pr, N, c)) {
+            bad = true;
+            continue;
+        }
+        got.push_back({{pr, N}, Entry{c, ms}});
     }
     std::fclose(f);
-    return loaded >= 0 ? AH_OK : AH_E_INVAL;
+    if (bad) return AH_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& kv : got) g_table[kv.first] = kv.second;
+    return AH_OK;
 }
 
 }  // extern "C"

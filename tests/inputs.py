@@ -50,3 +50,27 @@ def grid(N: int):
     """Integer coordinates (x0, x1, x2) of every site, each of shape (N^3,)."""
     idx = np.arange(N ** 3, dtype=np.int64)
     return idx % N, (idx // N) % N, idx // (N * N)
+
+
+def near_cut_state(N: int, seed: int, dx: float = 0.5, kmax: int = 1000, eps: float = 1e-4) -> np.ndarray:
+    """State whose windings sit on their decision boundaries.
+
+    phi has phase pi ((x0 + x1 + x2) mod 2) + U(-eps, eps), so with a trivial
+    link the gauge-invariant link phases lie within ~2 eps of the branch cut
+    at +-pi; A_i = 2 pi k / dx with k uniform in [-kmax, kmax] (links near 1,
+    but |dx A| up to ~2 pi kmax), plus pi / dx on x-links at odd x1, which
+    puts every (x, y) plaquette angle on a half turn.  Pi and E are Gaussian."""
+    rng = np.random.default_rng(seed)
+    V = N ** 3
+    x0, x1, x2 = grid(N)
+    st = np.empty((NCOMP, V), dtype=np.float64)
+    mod = 1.0 + 0.3 * rng.standard_normal(V)
+    ang = np.pi * ((x0 + x1 + x2) % 2) + rng.uniform(-eps, eps, V)
+    st[0] = mod * np.cos(ang)
+    st[1] = mod * np.sin(ang)
+    st[2:4] = 0.3 * rng.standard_normal((2, V))
+    k = rng.integers(-kmax, kmax + 1, (3, V))
+    st[4:7] = 2.0 * np.pi * k / dx
+    st[4] += (np.pi / dx) * (x1 % 2)
+    st[7:10] = 0.3 * rng.standard_normal((3, V))
+    return st

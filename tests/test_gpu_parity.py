@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from helpers import both_params, field_scaled_error, max_field_error, ulp_distance
-from inputs import random_state
+from inputs import near_cut_state, random_state
 
 pytestmark = pytest.mark.gpu
 
@@ -171,6 +171,30 @@ def test_measure_on_random_snapshot(oracle_mod, ah, precision):
     assert abs(gm["R"] - om["R"]) <= (1e-11 if precision == "fp64" else 1e-4) * abs(om["R"])
     for k in ("gauss_rms", "gauss_max", "gauss_rel"):
         assert abs(gm[k] - om[k]) <= 1e-11 * abs(om[k]), (k, gm[k], om[k])
+
+
+@pytest.mark.parametrize("tile", [(64, 8), (32, 8), (64, 4)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_windings_on_decision_boundaries(oracle_mod, ah, precision, tile):
+    """Link phases within ~1e-4 of the cut at +-pi, |dx A| up to ~6e3 and
+    plaquette angles on half turns: every winding still equals the oracle's,
+    in the fused diagnostics pass (several tiles, halo columns) and in the
+    winding field."""
+    N = 40
+    op, gp = both_params(oracle_mod, N, precision)
+    st = near_cut_state(N, seed=8, dx=op["dx"])
+    if precision == "fp32":
+        st = st.astype(np.float32).astype(np.float64)
+    with ah.Lattice(gp) as lat:
+        lat.set_step_config("tile", tile, 0)
+        lat.set_state(st, 3)
+        gm = lat.measure()
+        w = lat.winding()
+    om = oracle_mod.measure(op, st, 3)
+    wo = oracle_mod.winding(op, st)
+    assert np.count_nonzero(wo) > 0
+    assert gm["winding_sum_abs"] == om["winding_sum_abs"]
+    assert np.array_equal(w, wo.astype(np.int8))
 
 
 def test_deterministic_and_resumable(ah):

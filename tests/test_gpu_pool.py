@@ -74,10 +74,13 @@ def test_pool_alone_vs_mix_bitwise(ah):
                 series[rid] = pool.results(rid)
         assert sorted(finished) == sorted(ids)
         assert pool.stats()["active"] == 0 and pool.stats()["bytes_in_use"] == 0
-    # the pool runs whole-column z-chunks (>= 64 planes); alone with the same
-    # tiling the diagnostics records are summed in the same order
+    # the pool runs whole-column z-chunks (>= 64 planes) on 64 x 8 tiles (FP32)
+    # or 32 x 8 tiles (FP64, whose 512-thread measured march would spill);
+    # alone with the same tiling the diagnostics records are summed in the
+    # same order
     for (p, seed, n, every), rid in zip(reqs, ids):
-        st, ser = _alone(ah, p, seed, n, every, (64, 8), min(p.N, 64))
+        tile = (32, 8) if p.precision == "fp64" else (64, 8)
+        st, ser = _alone(ah, p, seed, n, every, tile, min(p.N, 64))
         assert np.array_equal(states[rid], st), (p, seed)
         assert len(series[rid]) == len(ser)
         for a, b in zip(series[rid], ser):

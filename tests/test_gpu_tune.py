@@ -1,0 +1,53 @@
+"""The autotuner: it times the tiled step's tile shapes and z-chunks for a
+(precision, N), records the fastest, and lattices created afterwards with
+automatic configuration use it.  Every tile shape computes the same fields
+bit for bit, so a tuned lattice evolves exactly as an untuned one."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {(64, 8), (64, 4), (32, 8), (128, 4), (64, 16), (128, 8)}
+
+
+@pytest.fixture
+def ah():
+    import paper_2005_14454_amd as ah
+    ah.tune_clear()
+    yield ah
+    ah.tune_clear()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_autotune_records_and_is_used(ah, precision):
+    p = ah.Params(N=48, precision=precision)
+    best = ah.autotune(p, steps=2)
+    assert best["kernel"] == "tile" and best["ms"] > 0
+    assert tuple(best["tile"]) in SHAPES
+    if precision == "fp64":
+        assert tuple(best["tile"]) not in {(64, 16), (128, 8)}
+    assert 8 <= best["zchunk"] <= 48
+    assert ah.tune_lookup(p)["tile"] == best["tile"]
+    with ah.Lattice(p) as lat:
+        cfg = lat.get_step_config()
+        assert (cfg["kernel"], cfg["tile"], cfg["zchunk"]) == ("tile", best["tile"], best["zchunk"])
+        lat.init(3)
+        lat.step(4)
+        tuned = lat.get_state()
+    ah.tune_clear()
+    with ah.Lattice(p) as lat:
+        lat.init(3)
+        lat.step(4)
+        assert np.array_equal(lat.get_state(), tuned)
+
+
+def test_tuned_automatic_zchunk_is_resolved(ah):
+    p = ah.Params(N=40, precision="fp32")
+    ah.tune_set(p, (64, 4), 0)
+    with ah.Lattice(p) as lat:
+        cfg = lat.get_step_config()
+        assert cfg["tile"] == (64, 4) and 8 <= cfg["zchunk"] <= 40
+        lat.init(5)
+        lat.step(3)
+        m = lat.measure()
+    assert m["nonfinite"] == 0 and m["step"] == 3

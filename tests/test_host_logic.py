@@ -92,3 +92,41 @@ def test_request_stream_recipe(ah):
         twin = reqs[r.pair_of]
         assert twin.params.precision == "fp32" and twin.seed == r.seed and twin.params.N == r.params.N
     assert steps_to_half_light_crossing(256) == 630 and steps_to_half_light_crossing(512) == 1270
+
+
+def test_tuning_table_roundtrip_and_validation(ah, tmp_path):
+    """The autotuner's table (set, look up, save as JSON, load), host side; only
+    supported tile shapes and z-chunks enter it, and a file with a bad entry
+    changes nothing."""
+    import json
+    p32 = ah.Params(N=96, precision="fp32")
+    p64 = ah.Params(N=40, precision="fp64")
+    ah.tune_clear()
+    try:
+        assert ah.tune_lookup(p32) is None
+        ah.tune_set(p32, (128, 8), 48)
+        ah.tune_set(p64, (32, 8), 0)
+        assert ah.tune_lookup(p32) == {"kernel": "tile", "tile": (128, 8), "zchunk": 48}
+        assert ah.tune_lookup(p64) == {"kernel": "tile", "tile": (32, 8), "zchunk": 0}
+        path = tmp_path / "tune.json"
+        ah.tune_save(str(path))
+        doc = json.loads(path.read_text())
+        assert sorted((e["precision"], e["N"]) for e in doc["entries"]) == [("fp32", 96), ("fp64", 40)]
+        ah.tune_clear()
+        assert ah.tune_lookup(p32) is None and ah.tune_lookup(p64) is None
+        ah.tune_load(str(path))
+        assert ah.tune_lookup(p32)["tile"] == (128, 8) and ah.tune_lookup(p64)["tile"] == (32, 8)
+        for bad in [(p64, (128, 8), 0), (p64, (64, 16), 0), (p32, (48, 8), 0), (p32, (64, 8), 3),
+                    (p32, (64, 8), -1)]:
+            with pytest.raises(ah.AHError):
+                ah.tune_set(*bad)
+        assert ah.tune_lookup(p64)["tile"] == (32, 8)
+        badfile = tmp_path / "bad.json"
+        badfile.write_text('{"version": 1, "entries": [\n'
+                           '{"precision": "fp32", "N": 64, "tile_x": 64, "tile_y": 8, "zchunk": 0, "ms": 1},\n'
+                           '{"precision": "fp32", "N": 80, "tile_x": 48, "tile_y": 8, "zchunk": 0, "ms": 1}\n]}\n')
+        with pytest.raises(ah.AHError):
+            ah.tune_load(str(badfile))
+        assert ah.tune_lookup(ah.Params(N=64, precision="fp32")) is None
+    finally:
+        ah.tune_clear()
