@@ -244,7 +244,7 @@ int rebuild(ah_pool* P)
     for (int measured = 1; measured >= 0; --measured) {
         for (auto& g : step_groups) {
             if (le != hipSuccess) break;
-            const int grid = (int)std::min<size_t>(g.n, measured ? 1024 : 2048);
+            const int grid = (int)g.n;  // one block per work item
             le = g.precision == AH_FP64 ? launch_step_batch<double>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx,
                                                                     g.ty, grid, measured != 0, P->stream)
                                         : launch_step_batch<float>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx, g.ty,

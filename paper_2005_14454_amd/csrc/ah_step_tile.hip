@@ -677,11 +677,20 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     }
 }
 
+// Waves per SIMD the compiler must leave room for.  The plain FP32 march
+// fits in 128 registers, i.e. four waves per SIMD: two 512-thread workgroups
+// per CU, so one can load while the other waits at a barrier.  Left to itself
+// the compiler may take a few more registers, which drops a 512-thread tile
+// to one workgroup per CU.  The measured march and FP64 need more registers
+// and are left free.
+template <typename R, bool MEAS>
+constexpr int kMinWaves = (!MEAS && sizeof(R) == 4) ? 4 : 1;
+
 // One lattice: block b owns tile t = xcd_tile(b) (tx fastest, then ty, then
 // z-chunk); with MEAS it writes diagnostics record t, so the records are in
 // tile order whatever the launch geometry.
 template <typename R, int TX, int TY, bool MEAS>
-__global__ void __launch_bounds__(TX* TY) k_step_tile(StepArgs<R> a, MeasArgs ma, double* partials, int write,
+__global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_tile(StepArgs<R> a, MeasArgs ma, double* partials, int write,
                                                       int zchunk, int tiles_x, int tiles_y)
 {
     __shared__ TileShared<R, TX, TY> sh;
@@ -714,54 +723,72 @@ __device__ inline bool measure_due(const PoolLattice& L, int64_t k)
 // run its steps.  MEAS: only lattices whose snapshot k is due for diagnostics
 // (measured step, or measurement alone for the final snapshot); otherwise
 // only lattices that are not due.
+// A block-uniform value moved into scalar registers.  The pool kernel reads
+// its lattice descriptor from memory, and the compiler keeps what it loads
+// from there in vector registers (one copy per lane), which would cost the
+// plain march a wave per SIMD of occupancy.
+template <typename T>
+__device__ inline T uniform(T v)
+{
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+    for (unsigned k = 0; k < sizeof(T) / 4; ++k) w[k] = __builtin_amdgcn_readfirstlane(w[k]);
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+
 template <typename R, int TX, int TY, bool MEAS>
-__global__ void __launch_bounds__(TX* TY) k_step_batch(const PoolLattice* __restrict__ lat,
+__global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(const PoolLattice* __restrict__ lat,
                                                        const WorkItem* __restrict__ work, int nwork)
 {
     __shared__ TileShared<R, TX, TY> sh;
     __shared__ MeasShared<R, TX, MEAS ? TY : 8> mxs;
-    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-        const WorkItem it = work[w];
-        const PoolLattice& L = lat[it.lattice];
-        const int64_t k = *L.counter;
-        const bool due = measure_due(L, k);
-        if (MEAS != due) continue;                   // uniform across the block
-        if (!MEAS && k >= L.nsteps) continue;
-        const double* row = L.coef + k * kCoefStride;
-        const int cur = (int)(k & 1);
-        StepArgs<R> a;
-        a.f = Fields<R>{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[0], (R*)L.mom[1], (R*)L.pp[cur][2],
-                        (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[2], (R*)L.mom[3], (R*)L.mom[4]};
-        a.ophr = (R*)L.pp[cur ^ 1][0];
-        a.ophi = (R*)L.pp[cur ^ 1][1];
-        a.oa0 = (R*)L.pp[cur ^ 1][2];
-        a.oa1 = (R*)L.pp[cur ^ 1][3];
-        a.oa2 = (R*)L.pp[cur ^ 1][4];
-        a.N = L.N;
-        a.dx = (R)L.dx;
-        a.sigma2 = (R)L.sigma2;
-        a.cP1 = (R)row[C_P1];
-        a.cP2 = (R)row[C_P2];
-        a.cE1 = (R)row[C_E1];
-        a.cE2 = (R)row[C_E2];
-        a.lamh = (R)row[C_LAMH];
-        a.kappa = (R)row[C_KAPPA];
-        a.deta = (R)L.deta;
-        const MeasArgs ma{L.dx, row[C_INV2E2F], row[C_LAMQ], row[C_GAUSS]};
-        int t = it.tile;
-        const int tx = t % L.tiles_x;
-        t /= L.tiles_x;
-        const int ty = t % L.tiles_y;
-        const int tz = t / L.tiles_y;
-        const int z0 = tz * L.zchunk;
-        const int z1 = (z0 + L.zchunk < L.N) ? z0 + L.zchunk : L.N;
-        if constexpr (MEAS)
-            march_step<R, TX, TY, true>(sh, &mxs, a, ma, L.partials + (int64_t)it.tile * kMeasStride, k < L.nsteps,
-                                        tx * TX, ty * TY, z0, z1);
-        else
-            march_step<R, TX, TY, false>(sh, nullptr, a, ma, nullptr, true, tx * TX, ty * TY, z0, z1);
-        __syncthreads();  // LDS is reused by the next item
-    }
+    // one work item per block; each XCD gets a contiguous band of the list,
+    // which is ordered by lattice and then tile index, so neighbouring tiles
+    // share an L2
+    const int w = xcd_tile(blockIdx.x, nwork);
+    const WorkItem it = work[w];
+    const PoolLattice& L = lat[it.lattice];
+    const int64_t k = *L.counter;
+    const bool due = measure_due(L, k);
+    if (MEAS != due) return;                     // uniform across the block
+    if (!MEAS && k >= L.nsteps) return;
+    const double* row = L.coef + k * kCoefStride;
+    const int cur = (int)(k & 1);
+    StepArgs<R> a;
+    a.f = Fields<R>{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[0], (R*)L.mom[1], (R*)L.pp[cur][2],
+                    (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[2], (R*)L.mom[3], (R*)L.mom[4]};
+    a.ophr = (R*)L.pp[cur ^ 1][0];
+    a.ophi = (R*)L.pp[cur ^ 1][1];
+    a.oa0 = (R*)L.pp[cur ^ 1][2];
+    a.oa1 = (R*)L.pp[cur ^ 1][3];
+    a.oa2 = (R*)L.pp[cur ^ 1][4];
+    a.N = L.N;
+    a.dx = (R)L.dx;
+    a.sigma2 = (R)L.sigma2;
+    a.cP1 = (R)row[C_P1];
+    a.cP2 = (R)row[C_P2];
+    a.cE1 = (R)row[C_E1];
+    a.cE2 = (R)row[C_E2];
+    a.lamh = (R)row[C_LAMH];
+    a.kappa = (R)row[C_KAPPA];
+    a.deta = (R)L.deta;
+    a = uniform(a);
+    const MeasArgs ma = uniform(MeasArgs{L.dx, row[C_INV2E2F], row[C_LAMQ], row[C_GAUSS]});
+    int t = it.tile;
+    const int tx = t % L.tiles_x;
+    t /= L.tiles_x;
+    const int ty = t % L.tiles_y;
+    const int tz = t / L.tiles_y;
+    const int z0 = uniform(tz * L.zchunk);
+    const int z1 = uniform((z0 + L.zchunk < L.N) ? z0 + L.zchunk : L.N);
+    const int x0 = uniform(tx * TX), y0 = uniform(ty * TY);
+    if constexpr (MEAS)
+        march_step<R, TX, TY, true>(sh, &mxs, a, ma, uniform(L.partials + (int64_t)it.tile * kMeasStride),
+                                    k < L.nsteps, x0, y0, z0, z1);
+    else
+        march_step<R, TX, TY, false>(sh, nullptr, a, ma, nullptr, true, x0, y0, z0, z1);
 }
 
 
@@ -898,25 +925,31 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
         ma.gauss_c = mc->gauss_c;
     }
     const int zc = tc.zchunk > 0 ? tc.zchunk : N;
-#define AH_TILE_CASE(TXv, TYv)                                                                                     \
+    // MEASv: whether the shape has a measured instance (1024-thread tiles have
+    // none: their measured march would spill, and the runtime measures them
+    // on a 512-thread shape)
+#define AH_TILE_CASE(TXv, TYv, MEASv)                                                                              \
     if (tc.tx == TXv && tc.ty == TYv) {                                                                            \
         const int tiles_x = (N + TXv - 1) / TXv, tiles_y = (N + TYv - 1) / TYv;                                   \
         const int nb = tiles_x * tiles_y * ((N + zc - 1) / zc);                                                   \
-        if (mc)                                                                                                    \
-            hipLaunchKernelGGL((k_step_tile<R, TXv, TYv, true>), dim3(nb), dim3(TXv * TYv), 0, s, a, ma, partials, \
-                               write ? 1 : 0, zc, tiles_x, tiles_y);                                              \
-        else                                                                                                       \
+        if (mc) {                                                                                                  \
+            if constexpr (!MEASv) return hipErrorInvalidValue;                                                     \
+            else                                                                                                   \
+                hipLaunchKernelGGL((k_step_tile<R, TXv, TYv, MEASv>), dim3(nb), dim3(TXv * TYv), 0, s, a, ma,      \
+                                   partials, write ? 1 : 0, zc, tiles_x, tiles_y);                                \
+        } else {                                                                                                   \
             hipLaunchKernelGGL((k_step_tile<R, TXv, TYv, false>), dim3(nb), dim3(TXv * TYv), 0, s, a, ma, partials, \
                                1, zc, tiles_x, tiles_y);                                                          \
+        }                                                                                                          \
         return hipGetLastError();                                                                                 \
     }
-    AH_TILE_CASE(64, 8)
-    AH_TILE_CASE(64, 4)
-    AH_TILE_CASE(32, 8)
-    AH_TILE_CASE(128, 4)
+    AH_TILE_CASE(64, 8, true)
+    AH_TILE_CASE(64, 4, true)
+    AH_TILE_CASE(32, 8, true)
+    AH_TILE_CASE(128, 4, true)
     if constexpr (sizeof(R) == 4) {
-        AH_TILE_CASE(64, 16)
-        AH_TILE_CASE(128, 8)
+        AH_TILE_CASE(64, 16, false)
+        AH_TILE_CASE(128, 8, false)
     }
 #undef AH_TILE_CASE
     return hipErrorInvalidValue;

@@ -33,3 +33,39 @@ def max_field_error(got, ref) -> float:
 
 def ulp_distance(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     return np.abs(a - b) / np.spacing(np.maximum(np.abs(a), np.abs(b)))
+
+
+def same_record(a: dict, b: dict) -> bool:
+    """Bitwise equality of two measurement dicts (NaN equals NaN)."""
+    if a.keys() != b.keys():
+        return False
+    for k in a:
+        x, y = a[k], b[k]
+        if isinstance(x, float) and isinstance(y, float):
+            if not (x == y or (math.isnan(x) and math.isnan(y))):
+                return False
+        elif x != y:
+            return False
+    return True
+
+
+def pool_tile(precision: str):
+    """Tile shape the pool runs a lattice of this precision on (for N < 128 and
+    no tuned entry): 64 x 8 for FP32, 32 x 8 for FP64."""
+    return (32, 8) if precision == "fp64" else (64, 8)
+
+
+def run_alone(gp, seed, nsteps, every, tile, zchunk):
+    """One lattice run alone through ah_step / ah_measure: its fields after
+    nsteps and its diagnostics series (every `every` steps and the last)."""
+    import paper_2005_14454_amd as ah
+    series = []
+    with ah.Lattice(gp) as lat:
+        lat.set_step_config("tile", tile, zchunk)
+        lat.init(seed)
+        for k in range(nsteps + 1):
+            if k == nsteps or (every > 0 and k % every == 0):
+                series.append(lat.measure())
+            if k < nsteps:
+                lat.step(1)
+        return lat.get_state(), series

@@ -12,7 +12,7 @@
 import numpy as np
 import pytest
 
-from helpers import both_params, field_scaled_error
+from helpers import both_params, field_scaled_error, pool_tile, run_alone, same_record
 
 pytestmark = pytest.mark.gpu
 
@@ -21,34 +21,6 @@ pytestmark = pytest.mark.gpu
 def ah():
     import paper_2005_14454_amd as ah
     return ah
-
-
-def same_record(a, b):
-    """Bitwise equality of two measurement dicts (NaN equals NaN)."""
-    if a.keys() != b.keys():
-        return False
-    for k in a:
-        x, y = a[k], b[k]
-        if isinstance(x, float) and isinstance(y, float):
-            if not (x == y or (np.isnan(x) and np.isnan(y))):
-                return False
-        elif x != y:
-            return False
-    return True
-
-
-def _alone(ah, gp, seed, nsteps, every, tile, zchunk):
-    """Run one lattice alone: fields after nsteps and the diagnostics series."""
-    series = []
-    with ah.Lattice(gp) as lat:
-        lat.set_step_config("tile", tile, zchunk)
-        lat.init(seed)
-        for k in range(nsteps + 1):
-            if k == nsteps or (every > 0 and k % every == 0):
-                series.append(lat.measure())
-            if k < nsteps:
-                lat.step(1)
-        return lat.get_state(), series
 
 
 def test_pool_alone_vs_mix_bitwise(ah):
@@ -79,8 +51,7 @@ def test_pool_alone_vs_mix_bitwise(ah):
     # alone with the same tiling the diagnostics records are summed in the
     # same order
     for (p, seed, n, every), rid in zip(reqs, ids):
-        tile = (32, 8) if p.precision == "fp64" else (64, 8)
-        st, ser = _alone(ah, p, seed, n, every, tile, min(p.N, 64))
+        st, ser = run_alone(p, seed, n, every, pool_tile(p.precision), min(p.N, 64))
         assert np.array_equal(states[rid], st), (p, seed)
         assert len(series[rid]) == len(ser)
         for a, b in zip(series[rid], ser):
