@@ -41,11 +41,16 @@ def measured_traffic(precision, N, tile):
         return None
     real = "float" if precision == "fp32" else "double"
     name = f"k_step_tile<{real}, {tile[0]}, {tile[1]}, false>"
+    # one row per launch geometry; the autotuner's candidates have few
+    # dispatches, the benchmark's own configuration the most
+    best = None
     for line in text.splitlines():
         if line.startswith(name):
-            total_gb = float(line[len(name):].split()[4])
-            return total_gb * 1e9
-    return None
+            cols = line[len(name):].split()
+            n, total_gb = int(cols[6]), float(cols[4])
+            if best is None or n > best[0]:
+                best = (n, total_gb)
+    return best[1] * 1e9 if best else None
 BYTES_PER_SITE = {"fp32": 80, "fp64": 160}  # read 10 reals + write 10 reals per site-update
 
 

@@ -131,8 +131,9 @@ struct PoolLattice {
     double dx, deta, sigma2;
 };
 struct WorkItem {
-    int lattice, tile;
+    int lattice, tile;  // lattice < 0: an empty item (padding)
 };
+constexpr int kXcdCount = 8;           // XCDs of the device; block b runs on XCD b % 8
 constexpr int kSeriesStride = 16;      // M_COUNT sums + step index + pad
 
 // ---- launchers (ah_kernels.hip, ah_step_tile.hip) -------------------------

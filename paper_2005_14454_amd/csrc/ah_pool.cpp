@@ -198,16 +198,38 @@ int rebuild(ah_pool* P)
     for (int i = 0; i < nslot; ++i)
         if (P->slots[i].used)
             by_shape[{P->slots[i].p.precision, P->slots[i].cfg.tile_x, P->slots[i].cfg.tile_y}].push_back(i);
+    // The step kernels run one block per item and give XCD x (which runs
+    // blocks x, x+8, ...) the x-th eighth of the list.  So that every XCD
+    // gets an equal share of every lattice, with neighbouring tiles (which
+    // read each other's halo) in the same L2, each lattice's tiles, in index
+    // order, are cut into eight contiguous runs, run x goes to band x, bands
+    // list the lattices with the longest z-marches first and are padded to
+    // one length with empty items.
     for (auto& kv : by_shape) {
         Group g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), work.size(), 0};
-        for (int i : kv.second) {
+        std::vector<int> order = kv.second;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const PoolLattice &da = P->slots[a].d, &db = P->slots[b].d;
+            return std::min(da.zchunk, da.N) > std::min(db.zchunk, db.N);  // planes per item
+        });
+        std::vector<WorkItem> band[kXcdCount];
+        for (int i : order) {
             const PoolLattice& d = P->slots[i].d;
             const int tiles_z = (d.N + d.zchunk - 1) / d.zchunk;
             const int nt = d.tiles_x * d.tiles_y * tiles_z;
-            for (int t = 0; t < nt; ++t) work.push_back({i, t});
+            for (int x = 0; x < kXcdCount; ++x) {
+                const int t0 = (int)((int64_t)nt * x / kXcdCount), t1 = (int)((int64_t)nt * (x + 1) / kXcdCount);
+                for (int t = t0; t < t1; ++t) band[x].push_back({i, t});
+            }
+        }
+        size_t len = 0;
+        for (auto& b : band) len = std::max(len, b.size());
+        for (auto& b : band) {
+            b.resize(len, WorkItem{-1, 0});
+            work.insert(work.end(), b.begin(), b.end());
         }
         g.n = work.size() - g.off;
-        if (g.n) step_groups.push_back(g);
+        if (len) step_groups.push_back(g);
     }
     if (work.size() > P->work_cap) {
         if (P->d_work) (void)hipFree(P->d_work);

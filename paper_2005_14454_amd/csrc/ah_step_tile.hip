@@ -95,9 +95,8 @@ __device__ inline int wrapi(int v, int N)
 // to XCD b % 8) cover a contiguous range of tile indices.
 __device__ inline int xcd_tile(int b, int nb)
 {
-    constexpr int kXcd = 8;
-    const int per = nb / kXcd, rem = nb % kXcd;
-    const int xcd = b % kXcd, k = b / kXcd;
+    const int per = nb / kXcdCount, rem = nb % kXcdCount;
+    const int xcd = b % kXcdCount, k = b / kXcdCount;
     return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
@@ -744,11 +743,11 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(con
 {
     __shared__ TileShared<R, TX, TY> sh;
     __shared__ MeasShared<R, TX, MEAS ? TY : 8> mxs;
-    // one work item per block; each XCD gets a contiguous band of the list,
-    // which is ordered by lattice and then tile index, so neighbouring tiles
-    // share an L2
+    // one work item per block; XCD x gets the x-th eighth of the list (the
+    // host lays the list out so that this is an equal share of every lattice)
     const int w = xcd_tile(blockIdx.x, nwork);
     const WorkItem it = work[w];
+    if (it.lattice < 0) return;
     const PoolLattice& L = lat[it.lattice];
     const int64_t k = *L.counter;
     const bool due = measure_due(L, k);
