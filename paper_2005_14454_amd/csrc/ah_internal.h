@@ -90,14 +90,15 @@ inline bool tile_supported(int precision, int tx, int ty)
 // Smallest z-chunk the tiled kernels accept for a lattice of side N.
 inline int min_zchunk(int N) { return N < 8 ? N : 8; }
 
-// Replace a tile shape whose measured march would spill registers by the
-// fastest one that does not (FP32: 1024-thread tiles -> 64 x 8; FP64:
-// 512-thread tiles -> 32 x 8).  Returns whether it changed.
+// Tile shape for the measured march of a lattice stepped on (tx, ty): FP32
+// always 64 x 8, the fastest measured march (the 1024-thread shapes would
+// spill registers); FP64 32 x 8 in place of the 512-thread shapes, whose
+// measured march spills.  Returns whether it changed.
 inline bool measured_tile(int precision, int* tx, int* ty)
 {
     const int nt = *tx * *ty;
     int mx = *tx, my = *ty;
-    if (precision == AH_FP32 && nt == 1024) {
+    if (precision == AH_FP32) {
         mx = 64;
         my = 8;
     } else if (precision == AH_FP64 && nt == 512) {

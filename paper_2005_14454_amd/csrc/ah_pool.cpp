@@ -350,7 +350,10 @@ static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why
     // keeps its registers: FP32 1024-thread tiles are halved in y, FP64
     // 512-thread tiles become 32 x 8
     if (p.precision == AH_FP32 && cfg->tile_x * cfg->tile_y == 1024) cfg->tile_y /= 2;
-    if (p.precision == AH_FP64) (void)measured_tile(p.precision, &cfg->tile_x, &cfg->tile_y);
+    if (p.precision == AH_FP64 && cfg->tile_x * cfg->tile_y == 512) {
+        cfg->tile_x = 32;
+        cfg->tile_y = 8;
+    }
     int zc = cfg->zchunk < 64 ? 64 : cfg->zchunk;
     if (zc > p.N) zc = p.N;
     cfg->zchunk = zc;

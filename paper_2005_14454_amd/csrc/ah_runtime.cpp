@@ -382,11 +382,9 @@ MeasConst meas_const(const ah_params& p, int64_t n)
 // Tile configuration used for the diagnostics of a compact-action handle:
 // the step's own when the step is tiled, the default tile otherwise.
 // Tile of the measured march.  Any tile shape computes the same fields bit
-// for bit, so the measured step may use another shape than the plain one: the
-// step's own, unless its measured march would spill registers (FP32
-// 1024-thread tiles, FP64 512-thread tiles), in which case
-// the fastest shape that does not (FP32 64 x 8, FP64 32 x 8), with the
-// automatic z-chunk of that shape.  The site kernel's lattices (and
+// for bit, so the measured step may use another shape than the plain one
+// (measured_tile: FP32 64 x 8, FP64 32 x 8 in place of the 512-thread
+// shapes), with the automatic z-chunk of that shape when it differs.  The site kernel's lattices (and
 // ah_measure on them) use the automatic tile configuration.
 TileConfig meas_tiles(const ah_handle* h)
 {
