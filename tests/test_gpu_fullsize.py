@@ -100,3 +100,39 @@ def test_fullsize_1024_matter_era_switch_sampled(oracle_mod):
     assert max(err.values()) <= 2e-6, err
     assert meas["nonfinite"] == 0 and meas["step"] == 6
     assert meas["winding_sum_abs"] > 0
+
+
+def test_512_fp32_against_fp64_over_the_run():
+    """512^3, radiation era, seed 1: the FP32 step against the FP64 step (whose
+    parity with the oracle the tests above establish) after 100 steps, field
+    by field over the whole lattice, within 1e-4 of each field's scale; then
+    both to 1280 steps (eta = 129, half a light crossing) with the diagnostics
+    at the end: Gauss's law holds to FP64 round-off on the FP64 lattice and to
+    FP32 round-off on the FP32 one, and the two string lengths agree."""
+    import paper_2005_14454_amd as ah
+    lats = {prec: ah.Lattice(ah.Params(N=N, precision=prec, m=1.0)) for prec in ("fp32", "fp64")}
+    try:
+        for lat in lats.values():
+            lat.init(1)
+            lat.step(100)
+        s64 = lats["fp64"].get_state()
+        s32 = lats["fp32"].get_state()
+        err = field_scaled_error(s32, s64)
+        del s32, s64
+        print("512^3 FP32 vs FP64 after 100 steps", err)
+        assert max(err.values()) <= 1e-4, err
+        end = {}
+        for prec, lat in lats.items():
+            lat.step(1180)
+            end[prec] = lat.measure()
+    finally:
+        for lat in lats.values():
+            lat.close()
+    m32, m64 = end["fp32"], end["fp64"]
+    ratio = m32["L_W"] / m64["L_W"]
+    print("512^3 at step 1280: gauss_rel fp64 %.3e fp32 %.3e, L_W fp32/fp64 = %.5f (L_W fp64 %.1f)"
+          % (m64["gauss_rel"], m32["gauss_rel"], ratio, m64["L_W"]))
+    assert m64["step"] == m32["step"] == 1280
+    assert m64["nonfinite"] == 0 and m32["nonfinite"] == 0
+    assert m64["gauss_rel"] < 1e-12 and m32["gauss_rel"] < 1e-4
+    assert m64["L_W"] > 0 and abs(ratio - 1.0) < 0.05
