@@ -90,21 +90,13 @@ inline bool tile_supported(int precision, int tx, int ty)
 // Smallest z-chunk the tiled kernels accept for a lattice of side N.
 inline int min_zchunk(int N) { return N < 8 ? N : 8; }
 
-// Tile shape for the measured march of a lattice stepped on (tx, ty): FP32
-// always 64 x 8, the fastest measured march (the 1024-thread shapes would
-// spill registers); FP64 32 x 8 in place of the 512-thread shapes, whose
-// measured march spills.  Returns whether it changed.
+// Tile shape for the measured march of a lattice stepped on (tx, ty): the
+// fastest measured march, FP32 64 x 8 and FP64 32 x 8 (the 1024-thread FP32
+// and 512-thread FP64 shapes would spill registers).  Returns whether it
+// changed.
 inline bool measured_tile(int precision, int* tx, int* ty)
 {
-    const int nt = *tx * *ty;
-    int mx = *tx, my = *ty;
-    if (precision == AH_FP32) {
-        mx = 64;
-        my = 8;
-    } else if (precision == AH_FP64 && nt == 512) {
-        mx = 32;
-        my = 8;
-    }
+    const int mx = precision == AH_FP64 ? 32 : 64, my = 8;
     const bool changed = mx != *tx || my != *ty;
     *tx = mx;
     *ty = my;

@@ -347,13 +347,10 @@ static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why
     const int rc = resolve_step_config(p, t, cfg, why);
     if (rc != AH_OK) return rc;
     // one tile shape serves both nodes, so it must be one whose measured march
-    // keeps its registers: FP32 1024-thread tiles are halved in y, FP64
-    // 512-thread tiles become 32 x 8
+    // keeps its registers: FP32 1024-thread tiles are halved in y, FP64 runs
+    // on 32 x 8 (as fast as any FP64 shape for the plain step)
     if (p.precision == AH_FP32 && cfg->tile_x * cfg->tile_y == 1024) cfg->tile_y /= 2;
-    if (p.precision == AH_FP64 && cfg->tile_x * cfg->tile_y == 512) {
-        cfg->tile_x = 32;
-        cfg->tile_y = 8;
-    }
+    if (p.precision == AH_FP64) (void)measured_tile(p.precision, &cfg->tile_x, &cfg->tile_y);
     int zc = cfg->zchunk < 64 ? 64 : cfg->zchunk;
     if (zc > p.N) zc = p.N;
     cfg->zchunk = zc;

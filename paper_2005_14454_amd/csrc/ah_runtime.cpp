@@ -383,8 +383,8 @@ MeasConst meas_const(const ah_params& p, int64_t n)
 // the step's own when the step is tiled, the default tile otherwise.
 // Tile of the measured march.  Any tile shape computes the same fields bit
 // for bit, so the measured step may use another shape than the plain one
-// (measured_tile: FP32 64 x 8, FP64 32 x 8 in place of the 512-thread
-// shapes), with the automatic z-chunk of that shape when it differs.  The site kernel's lattices (and
+// (measured_tile: FP32 64 x 8, FP64 32 x 8), with the automatic z-chunk of
+// that shape when it differs from the step's.  The site kernel's lattices (and
 // ah_measure on them) use the automatic tile configuration.
 TileConfig meas_tiles(const ah_handle* h)
 {

@@ -143,6 +143,9 @@ struct MeasShared {
     static constexpr int RS = (TX + 2) * (TY + 2);
     R A[2][3][RS];                      // stored A of the link planes held in the U ring
     float Y[2][3][RS];                  // link phases of planes z (ring of two)
+    // FP64 lattices: each thread's running diagnostics sums (kept here rather
+    // than in registers, which the FP64 measured march runs out of)
+    double acc[8][sizeof(R) == 8 ? TX * TY : 1];
     double red[TX * TY / 64][M_COUNT];  // block reduction
 };
 
@@ -154,10 +157,35 @@ __device__ inline Cx<double> link64(double dx, double a)
     return {c, -s};
 }
 
+// atan2(y, x) in FP32 to within 1e-6 rad for max(|x|, |y|) in [1e-30, 1e30]:
+// reduction to t = min(|x|, |y|) / max(|x|, |y|) in [0, 1], atan(t) ~ t P(t^2)
+// with P of degree 6 fitted by weighted least squares on Chebyshev nodes
+// (largest error 3.3e-7 in FP32 over [0, 1]), then the octant and the sign.
+// Only the angle of a branch the caller has already made safe is taken from
+// it; the cut itself is decided in FP64.
+__device__ inline float atan2_fast(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay));
+    const float s = t * t;
+    float p = 0.00681175384670496f;
+    p = fm(p, s, -0.033604107797145844f);
+    p = fm(p, s, 0.07962355017662048f);
+    p = fm(p, s, -0.13233335316181183f);
+    p = fm(p, s, 0.19807814061641693f);
+    p = fm(p, s, -0.3331736922264099f);
+    p = fm(p, s, 0.9999961256980896f);
+    float a = p * t;
+    if (ay > ax) a = 1.57079632679489662f - a;
+    if (x < 0.f) a = 3.14159265358979324f - a;
+    return copysignf(a, y);
+}
+
 // Link phase arg(conj(phi^x) U phi^{x+j}) in (-pi, pi].  z is formed in FP64
 // with plain products and sums; its sign decides the branch exactly as an
-// FP64 atan2 would (-0 -> +0), and the angle itself is evaluated in FP32 on the
-// exactly rescaled z: the windings only need it to well below pi.
+// FP64 atan2 would (-0 -> +0; atan2_fast keeps the sign of its first
+// argument), and the angle itself is evaluated in FP32 on the exactly
+// rescaled z: the windings only need it to well below pi.
 __device__ inline float link_phase(double pr, double pim, Cx<double> U, double vr, double vi)
 {
     const double wr = U.r * vr - U.i * vi;
@@ -168,7 +196,7 @@ __device__ inline float link_phase(double pr, double pim, Cx<double> U, double v
     const double mz = fmax(fabs(zr), fabs(zi));
     if (mz == 0.0) return signbit(zr) ? 3.14159265358979f : 0.0f;
     const int e = ilogb(mz);
-    return atan2f((float)ldexp(zi, -e), (float)ldexp(zr, -e));
+    return atan2_fast((float)ldexp(zi, -e), (float)ldexp(zr, -e));
 }
 
 // The FP64 evaluation for an FP32 lattice's link near the cut.  It runs for a
@@ -182,17 +210,20 @@ __device__ __attribute__((noinline)) float link_phase_near_cut(Cx<float> ph, Cx<
 // Link phase of an FP32 lattice from z = conj(ph) (U pn), formed in FP32 from
 // the link the step itself uses; its angle, taken in FP32, is within
 //   |dx A| 2^-22 (rounding of dx A, in the link's phase)
-//   + 1e-5        (sincosf, the two complex products, atan2f; all a few ulp)
+//   + 1e-5        (sincosf, the two complex products, atan2_fast)
 // of the FP64 value, so unless it lies that close to the cut at +-pi it is on
-// the same side of it.  Near the cut, and where |z| leaves the range in which
-// FP32 keeps its relative precision (or is not finite), the FP64 evaluation
-// above decides from the stored A.
+// the same side of it.  Near the cut, where |z| leaves the range in which
+// FP32 keeps its relative precision (or is not finite), and where |dx A|
+// exceeds 1e5 (so that four phases stay well within pi of the FP64 sum), the
+// FP64 evaluation above decides from the stored A.
 __device__ inline float link_phase_f(Cx<float> z, Cx<float> ph, Cx<float> pn, float a, double dx)
 {
-    const float y = atan2f(z.i, z.r);
     const float mz = fmaxf(fabsf(z.r), fabsf(z.i));
-    const float tol = 1e-5f + 2.4e-7f * fabsf((float)dx * a);
-    if (mz > 1e-30f && mz < 1e30f && 3.14159265f - fabsf(y) > tol) return y;
+    const float dxa = fabsf((float)dx * a);
+    if (mz > 1e-30f && mz < 1e30f && dxa < 1e5f) {
+        const float y = atan2_fast(z.i, z.r);
+        if (3.14159265f - fabsf(y) > 1e-5f + 2.4e-7f * dxa) return y;
+    }
     return link_phase_near_cut(ph, pn, a, dx);
 }
 
@@ -329,10 +360,16 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     };
     // sums of the march: M_KIN .. M_GRADL (8 slots, FP64) and the exact
     // counts M_WABS, M_NONFIN (integers); the Gauss slots belong to k_gauss
-    double acc[8];
+    double acc_reg[8];
+    auto acc = [&](int k) -> double& {
+        if constexpr (sizeof(R) == 8)
+            return mx->acc[k][tid];
+        else
+            return acc_reg[k];
+    };
     int wabs = 0, nonfin = 0;
     if constexpr (MEAS)
-        for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+        for (int k = 0; k < 8; ++k) acc(k) = 0.0;
     {
         const int64_t pm = plane_of(z0 - 1), p0 = plane_of(z0);
         const R* A[3] = {f.a0, f.a1, f.a2};
@@ -390,11 +427,13 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     // of plane t+1 (halo) and t+2 (own), Pi and E of plane t+1 (own).  The
     // plain march loads them one iteration ahead.  The measured march of FP32
     // lattices holds fewer waves per SIMD (it needs more registers), so it
-    // loads them two iterations ahead to keep as many loads in flight (FP64
-    // has no registers to spare for that); it loads every iteration's
-    // operands, the last ones of a chunk from wrapped planes that it does not
-    // use.
+    // loads them two iterations ahead to keep as many loads in flight; it
+    // loads every iteration's operands, the last ones of a chunk from wrapped
+    // planes that it does not use.  The FP64 measured march has no registers
+    // to hold them across the plane's arithmetic and loads them (LATE) just
+    // before they are used, which keeps it at two waves per SIMD.
     constexpr bool D2 = MEAS && sizeof(R) == 4;
+    constexpr bool LATE = MEAS && sizeof(R) == 8;
     struct Pre {
         R a[3], ha[3];
         Cx<R> hphi, phi2;
@@ -430,7 +469,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         //         iterations (q1 holds those of this one)
         if constexpr (D2)
             prefetch(z + 1, q2);
-        else if (more || MEAS)
+        else if (!LATE && more)
             prefetch(z, q1);
         const R* rA = q1.a;
         const R* hA = q1.ha;
@@ -567,14 +606,14 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                     const double el = (double)(eb0 * eb0 + eb1 * eb1 + eb2 * eb2) * ma.inv_2e2f;
                     const double mag = (double)(R(2) * (oxy + oxz + oyz) * (inv_dx2 * inv_dx2)) * ma.inv_2e2f;
                     const double L = kin - grad - pot_e + el - mag;
-                    acc[M_KIN] += kin;
-                    acc[M_GRAD] += grad;
-                    acc[M_POT] += pot_e;
-                    acc[M_EL] += el;
-                    acc[M_MAG] += mag;
-                    acc[M_L] += L;
-                    acc[M_KINL] += kin * L;
-                    acc[M_GRADL] += grad * L;
+                    acc(M_KIN) += kin;
+                    acc(M_GRAD) += grad;
+                    acc(M_POT) += pot_e;
+                    acc(M_EL) += el;
+                    acc(M_MAG) += mag;
+                    acc(M_L) += L;
+                    acc(M_KINL) += kin * L;
+                    acc(M_GRADL) += grad * L;
                 }
             }
             fxz_m = fxz;
@@ -594,6 +633,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             yz_b = yz_c;
         }
 
+        if constexpr (LATE) prefetch(z, q1);
         // ---- 3. plane z+2 links into slot cur, plane z+1 phi into sPhi
         Cx<R> Upp[3];
         if (more) {
@@ -656,7 +696,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         auto& red = mx->red;
         const int lane = tid & 63, wv = tid >> 6;
         for (int k = 0; k < 8; ++k) {
-            const double r = wave_sum(acc[k]);
+            const double r = wave_sum(acc(k));
             if (lane == 0) red[wv][k] = r;
         }
         const double rw = wave_sum((double)wabs), rn = wave_sum((double)nonfin);
@@ -680,10 +720,20 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
 // fits in 128 registers, i.e. four waves per SIMD: two 512-thread workgroups
 // per CU, so one can load while the other waits at a barrier.  Left to itself
 // the compiler may take a few more registers, which drops a 512-thread tile
-// to one workgroup per CU.  The measured march and FP64 need more registers
-// and are left free.
+// to one workgroup per CU.  FP64 fits two waves per SIMD (its measured march
+// only with its sums in LDS and its loads issued late, spilling a few
+// registers); the FP32 measured march needs more than 128 and is left free.
 template <typename R, bool MEAS>
-constexpr int kMinWaves = (!MEAS && sizeof(R) == 4) ? 4 : 1;
+constexpr int kMinWaves = sizeof(R) == 8 ? 2 : (MEAS ? 1 : 4);
+
+// Tile shapes with a measured instance: the 1024-thread FP32 and 512-thread
+// FP64 shapes would spill (or overflow LDS); lattices are measured on 64 x 8
+// (FP32) and 32 x 8 (FP64) tiles.
+template <typename R>
+constexpr bool has_measured(int tx, int ty)
+{
+    return tx * ty <= (sizeof(R) == 8 ? 256 : 512);
+}
 
 // One lattice: block b owns tile t = xcd_tile(b) (tx fastest, then ty, then
 // z-chunk); with MEAS it writes diagnostics record t, so the records are in
@@ -924,9 +974,7 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
         ma.gauss_c = mc->gauss_c;
     }
     const int zc = tc.zchunk > 0 ? tc.zchunk : N;
-    // MEASv: whether the shape has a measured instance (1024-thread tiles have
-    // none: their measured march would spill, and the runtime measures them
-    // on a 512-thread shape)
+    // MEASv: whether the shape has a measured instance
 #define AH_TILE_CASE(TXv, TYv, MEASv)                                                                              \
     if (tc.tx == TXv && tc.ty == TYv) {                                                                            \
         const int tiles_x = (N + TXv - 1) / TXv, tiles_y = (N + TYv - 1) / TYv;                                   \
@@ -942,10 +990,10 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
         }                                                                                                          \
         return hipGetLastError();                                                                                 \
     }
-    AH_TILE_CASE(64, 8, true)
-    AH_TILE_CASE(64, 4, true)
-    AH_TILE_CASE(32, 8, true)
-    AH_TILE_CASE(128, 4, true)
+    AH_TILE_CASE(64, 8, has_measured<R>(64, 8))
+    AH_TILE_CASE(64, 4, has_measured<R>(64, 4))
+    AH_TILE_CASE(32, 8, has_measured<R>(32, 8))
+    AH_TILE_CASE(128, 4, has_measured<R>(128, 4))
     if constexpr (sizeof(R) == 4) {
         AH_TILE_CASE(64, 16, false)
         AH_TILE_CASE(128, 8, false)
@@ -964,13 +1012,19 @@ template <typename R>
 hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,
                              bool measured, hipStream_t s)
 {
+    // a pool tile shape serves both nodes, so only shapes with a measured
+    // instance are built
 #define AH_BATCH_CASE(TXv, TYv)                                                                                      \
-    if (tx == TXv && ty == TYv) {                                                                                    \
-        if (measured)                                                                                                \
-            hipLaunchKernelGGL((k_step_batch<R, TXv, TYv, true>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work, nwork); \
-        else                                                                                                         \
-            hipLaunchKernelGGL((k_step_batch<R, TXv, TYv, false>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work, nwork); \
-        return hipGetLastError();                                                                                   \
+    if constexpr (has_measured<R>(TXv, TYv)) {                                                                       \
+        if (tx == TXv && ty == TYv) {                                                                                \
+            if (measured)                                                                                            \
+                hipLaunchKernelGGL((k_step_batch<R, TXv, TYv, true>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work,  \
+                                   nwork);                                                                           \
+            else                                                                                                     \
+                hipLaunchKernelGGL((k_step_batch<R, TXv, TYv, false>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work, \
+                                   nwork);                                                                           \
+            return hipGetLastError();                                                                                \
+        }                                                                                                            \
     }
     AH_BATCH_CASE(64, 8)
     AH_BATCH_CASE(64, 4)
