@@ -471,9 +471,17 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             prefetch(z + 1, q2);
         else if (!LATE && more)
             prefetch(z, q1);
-        const R* rA = q1.a;
+        const R* rA = q1.a;  // read at step 3, after the late loads
         const R* hA = q1.ha;
-        const Cx<R> hphi = q1.hphi;
+        Cx<R> hphi = q1.hphi;
+        if constexpr (LATE) {
+            // the halo phi of plane z+1 is needed before the late loads (by the
+            // halo link phases of this plane), so it is loaded here
+            if (has_halo) {
+                const int64_t p1 = plane_of(z + 1);
+                hphi = Cx<R>{f.phr[p1 + halo_xy], f.phi[p1 + halo_xy]};
+            }
+        }
         const Cx<R> rphi = phi_p;
         float yx_c = 0.f, yy_c = 0.f, yz_c = 0.f;
         double th_xy = 0.0;
