@@ -226,7 +226,9 @@ int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double*
 /* Recorded choice for (p->precision, p->N); AH_E_AGAIN if none. */
 int ah_tune_lookup(const ah_params* p, ah_step_config* out);
 
-/* Record a choice by hand (kernel must be AH_KERNEL_TILE). */
+/* Record a choice by hand: kernel AH_KERNEL_TILE, a tile shape supported
+ * for the precision, zchunk 0 (automatic) or >= min(8, N); AH_E_INVAL
+ * otherwise. */
 int ah_tune_set(const ah_params* p, const ah_step_config* c);
 
 /* Forget every recorded choice. */
@@ -235,7 +237,8 @@ int ah_tune_clear(void);
 /* Save / load the tuning table as JSON (one entry per line:
  * {"precision": "fp32", "N": 128, "tile_x": 64, "tile_y": 8, "zchunk": 32, "ms": 0.01}).
  * Loading adds to (and overrides entries of) the table.  AH_E_INVAL if the
- * file cannot be opened. */
+ * file cannot be opened or holds an entry that does not parse or that
+ * ah_tune_set would refuse; the table is then unchanged. */
 int ah_tune_save(const char* path);
 int ah_tune_load(const char* path);
 
@@ -245,11 +248,13 @@ int ah_tune_load(const char* path);
  * active ones together: each ah_pool_advance step is one replay of a HIP
  * graph holding the diagnostics pass of the lattices whose snapshot is due,
  * its fixed-order fold, the tiled step of every active lattice (one kernel
- * node per precision and tile shape, blocks striding over a work list of
- * (lattice, tile) items) and a counter update.  Every lattice takes the
- * coefficients of its own step from its own FP64 table, so its fields and
- * diagnostics are bitwise identical to the same lattice run alone through
- * ah_step with the same tile shape.  Requests enter and leave between
+ * node per precision and tile shape, one block per (lattice, tile) work
+ * item) and a counter update.  Pool lattices run the tuned (else default)
+ * tile shape with FP32 1024-thread shapes halved in y and FP64 on 32 x 8,
+ * and z-chunks of at least 64 planes.  Every lattice takes the coefficients
+ * of its own step from its own FP64 table, so its fields and diagnostics are
+ * bitwise identical to the same lattice run alone through ah_step /
+ * ah_measure with the same tiling.  Requests enter and leave between
  * advances (continuous batching); the graph is rebuilt when the set changes.
  * A pool is used from one host thread at a time. */
 typedef struct ah_pool ah_pool;
