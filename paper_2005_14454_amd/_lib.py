@@ -76,6 +76,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is not built: run paper_2005_14454_amd.build.build() "
                            "(or __graft_entry__.build()) first")
+    # torch ships its own HIP runtime under the same soname as the system one
+    # libah.so links against; whichever is loaded first serves the whole
+    # process.  Importing torch first makes it torch's, the runtime that owns
+    # the device memory and streams handed to the library (loading the system
+    # one first leaves torch on a runtime it was not built with, and device
+    # calls then fail).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp = ctypes.c_void_p

@@ -121,3 +121,24 @@ def test_pool_staggered_completion_and_progress(ah):
         assert [m["step"] for m in ser] == [0, 2, 4, 5]
         for rid in ids:
             assert len(pool.results(rid)) == 1
+
+
+def test_pool_after_host_only_calls_in_a_fresh_process():
+    """Host-only calls made before anything touches the GPU (a footprint)
+    still leave the process able to create and run a pool: the library loads
+    the HIP runtime that torch uses, whatever is called first."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import paper_2005_14454_amd as ah\n"
+            "p = ah.Params(N=16)\n"
+            "fp = ah.pool_footprint(p, 4, 2)\n"
+            "with ah.Pool(4 * fp, 2) as pool:\n"
+            "    rid = pool.submit(p, 1, 4, 2)\n"
+            "    pool.advance(5)\n"
+            "    assert pool.poll() == [rid]\n"
+            "    assert [m['step'] for m in pool.results(rid)] == [0, 2, 4]\n"
+            "print('ok', flush=True)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stderr[-3000:]
