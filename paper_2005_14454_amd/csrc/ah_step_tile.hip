@@ -498,9 +498,6 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         }
 
         // ---- 1. update of the own site at plane z
-        R fxz_w = 0, fyz_w = 0;  // own plaquette sines (diagnostics reuse)
-        (void)fxz_w;
-        (void)fyz_w;
         {
             const Cx<R> ph_xm = sPhi[rxm], ph_xp = sPhi[rxp], ph_ym = sPhi[rym], ph_yp = sPhi[ryp];
             const Cx<R> ux_xm = sU[cur][0][rxm];  // U_x^{x-kx}

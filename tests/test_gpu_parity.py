@@ -124,6 +124,28 @@ def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference, kernel):
         assert np.array_equal(lat.winding(), oracle_mod.winding(op, got).astype(np.int8))
 
 
+def test_config0_series_fp64_fused(oracle_mod, ah):
+    """64^3 FP64 radiation era, seed 0, 160 steps with the diagnostics every 10
+    steps formed in the same pass as the step (ah_step_measured): every record
+    against the oracle's diagnostics of its own snapshot at that step."""
+    op, gp = both_params(oracle_mod, 64, "fp64", m=1.0)
+    with ah.Lattice(gp) as lat:
+        lat.init(0)
+        series = lat.step_measured(160, 10) + [lat.measure()]
+    assert [m["step"] for m in series] == list(range(0, 161, 10))
+    st = oracle_mod.init(op, 0)
+    for k, gm in enumerate(series):
+        n = 10 * k
+        if n > 0:
+            st = oracle_mod.step(op, st, n - 10, 10)
+        om = oracle_mod.measure(op, st, n)
+        assert gm["winding_sum_abs"] == om["winding_sum_abs"], n
+        for key in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag", "sum_L", "R"):
+            assert abs(gm[key] - om[key]) <= 1e-9 * abs(om[key]) + 1e-12, (n, key, gm[key], om[key])
+        assert gm["gauss_rel"] < 1e-12 and om["gauss_rel"] < 1e-12, n
+        assert gm["nonfinite"] == 0 and gm["flags"] == 0
+
+
 @pytest.mark.parametrize("kernel", ["site", "tile"])
 def test_config1_fp32_100_steps(oracle_mod, ah, config1_reference, kernel):
     op, ic, ref = config1_reference
