@@ -731,13 +731,15 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
 template <typename R, bool MEAS>
 constexpr int kMinWaves = sizeof(R) == 8 ? 2 : (MEAS ? 1 : 4);
 
-// Tile shapes with a measured instance: the 1024-thread FP32 and 512-thread
-// FP64 shapes would spill (or overflow LDS); lattices are measured on 64 x 8
-// (FP32) and 32 x 8 (FP64) tiles.
+// Tile shapes with a measured instance.  Lattices are measured on 64 x 8
+// (FP32) and 32 x 8 (FP64) tiles; pool lattices, whose one shape serves both
+// nodes, run FP32 shapes of up to 512 threads and FP64 on 32 x 8.  (The
+// 1024-thread FP32 shapes would spill; the FP64 measured march fits two
+// waves per SIMD only on 32 x 8.)
 template <typename R>
 constexpr bool has_measured(int tx, int ty)
 {
-    return tx * ty <= (sizeof(R) == 8 ? 256 : 512);
+    return sizeof(R) == 8 ? (tx == 32 && ty == 8) : tx * ty <= 512;
 }
 
 // One lattice: block b owns tile t = xcd_tile(b) (tx fastest, then ty, then
