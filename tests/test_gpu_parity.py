@@ -68,6 +68,24 @@ def test_one_step_fp64(oracle_mod, ah, N, m, s, kernel):
     assert max(err.values()) <= 1e-13, err
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_core_growth_negative_s(oracle_mod, ah, precision, tol):
+    """s = -1 (the cores grow with a, the paper's option for resolving them
+    early) switching to s = 1 at eta = 3, radiation era, 40 steps from the
+    random-phase IC, against the oracle."""
+    N = 24
+    op, gp = both_params(oracle_mod, N, precision, m=1.0, s_early=-1.0, s_late=1.0, eta_switch=3.0, eta_ref=2.0)
+    ic = oracle_mod.init(op, 9)
+    with ah.Lattice(gp) as lat:
+        lat.set_state(ic, 0)
+        lat.step(40)
+        got = lat.get_state()
+    ref = oracle_mod.step(op, ic, 0, 40)
+    err = field_scaled_error(got, ref)
+    print("core growth", precision, err)
+    assert max(err.values()) <= tol, err
+
+
 @pytest.mark.parametrize("gauge", ["compact", "noncompact"])
 def test_one_step_gauge_actions(oracle_mod, ah, gauge):
     N = 12

@@ -206,20 +206,22 @@ def test_hubble_damping_telescopes(oracle_mod, m):
     assert np.all(out[7] == 0.4)
 
 
-def test_homogeneous_mode_reduces_to_scalar_recurrence(oracle_mod):
+@pytest.mark.parametrize("m,s,eta_ref", [(2.0, 1.0, 5.0), (1.0, -1.0, 2.0)])
+def test_homogeneous_mode_reduces_to_scalar_recurrence(oracle_mod, m, s, eta_ref):
     """Uniform real phi with A = E = 0: every stencil term cancels and the lattice
     update is the one-site recurrence of a damped anharmonic oscillator whose
-    coupling grows as f_n = a_n^{2s}."""
+    coupling scales as f_n = a_n^{2s} (s = 1: the true equations; s = -1: the
+    cores grow as a does)."""
     N = 4
-    p = oracle_mod.params(N=N, m=2.0, s_early=1.0, s_late=1.0, eta_ref=5.0, sigma=1.0, lambda0=2.0)
+    p = oracle_mod.params(N=N, m=m, s_early=s, s_late=s, eta_ref=eta_ref, sigma=1.0, lambda0=2.0)
     st = np.zeros((10, N ** 3))
     st[0], st[2] = 0.4, 0.1
     out = oracle_mod.step(p, st, 0, 80)
     ph, pi = 0.4, 0.1
     for n in range(80):
         eta = 1.0 + 0.1 * n
-        f = ((eta / 5.0) ** 2) ** 2
-        d = 2.0 * 0.1 / eta
+        f = ((eta / eta_ref) ** m) ** (2 * s)
+        d = m * 0.1 / eta
         pi = ((1 - d) * pi + 0.1 * (-(2.0 * f / 2.0) * (ph * ph - 1.0) * ph)) / (1 + d)
         ph = ph + 0.1 * pi
     assert abs(out[0, 17] - ph) < 1e-13 and abs(out[2, 17] - pi) < 1e-13
