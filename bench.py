@@ -128,20 +128,21 @@ def single_rate(N, precision="fp32", steps=10):
     return N ** 3 * n / (ms / 1e3)
 
 
-def batched_ensemble(nlat=64, measure_every=20, chunk=16):
-    """64 independent FP32 lattices, N uniform on {64, 96, 128, 192, 256}, m on
-    {1, 2} (PCG64 seed 4), seeds 100..163, s = 0, each to eta = dx N / 2, in one
-    pool: one graph replay per step advances every unfinished lattice; tile
-    shape and z-chunk autotuned per size class.  Reported beside the same 64
-    lattices run one after another through the single-lattice path (each with
-    its own launches, same diagnostics cadence)."""
+def batched_ensemble(sizes=(64, 96, 128, 192, 256), nlat=64, rng_seed=4, measure_every=20, chunk=16):
+    """nlat independent FP32 lattices, N uniform on `sizes`, m on {1, 2}
+    (PCG64 rng_seed), seeds 100.., s = 0, each to eta = dx N / 2, in one pool:
+    one graph replay per step advances every unfinished lattice; tile shape
+    and z-chunk per size class from the tuning table (or autotuned).  Reported
+    beside the same lattices run one after another through the single-lattice
+    path (each with its own launches, same diagnostics cadence); both sides
+    time the stepping only (allocation and initial conditions outside)."""
     import numpy as np
     import torch
     import paper_2005_14454_amd as ah
     from paper_2005_14454_amd.serve import steps_to_half_light_crossing
 
-    rng = np.random.default_rng(4)
-    Ns = [int(v) for v in rng.choice([64, 96, 128, 192, 256], nlat)]
+    rng = np.random.default_rng(rng_seed)
+    Ns = [int(v) for v in rng.choice(list(sizes), nlat)]
     ms = [float(v) for v in rng.choice([1.0, 2.0], nlat)]
     tuned = {}
     for N in sorted(set(Ns)):
@@ -169,19 +170,20 @@ def batched_ensemble(nlat=64, measure_every=20, chunk=16):
     # the same lattices one after another through the single-lattice path,
     # with the same diagnostics cadence (fused into the step) and final record
     rate = {N: single_rate(N) for N in sorted(set(Ns))}
-    torch.cuda.synchronize()
-    s0 = time.perf_counter()
+    sequential_s = 0.0
     for p, seed, n in reqs:
         with ah.Lattice(p) as lat:
             lat.init(seed)
+            lat.synchronize()
+            s0 = time.perf_counter()
             lat.step_measured(n, measure_every)
             lat.measure()
-    torch.cuda.synchronize()
-    sequential_s = time.perf_counter() - s0
+            lat.synchronize()
+            sequential_s += time.perf_counter() - s0
     sec = t1 - t0
-    return {"lattices": nlat, "site_updates": su, "wall_s": sec, "value": su / sec, "unit": "site-updates/s",
-            "graph_replays": steps, "sequential_wall_s": sequential_s, "sequential_value": su / sequential_s,
-            "speedup_vs_sequential": sequential_s / sec,
+    return {"lattices": nlat, "sizes": list(sizes), "site_updates": su, "wall_s": sec, "value": su / sec,
+            "unit": "site-updates/s", "graph_replays": steps, "sequential_wall_s": sequential_s,
+            "sequential_value": su / sequential_s, "speedup_vs_sequential": sequential_s / sec,
             "tuned": {str(k): v for k, v in tuned.items()},
             "single_lattice_su_per_s": {str(k): v for k, v in rate.items()},
             "nonfinite": sum(m["nonfinite"] for m in finals)}
@@ -273,6 +275,11 @@ def main():
     if batched:
         print(f"# batched: {batched['value']:.4e} su/s over {batched['lattices']} lattices, "
               f"{batched['speedup_vs_sequential']:.2f}x vs sequential", file=sys.stderr, flush=True)
+    # many small lattices, where the single-lattice path is launch-bound
+    batched_small = None if args.no_batched else batched_ensemble((32, 48, 64), nlat=128, rng_seed=6)
+    if batched_small:
+        print(f"# batched small: {batched_small['value']:.4e} su/s over {batched_small['lattices']} lattices, "
+              f"{batched_small['speedup_vs_sequential']:.2f}x vs sequential", file=sys.stderr, flush=True)
     serv = None if args.no_served else served(args.served_requests, capacity_su=fp32["value"])
     if serv:
         print(f"# served: {serv['throughput_su_per_s']:.4e} su/s, p50 {serv['ttc_p50_s']:.2f} s, "
@@ -300,6 +307,7 @@ def main():
         "cpu_baseline": cpu,
         "hbm_copy_probe": probe,
         "batched": batched,
+        "batched_small": batched_small,
         "served": serv,
         "fp64": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
                                            "roofline": fp64["roofline"], "dtype": "f64", "tuned": fp64["tuned"]},
