@@ -256,7 +256,7 @@ def main():
     ap.add_argument("--served-requests", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the lattice path runs on one GPU (asked for --gpus {args.gpus}); "
               "the lattice is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
