@@ -15,6 +15,16 @@ from inputs import sample_sites
 
 pytestmark = pytest.mark.gpu
 
+
+@pytest.fixture(autouse=True)
+def _release_cached_device_memory():
+    """The lattices here take 8-132 GB each; hand torch's cached blocks back
+    to the device between tests so that they never add up."""
+    import torch
+    torch.cuda.empty_cache()
+    yield
+    torch.cuda.empty_cache()
+
 N = 512
 
 
@@ -163,3 +173,34 @@ def test_1024_matter_era_core_growth_switch_full_run():
     before = [m for m in series if m["eta"] < 50.0]
     assert max(m["gauss_rel"] for m in before) < 1e-4
     assert all(m["winding_sum_abs"] > 0 for m in series)
+
+
+def test_beyond_2_31_sites_fp32_sampled(oracle_mod):
+    """1300^3 FP32 (2.2e9 sites, past 2^31; 132 GB resident): every index of the
+    path is 64-bit.  One step from a GPU-made snapshot against the oracle on
+    sampled sites (each from its gathered 3x3x3 neighbourhood, as for 1024^3),
+    including the sites whose flat index is just below and above 2^31 and the
+    far corner."""
+    import paper_2005_14454_amd as ah
+    N = 1300
+    gp = ah.Params(N=N, precision="fp32", m=1.0)
+    op = oracle_mod.params(N=3, m=1.0, eta_ref=0.5 * 0.5 * N)
+    rng = np.random.default_rng(41)
+    special = [0, N ** 3 - 1, 2 ** 31 - 1, 2 ** 31, 2 ** 31 + N * N - 1, N * N * (N - 1)]
+    centres = np.unique(np.concatenate([rng.integers(0, N ** 3, 120), special]))
+    with ah.Lattice(gp) as lat:
+        lat.init(3)
+        lat.step(2)
+        cubes = np.array([cube(N, int(s)) for s in centres])
+        before = lat.gather(cubes.reshape(-1)).reshape(len(centres), 27, 10)
+        lat.step(1)
+        after = lat.gather(centres)
+        meas = lat.measure()
+    ref = np.empty_like(after)
+    for k in range(len(centres)):
+        ref[k] = oracle_mod.step_sites(op, np.ascontiguousarray(before[k].T), 2, [13])[0]
+    err = field_scaled_error(after.T, ref.T)
+    print("1300^3 FP32 sampled one-step error", err)
+    assert max(err.values()) <= 2e-6, err
+    assert meas["nonfinite"] == 0 and meas["step"] == 3
+    assert meas["gauss_rel"] < 1e-5 and meas["winding_sum_abs"] > 0
