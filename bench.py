@@ -205,8 +205,10 @@ def served(nreq=40, capacity_su=3.0e10):
 
 
 def copy_probe(nbytes=8 << 30, reps=10):
-    """Achievable HBM bandwidth of a plain device-to-device copy (torch's copy
-    kernel) of nbytes: (read + write bytes) / time."""
+    """Achievable HBM bandwidth: torch's device-to-device copy of nbytes
+    ((read + write bytes) / time; also the known-size copy the PMC traffic
+    figures are calibrated with) and the library's streaming copy, read-only
+    and write-only kernels (best launch shape)."""
     import torch
     n = nbytes // 4
     a = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -223,7 +225,9 @@ def copy_probe(nbytes=8 << 30, reps=10):
     ms = ev0.elapsed_time(ev1) / reps
     del a, b
     torch.cuda.empty_cache()
-    return {"bytes_per_copy": 2 * n * 4, "ms": ms, "GB/s": 2 * n * 4 / ms / 1e6}
+    import paper_2005_14454_amd as ah
+    return {"bytes_per_copy": 2 * n * 4, "ms": ms, "GB/s": 2 * n * 4 / ms / 1e6,
+            "streaming_kernels": ah.hbm_probe(nbytes // 2, 5)}
 
 
 def cpu_baseline(N, seed, steps=4):

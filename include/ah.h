@@ -316,6 +316,15 @@ const char* ah_pool_last_error(const ah_pool* pool);
 /* Free the arena and everything else the pool holds. */
 int ah_pool_destroy(ah_pool* pool);
 
+/* ------------------------------------------------------ bandwidth probe */
+/* Achievable HBM bandwidth of the current device, the reference the step's
+ * bytes per second are read against besides the nominal peak: streaming
+ * copy (bytes read + written), read-only and write-only kernels over two
+ * library-allocated buffers of `bytes` each (>= 1 MiB; freed before
+ * returning), `reps` timed launches per launch shape, best shape reported, in
+ * GB/s (1e9 bytes/s).  Synchronous; AH_E_NOMEM if the buffers do not fit. */
+int ah_hbm_probe(size_t bytes, int32_t reps, double* copy_gbps, double* read_gbps, double* write_gbps);
+
 /* Static description of an error code. */
 const char* ah_strerror(int code);
 

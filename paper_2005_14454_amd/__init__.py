@@ -276,6 +276,18 @@ def tune_load(path: str):
     _lib.check(_lib.load().ah_tune_load(path.encode()), what="ah_tune_load")
 
 
+def hbm_probe(nbytes: int = 4 << 30, reps: int = 5) -> dict:
+    """Achievable HBM bandwidth of the current device (GB/s): streaming copy,
+    read-only and write-only kernels over two buffers of nbytes."""
+    import torch
+    lib = _lib.load()
+    c, r, w = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    with torch.cuda.device(torch.cuda.current_device()):
+        _lib.check(lib.ah_hbm_probe(nbytes, reps, ctypes.byref(c), ctypes.byref(r), ctypes.byref(w)),
+                   what="ah_hbm_probe")
+    return {"bytes": nbytes, "copy_GB/s": c.value, "read_GB/s": r.value, "write_GB/s": w.value}
+
+
 def pool_footprint(p: Params, nsteps: int, measure_every: int) -> int:
     n = ctypes.c_size_t()
     _lib.check(_lib.load().ah_pool_footprint(ctypes.byref(p.to_c()), nsteps, measure_every, ctypes.byref(n)),

@@ -128,6 +128,8 @@ def load():
         "ah_pool_last_error": ([vp], ctypes.c_char_p),
         "ah_pool_destroy": ([vp], ctypes.c_int),
         "ah_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "ah_hbm_probe": ([ctypes.c_size_t, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double),
+                          P(ctypes.c_double)], ctypes.c_int),
         "ah_last_error": ([vp], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():

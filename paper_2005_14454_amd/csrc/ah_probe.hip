@@ -1,0 +1,109 @@
+// HBM bandwidth probe: streaming copy, read-only and write-only kernels over
+// two device buffers, to state the bandwidth a kernel can reach on this
+// device (the step kernels' roofline is quoted against the nominal peak and
+// this achievable one).
+#include <algorithm>
+#include <cstddef>
+
+#include "ah.h"
+#include "ah_internal.h"
+
+namespace ah {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ void k_probe_copy(const v4f* __restrict__ a, v4f* __restrict__ b, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
+}
+
+__global__ void k_probe_read(const v4f* __restrict__ a, float* __restrict__ sink, size_t n)
+{
+    float s = 0.f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const v4f v = __builtin_nontemporal_load(a + i);
+        s += (v.x + v.y) + (v.z + v.w);
+    }
+    if (s == 1.2345e-38f) sink[threadIdx.x] = s;  // keeps the loads; the buffers hold zeros
+}
+
+__global__ void k_probe_write(v4f* __restrict__ b, size_t n)
+{
+    const v4f v = {1.f, 2.f, 3.f, 4.f};
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(v, b + i);
+}
+
+}  // namespace
+}  // namespace ah
+
+extern "C" int ah_hbm_probe(size_t bytes, int32_t reps, double* copy_gbps, double* read_gbps, double* write_gbps)
+{
+    using namespace ah;
+    if (bytes < ((size_t)1 << 20) || reps < 1 || !copy_gbps || !read_gbps || !write_gbps) return AH_E_INVAL;
+    bytes = bytes / 16 * 16;
+    const size_t n = bytes / 16;
+    void *a = nullptr, *b = nullptr;
+    float* sink = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = AH_OK;
+    hipError_t e = hipMalloc(&a, bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&sink, 1024 * sizeof(float));
+    if (e != hipSuccess) rc = AH_E_NOMEM;
+    if (rc == AH_OK) {
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = hipMemsetAsync(a, 0, bytes, s);
+        if (e == hipSuccess) e = hipMemsetAsync(b, 0, bytes, s);
+        if (e != hipSuccess) rc = AH_E_DEVICE;
+    }
+    double best[3] = {0.0, 0.0, 0.0};
+    // a few launch shapes; the probe reports the best of each kind
+    const int grids[5] = {1024, 2048, 4096, 8192, 16384};
+    const int blocks[3] = {256, 512, 1024};
+    for (int kind = 0; kind < 3 && rc == AH_OK; ++kind)
+        for (int g : grids)
+            for (int bs : blocks) {
+                auto launch = [&]() {
+                    if (kind == 0)
+                        hipLaunchKernelGGL(k_probe_copy, dim3(g), dim3(bs), 0, s, (const v4f*)a, (v4f*)b, n);
+                    else if (kind == 1)
+                        hipLaunchKernelGGL(k_probe_read, dim3(g), dim3(bs), 0, s, (const v4f*)a, sink, n);
+                    else
+                        hipLaunchKernelGGL(k_probe_write, dim3(g), dim3(bs), 0, s, (v4f*)b, n);
+                };
+                launch();
+                e = hipEventRecord(e0, s);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                    launch();
+                    e = hipGetLastError();
+                }
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    rc = AH_E_DEVICE;
+                    break;
+                }
+                const double moved = (kind == 0 ? 2.0 : 1.0) * (double)bytes * reps;
+                best[kind] = std::max(best[kind], moved / (ms * 1e-3) / 1e9);
+            }
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (s) (void)hipStreamDestroy(s);
+    if (sink) (void)hipFree(sink);
+    if (b) (void)hipFree(b);
+    if (a) (void)hipFree(a);
+    (void)hipGetLastError();
+    if (rc != AH_OK) return rc;
+    *copy_gbps = best[0];
+    *read_gbps = best[1];
+    *write_gbps = best[2];
+    return AH_OK;
+}

@@ -51,3 +51,13 @@ def test_tuned_automatic_zchunk_is_resolved(ah):
         lat.step(3)
         m = lat.measure()
     assert m["nonfinite"] == 0 and m["step"] == 3
+
+
+def test_hbm_probe_is_plausible(ah):
+    """The bandwidth probe reports rates that a device can reach: above 1 TB/s
+    and not above the nominal 8 TB/s HBM peak (with a margin for timing)."""
+    out = ah.hbm_probe(1 << 30, 3)
+    for k in ("copy_GB/s", "read_GB/s", "write_GB/s"):
+        assert 1000.0 < out[k] < 8400.0, out
+    with pytest.raises(ah.AHError):
+        ah.hbm_probe(1000, 1)
