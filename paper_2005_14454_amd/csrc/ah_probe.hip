@@ -67,8 +67,9 @@ extern "C" int ah_hbm_probe(size_t bytes, int32_t reps, double* copy_gbps, doubl
     const int grids[5] = {1024, 2048, 4096, 8192, 16384};
     const int blocks[3] = {256, 512, 1024};
     for (int kind = 0; kind < 3 && rc == AH_OK; ++kind)
-        for (int g : grids)
-            for (int bs : blocks) {
+        for (int gi = 0; gi < 5 && rc == AH_OK; ++gi)
+            for (int bi = 0; bi < 3 && rc == AH_OK; ++bi) {
+                const int g = grids[gi], bs = blocks[bi];
                 auto launch = [&]() {
                     if (kind == 0)
                         hipLaunchKernelGGL(k_probe_copy, dim3(g), dim3(bs), 0, s, (const v4f*)a, (v4f*)b, n);
@@ -89,7 +90,7 @@ extern "C" int ah_hbm_probe(size_t bytes, int32_t reps, double* copy_gbps, doubl
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
                 if (e != hipSuccess) {
                     rc = AH_E_DEVICE;
-                    break;
+                    continue;
                 }
                 const double moved = (kind == 0 ? 2.0 : 1.0) * (double)bytes * reps;
                 best[kind] = std::max(best[kind], moved / (ms * 1e-3) / 1e9);
