@@ -138,7 +138,7 @@ def test_scaling_fit_recovers_known_rates():
     the printed one."""
     from paper_2005_14454_amd.scaling import analyse, mean_err
     series = []
-    for k in range(0, 200):
+    for k in range(0, 300):
         eta = 1.0 + 0.5 * k
         inside = 80.0 <= eta <= 128.0
         series.append({"eta": eta, "xi_L": 0.27 * eta + 3.0 if inside else 1e3,
