@@ -1,5 +1,5 @@
 """GPU parity at the benchmark's full size (512^3) in the launch configuration
-the benchmark times (automatic kernel choice: the tiled step).
+the benchmark times (the tiled step on the recorded tuning table's tiling).
 
 The oracle cannot evolve 512^3 in seconds, so one GPU step from a GPU-made
 snapshot is checked against the oracle evaluated one site at a time on
@@ -38,11 +38,26 @@ def _boundary_sites(N):
     return np.array(out, dtype=np.int64)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp64", 1e-13)])
-def test_fullsize_one_step_sampled(oracle_mod, precision, tol):
+@pytest.fixture
+def bench_tiling():
+    """The launch configuration the benchmark times: the recorded tuning table
+    (cleared again afterwards, so that other tests see the defaults)."""
     import paper_2005_14454_amd as ah
+    from paper_2005_14454_amd.tune import TABLE
+    ah.tune_clear()
+    ah.tune_load(TABLE)
+    yield ah
+    ah.tune_clear()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp64", 1e-13)])
+def test_fullsize_one_step_sampled(oracle_mod, bench_tiling, precision, tol):
+    ah = bench_tiling
     op, gp = both_params(oracle_mod, N, precision, m=1.0)
+    want = ah.tune_lookup(gp)
     with ah.Lattice(gp) as lat:
+        cfg = lat.get_step_config()
+        assert (cfg["tile"], cfg["zchunk"]) == (want["tile"], want["zchunk"]), (cfg, want)
         lat.init(1)
         lat.step(5)
         before = lat.get_state()

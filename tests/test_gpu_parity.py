@@ -237,6 +237,31 @@ def test_windings_on_decision_boundaries(oracle_mod, ah, precision, tile):
     assert np.array_equal(w, wo.astype(np.int8))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_windings_with_zero_phi_sites(oracle_mod, ah, precision):
+    """Degenerate link phases: phi exactly zero (of either sign) at 10% of the
+    sites, so z = conj(phi) U phi' is a signed zero and the phase follows the
+    definition's convention for atan2(0, +-0); windings and their sum equal
+    the oracle's."""
+    N = 24
+    op, gp = both_params(oracle_mod, N, precision)
+    st = random_state(N, seed=19)
+    rng = np.random.default_rng(20)
+    zero = rng.random(N ** 3) < 0.1
+    neg = rng.random(N ** 3) < 0.5
+    st[0, zero] = np.where(neg[zero], -0.0, 0.0)
+    st[1, zero] = np.where(neg[zero], 0.0, -0.0)
+    if precision == "fp32":
+        st = st.astype(np.float32).astype(np.float64)
+    with ah.Lattice(gp) as lat:
+        lat.set_state(st, 2)
+        gm = lat.measure()
+        w = lat.winding()
+    om = oracle_mod.measure(op, st, 2)
+    assert gm["winding_sum_abs"] == om["winding_sum_abs"]
+    assert np.array_equal(w, oracle_mod.winding(op, st).astype(np.int8))
+
+
 def test_deterministic_and_resumable(ah):
     from paper_2005_14454_amd import Params
     gp = Params(N=32, m=1.0)
