@@ -11,7 +11,8 @@ diagnostics (windings, energy split, Lagrangian estimators, Gauss residual),
 formed in the same pass as its step, inside the timed region.
 
 Prints one JSON line.  Flags: --gpus N (only 1 is supported), --steps K,
---warmup W, --no-cpu-baseline, --no-fp64.
+--warmup W, --no-cpu-baseline, --cpu-sweep, --no-fp64, --no-batched,
+--no-served, --no-copy-probe.
 """
 import argparse
 import json
@@ -245,6 +246,44 @@ def cpu_baseline(N, seed, steps=4):
             "sample": f"{steps} FP64 steps of the {N}^3 lattice after one untimed step, {dt:.1f} s"}
 
 
+def cpu_sweep(seed, repeats=3):
+    """The oracle timed at the sizes of its own timing protocol: 64^3 and
+    128^3 for 20 steps and 256^3 for 5, each after one untimed step, on all
+    host threads and on one; median of `repeats` runs."""
+    import platform
+    import statistics
+
+    import oracle
+
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    full = oracle.num_threads()
+    rows = []
+    for threads in (full, 1):
+        oracle.set_threads(threads)
+        for N, steps in ((64, 20), (128, 20), (256, 5)):
+            p = oracle.params(N=N, m=1.0)
+            st = oracle.step(p, oracle.init(p, seed), 0, 1)
+            times = []
+            for _ in range(repeats):
+                t0 = time.perf_counter()
+                oracle.step(p, st, 1, steps)
+                times.append(time.perf_counter() - t0)
+            dt = statistics.median(times)
+            rows.append({"N": N, "steps": steps, "threads": threads, "median_s": dt,
+                         "su_per_s": steps * N ** 3 / dt})
+            print(f"# oracle {N}^3 x {steps} steps, {threads} threads: {rows[-1]['su_per_s']:.3e} su/s",
+                  file=sys.stderr, flush=True)
+    oracle.set_threads(full)
+    return {"cpu": model, "nproc": os.cpu_count(), "threads": full, "repeats": repeats, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +292,8 @@ def main():
     ap.add_argument("--N", type=int, default=512)
     ap.add_argument("--measure-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweep", action="store_true",
+                    help="also time the oracle at 64^3, 128^3 and 256^3 on all host threads and on one")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -290,6 +331,8 @@ def main():
               f"p99 {serv['ttc_p99_s']:.2f} s", file=sys.stderr, flush=True)
     probe = None if args.no_copy_probe else copy_probe()
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.N, seed)
+    if cpu is not None and args.cpu_sweep:
+        cpu["sweep"] = cpu_sweep(seed)
 
     out = {
         "metric": "lattice site-updates/s (FP64 vs FP32, % HBM peak); batched p50/p99 run latency",

@@ -80,6 +80,7 @@ def _load():
     lib.ahref_gauss.argtypes = [P(_Params), dp, ctypes.c_int64, dp]
     lib.ahref_measure.argtypes = [P(_Params), dp, ctypes.c_int64, P(_Meas)]
     lib.ahref_num_threads.restype = ctypes.c_int
+    lib.ahref_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
 
@@ -201,3 +202,8 @@ def measure(p: dict, st: np.ndarray, n: int) -> dict:
 
 def num_threads() -> int:
     return int(_load().ahref_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads for the oracle's later calls."""
+    _load().ahref_set_threads(int(n))

@@ -551,3 +551,12 @@ int ahref_num_threads(void)
     return 1;
 #endif
 }
+
+void ahref_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -101,6 +101,9 @@ void ahref_measure(const ahref_params* p, const double* st, int64_t n, ahref_mea
 /* OpenMP threads the oracle runs with */
 int ahref_num_threads(void);
 
+/* threads for the oracle's later calls (n > 0) */
+void ahref_set_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,3 +69,15 @@ def run_alone(gp, seed, nsteps, every, tile, zchunk):
             if k < nsteps:
                 lat.step(1)
         return lat.get_state(), series
+
+
+def rounding_floor(oracle_mod, N=64, seed=0, nsteps=100):
+    """Field-scaled difference after nsteps between the run from the
+    random-phase start and the run with phi nudged by one ulp at every site."""
+    op = oracle_mod.params(N=N, m=1.0)
+    ic = oracle_mod.init(op, seed)
+    nudged = ic.copy()
+    nudged[0:2] = np.nextafter(nudged[0:2], np.inf)
+    a = oracle_mod.step(op, ic, 0, nsteps)
+    b = oracle_mod.step(op, nudged, 0, nsteps)
+    return field_scaled_error(b, a)

@@ -117,8 +117,15 @@ def config1_reference(oracle_mod):
     return op, ic, oracle_mod.step(op, ic, 0, 100)
 
 
+@pytest.fixture(scope="module")
+def config1_rounding_floor(oracle_mod):
+    """What one ulp of phi in the start grows to by step 100 of the same run."""
+    from helpers import rounding_floor
+    return max(rounding_floor(oracle_mod).values())
+
+
 @pytest.mark.parametrize("kernel", ["site", "tile"])
-def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference, kernel):
+def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference, config1_rounding_floor, kernel):
     op, ic, ref = config1_reference
     _, gp = both_params(oracle_mod, 64, "fp64", m=1.0)
     with ah.Lattice(gp) as lat:
@@ -128,7 +135,8 @@ def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference, kernel):
             lat.step(10)
         got = lat.get_state()
         err = field_scaled_error(got, ref)
-        print("config1 fp64 100 steps", err)
+        print(f"config1 fp64 100 steps {err}; rounding floor of the run {config1_rounding_floor:.2e}, "
+              f"ratio {max(err.values()) / config1_rounding_floor:.1f}")
         assert max(err.values()) <= 1e-10, err
         # diagnostics of the GPU snapshot against the oracle on the same snapshot
         gm = lat.measure()
