@@ -3,7 +3,9 @@ identical seeded inputs.
 
 Tolerances (field-scaled max norm per field, max over phi, Pi, A, E):
   one step from an identical FP64 snapshot      <= 1e-13
-  64^3 radiation era, 100 steps, FP64            <= 1e-10
+  64^3 radiation era, 100 steps, FP64            <= 1e-10, and <= the run's rounding
+                                                 floor (what one ulp of phi in the start
+                                                 grows to in the oracle by step 100)
   64^3 radiation era, 100 steps, FP32 vs FP64    <= 1e-4
   windings on identical snapshots                bit-exact
   FP64 diagnostics on identical snapshots        <= 1e-11 relative
@@ -138,6 +140,8 @@ def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference, config1_round
         print(f"config1 fp64 100 steps {err}; rounding floor of the run {config1_rounding_floor:.2e}, "
               f"ratio {max(err.values()) / config1_rounding_floor:.1f}")
         assert max(err.values()) <= 1e-10, err
+        # and no further from the oracle than the oracle is from itself after a one-ulp change of the start
+        assert max(err.values()) <= config1_rounding_floor, (err, config1_rounding_floor)
         # diagnostics of the GPU snapshot against the oracle on the same snapshot
         gm = lat.measure()
         om = oracle_mod.measure(op, got, 100)
