@@ -32,7 +32,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     objs = []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        lang = ["-x", "hip"] + DEVICE_FLAGS if src.endswith(".hip") else []
+        # hipcc treats .cpp as HIP too: give every source the one target
+        lang = (["-x", "hip"] if src.endswith(".hip") else []) + DEVICE_FLAGS
         cmd = [HIPCC, *COMMON, *lang, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

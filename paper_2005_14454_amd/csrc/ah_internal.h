@@ -10,6 +10,19 @@
 
 namespace ah {
 
+// Runs the body of a C-ABI entry point: an exception from the host containers
+// it uses (host memory exhausted, a size past what a container can hold)
+// becomes AH_E_NOMEM instead of crossing the ABI.
+template <typename F>
+inline int no_throw(F&& body) noexcept
+{
+    try {
+        return body();
+    } catch (...) {
+        return AH_E_NOMEM;
+    }
+}
+
 // Structure-of-arrays field pointers of one lattice snapshot.  phi and A come
 // from the current ping-pong buffer, Pi and E are single buffers updated in
 // place; the drift writes phi and A into the other ping-pong buffer.

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <new>
@@ -58,9 +59,15 @@ struct Footprint {
     int64_t series_cap;
 };
 
+// Bytes of one pool lattice; total = SIZE_MAX when nsteps is too large for
+// its coefficient table to be addressed at all.
 Footprint footprint(const ah_params& p, const ah_step_config& cfg, int64_t nsteps, int measure_every)
 {
     Footprint f{};
+    if ((uint64_t)nsteps >= (SIZE_MAX / 4) / (kCoefStride * sizeof(double))) {
+        f.total = SIZE_MAX;
+        return f;
+    }
     const size_t V = (size_t)p.N * p.N * p.N;
     f.field = align_up(V * (p.precision == AH_FP64 ? 8 : 4));
     f.fields = 15 * f.field;
@@ -290,51 +297,53 @@ extern "C" {
 
 int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_pool** out)
 {
-    if (!out || max_slots <= 0 || max_slots > 65536 || hbm_budget < kAlign) return AH_E_INVAL;
-    *out = nullptr;
-    ah_pool* P = new (std::nothrow) ah_pool;
-    if (!P) return AH_E_NOMEM;
-    if (hipGetDevice(&P->device) != hipSuccess) {
-        delete P;
-        return AH_E_DEVICE;
-    }
-    hipError_t e;
-    if (hip_stream) {
-        P->stream = (hipStream_t)hip_stream;
-    } else {
-        e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
-        if (e != hipSuccess) {
+    return no_throw([&]() -> int {
+        if (!out || max_slots <= 0 || max_slots > 65536 || hbm_budget < kAlign) return AH_E_INVAL;
+        *out = nullptr;
+        ah_pool* P = new (std::nothrow) ah_pool;
+        if (!P) return AH_E_NOMEM;
+        if (hipGetDevice(&P->device) != hipSuccess) {
             delete P;
             return AH_E_DEVICE;
         }
-        P->owns_stream = true;
-    }
-    P->budget = hbm_budget / kAlign * kAlign;
-    e = hipMalloc(&P->arena, P->budget);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        if (P->owns_stream) (void)hipStreamDestroy(P->stream);
-        delete P;
-        return AH_E_NOMEM;
-    }
-    P->free_list.push_back({0, P->budget});
-    P->slots.resize(max_slots);
-    e = hipMalloc(&P->d_lat, max_slots * sizeof(PoolLattice));
-    if (e == hipSuccess) e = hipMalloc(&P->d_counters, 2 * max_slots * sizeof(int64_t));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&P->h_counters, 2 * max_slots * sizeof(int64_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMemset(P->d_counters, 0, 2 * max_slots * sizeof(int64_t));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        if (P->d_lat) (void)hipFree(P->d_lat);
-        if (P->d_counters) (void)hipFree(P->d_counters);
-        if (P->h_counters) (void)hipHostFree(P->h_counters);
-        (void)hipFree(P->arena);
-        if (P->owns_stream) (void)hipStreamDestroy(P->stream);
-        delete P;
-        return AH_E_NOMEM;
-    }
-    *out = P;
-    return AH_OK;
+        hipError_t e;
+        if (hip_stream) {
+            P->stream = (hipStream_t)hip_stream;
+        } else {
+            e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                delete P;
+                return AH_E_DEVICE;
+            }
+            P->owns_stream = true;
+        }
+        P->budget = hbm_budget / kAlign * kAlign;
+        e = hipMalloc(&P->arena, P->budget);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (P->owns_stream) (void)hipStreamDestroy(P->stream);
+            delete P;
+            return AH_E_NOMEM;
+        }
+        P->free_list.push_back({0, P->budget});
+        P->slots.resize(max_slots);
+        e = hipMalloc(&P->d_lat, max_slots * sizeof(PoolLattice));
+        if (e == hipSuccess) e = hipMalloc(&P->d_counters, 2 * max_slots * sizeof(int64_t));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&P->h_counters, 2 * max_slots * sizeof(int64_t), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMemset(P->d_counters, 0, 2 * max_slots * sizeof(int64_t));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (P->d_lat) (void)hipFree(P->d_lat);
+            if (P->d_counters) (void)hipFree(P->d_counters);
+            if (P->h_counters) (void)hipHostFree(P->h_counters);
+            (void)hipFree(P->arena);
+            if (P->owns_stream) (void)hipStreamDestroy(P->stream);
+            delete P;
+            return AH_E_NOMEM;
+        }
+        *out = P;
+        return AH_OK;
+    });
 }
 
 // Tile configuration of a pool lattice: the tuned (or default) tile shape,
@@ -359,154 +368,167 @@ static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why
 
 int ah_pool_footprint(const ah_params* p, int64_t nsteps, int32_t measure_every, size_t* bytes)
 {
-    std::string why;
-    if (validate_params(p, &why) != AH_OK || nsteps < 0 || measure_every < 0 || !bytes) return AH_E_INVAL;
-    if (p->gauge_action != AH_COMPACT) return AH_E_INVAL;
-    ah_step_config cfg;
-    if (pool_config(*p, &cfg, &why) != AH_OK) return AH_E_INVAL;
-    *bytes = footprint(*p, cfg, nsteps, measure_every).total;
-    return AH_OK;
+    return no_throw([&]() -> int {
+        std::string why;
+        if (validate_params(p, &why) != AH_OK || nsteps < 0 || measure_every < 0 || !bytes) return AH_E_INVAL;
+        if (p->gauge_action != AH_COMPACT) return AH_E_INVAL;
+        ah_step_config cfg;
+        if (pool_config(*p, &cfg, &why) != AH_OK) return AH_E_INVAL;
+        const size_t total = footprint(*p, cfg, nsteps, measure_every).total;
+        if (total == SIZE_MAX) return AH_E_INVAL;
+        *bytes = total;
+        return AH_OK;
+    });
 }
 
 int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps, int32_t measure_every,
                    int64_t* id)
 {
-    if (!P || !p || !id || nsteps < 0 || measure_every < 0) return pfail(P, AH_E_INVAL, "ah_pool_submit: bad argument");
-    std::string why;
-    int rc = validate_params(p, &why);
-    if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
-    ah_step_config cfg{AH_KERNEL_TILE, 0, 0, 0};
-    if (p->gauge_action != AH_COMPACT) return pfail(P, AH_E_INVAL, "ah_pool_submit: the pool runs the compact action");
-    rc = pool_config(*p, &cfg, &why);
-    if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
-    const Footprint fp = footprint(*p, cfg, nsteps, measure_every);
-    if (fp.total > P->budget) return pfail(P, AH_E_NOMEM, "ah_pool_submit: request larger than the pool budget");
-    int slot = -1;
-    for (int i = 0; i < (int)P->slots.size(); ++i)
-        if (!P->slots[i].used) {
-            slot = i;
-            break;
-        }
-    if (slot < 0) return pfail(P, AH_E_AGAIN, "ah_pool_submit: no free slot");
-    size_t off;
-    if (!arena_alloc(P, fp.total, &off)) return pfail(P, AH_E_AGAIN, "ah_pool_submit: not enough free memory now");
-    Guard g(P->device);
+    return no_throw([&]() -> int {
+        if (!P || !p || !id || nsteps < 0 || measure_every < 0) return pfail(P, AH_E_INVAL, "ah_pool_submit: bad argument");
+        std::string why;
+        int rc = validate_params(p, &why);
+        if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
+        ah_step_config cfg{AH_KERNEL_TILE, 0, 0, 0};
+        if (p->gauge_action != AH_COMPACT) return pfail(P, AH_E_INVAL, "ah_pool_submit: the pool runs the compact action");
+        rc = pool_config(*p, &cfg, &why);
+        if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
+        const Footprint fp = footprint(*p, cfg, nsteps, measure_every);
+        if (fp.total > P->budget) return pfail(P, AH_E_NOMEM, "ah_pool_submit: request larger than the pool budget");
+        int slot = -1;
+        for (int i = 0; i < (int)P->slots.size(); ++i)
+            if (!P->slots[i].used) {
+                slot = i;
+                break;
+            }
+        if (slot < 0) return pfail(P, AH_E_AGAIN, "ah_pool_submit: no free slot");
+        if (largest_free(P) < fp.total) return pfail(P, AH_E_AGAIN, "ah_pool_submit: not enough free memory now");
+        // the coefficient table before anything is taken, so that a host
+        // allocation failure leaves the pool as it was
+        std::vector<double> rows((size_t)(nsteps + 1) * kCoefStride, 0.0);
+        for (int64_t k = 0; k <= nsteps; ++k) coef_row(*p, k, rows.data() + k * kCoefStride);
+        size_t off;
+        if (!arena_alloc(P, fp.total, &off)) return pfail(P, AH_E_AGAIN, "ah_pool_submit: not enough free memory now");
+        Guard g(P->device);
 
-    Slot& s = P->slots[slot];
-    s = Slot{};
-    s.used = true;
-    s.id = P->next_id++;
-    s.p = *p;
-    s.nsteps = nsteps;
-    s.measure_every = measure_every;
-    s.off = off;
-    s.bytes = fp.total;
-    s.cfg = cfg;
-    char* base = (char*)P->arena + off;
-    PoolLattice& d = s.d;
-    std::memset(&d, 0, sizeof(d));
-    for (int b = 0; b < 2; ++b)
+        Slot& s = P->slots[slot];
+        s = Slot{};
+        s.used = true;
+        s.id = P->next_id++;
+        s.p = *p;
+        s.nsteps = nsteps;
+        s.measure_every = measure_every;
+        s.off = off;
+        s.bytes = fp.total;
+        s.cfg = cfg;
+        char* base = (char*)P->arena + off;
+        PoolLattice& d = s.d;
+        std::memset(&d, 0, sizeof(d));
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 5; ++c) {
+                d.pp[b][c] = base;
+                base += fp.field;
+            }
         for (int c = 0; c < 5; ++c) {
-            d.pp[b][c] = base;
+            d.mom[c] = base;
             base += fp.field;
         }
-    for (int c = 0; c < 5; ++c) {
-        d.mom[c] = base;
-        base += fp.field;
-    }
-    d.partials = (double*)base;
-    base += fp.partials;
-    double* coef = (double*)base;
-    d.coef = coef;
-    base += fp.coef;
-    d.series = (double*)base;
-    d.counter = P->d_counters + 2 * slot;
-    d.nsteps = nsteps;
-    d.series_cap = fp.series_cap;
-    d.N = p->N;
-    d.tiles_x = (p->N + cfg.tile_x - 1) / cfg.tile_x;
-    d.tiles_y = (p->N + cfg.tile_y - 1) / cfg.tile_y;
-    d.zchunk = cfg.zchunk;
-    d.meas_zchunk = fp.meas_zc;
-    d.meas_blocks = fp.meas_blocks;
-    d.gauss_blocks = fp.gauss_blocks;
-    d.measure_every = measure_every;
-    d.precision = p->precision;
-    d.compact = 1;
-    d.dx = p->dx;
-    d.deta = p->deta;
-    d.sigma2 = p->sigma * p->sigma;
+        d.partials = (double*)base;
+        base += fp.partials;
+        double* coef = (double*)base;
+        d.coef = coef;
+        base += fp.coef;
+        d.series = (double*)base;
+        d.counter = P->d_counters + 2 * slot;
+        d.nsteps = nsteps;
+        d.series_cap = fp.series_cap;
+        d.N = p->N;
+        d.tiles_x = (p->N + cfg.tile_x - 1) / cfg.tile_x;
+        d.tiles_y = (p->N + cfg.tile_y - 1) / cfg.tile_y;
+        d.zchunk = cfg.zchunk;
+        d.meas_zchunk = fp.meas_zc;
+        d.meas_blocks = fp.meas_blocks;
+        d.gauss_blocks = fp.gauss_blocks;
+        d.measure_every = measure_every;
+        d.precision = p->precision;
+        d.compact = 1;
+        d.dx = p->dx;
+        d.deta = p->deta;
+        d.sigma2 = p->sigma * p->sigma;
 
-    std::vector<double> rows((size_t)(nsteps + 1) * kCoefStride, 0.0);
-    for (int64_t k = 0; k <= nsteps; ++k) coef_row(*p, k, rows.data() + k * kCoefStride);
-    // enqueue on the pool stream (after any graph replays already queued),
-    // then wait so that the host staging vector can go
-    hipError_t e = hipMemcpyAsync(coef, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice, P->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 2 * sizeof(int64_t), P->stream);
-    if (e == hipSuccess) {
-        Fields<double> f64;
-        Fields<float> f32;
-        if (p->precision == AH_FP64) {
-            f64 = Fields<double>{(double*)d.pp[0][0], (double*)d.pp[0][1], (double*)d.mom[0], (double*)d.mom[1],
-                                 (double*)d.pp[0][2], (double*)d.pp[0][3], (double*)d.pp[0][4], (double*)d.mom[2],
-                                 (double*)d.mom[3], (double*)d.mom[4]};
-            e = launch_init<double>(f64, p->N, p->sigma, seed, P->stream);
-        } else {
-            f32 = Fields<float>{(float*)d.pp[0][0], (float*)d.pp[0][1], (float*)d.mom[0], (float*)d.mom[1],
-                                (float*)d.pp[0][2], (float*)d.pp[0][3], (float*)d.pp[0][4], (float*)d.mom[2],
-                                (float*)d.mom[3], (float*)d.mom[4]};
-            e = launch_init<float>(f32, p->N, p->sigma, seed, P->stream);
+        // enqueue on the pool stream (after any graph replays already queued),
+        // then wait so that the host staging vector can go
+        hipError_t e = hipMemcpyAsync(coef, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice, P->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 2 * sizeof(int64_t), P->stream);
+        if (e == hipSuccess) {
+            Fields<double> f64;
+            Fields<float> f32;
+            if (p->precision == AH_FP64) {
+                f64 = Fields<double>{(double*)d.pp[0][0], (double*)d.pp[0][1], (double*)d.mom[0], (double*)d.mom[1],
+                                     (double*)d.pp[0][2], (double*)d.pp[0][3], (double*)d.pp[0][4], (double*)d.mom[2],
+                                     (double*)d.mom[3], (double*)d.mom[4]};
+                e = launch_init<double>(f64, p->N, p->sigma, seed, P->stream);
+            } else {
+                f32 = Fields<float>{(float*)d.pp[0][0], (float*)d.pp[0][1], (float*)d.mom[0], (float*)d.mom[1],
+                                    (float*)d.pp[0][2], (float*)d.pp[0][3], (float*)d.pp[0][4], (float*)d.mom[2],
+                                    (float*)d.mom[3], (float*)d.mom[4]};
+                e = launch_init<float>(f32, p->N, p->sigma, seed, P->stream);
+            }
         }
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
-    if (e != hipSuccess) {
-        arena_free(P, s.off, s.bytes);
-        s = Slot{};
-        return phip(P, e, "ah_pool_submit");
-    }
-    P->dirty = true;
-    *id = s.id;
-    return AH_OK;
+        if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+        if (e != hipSuccess) {
+            arena_free(P, s.off, s.bytes);
+            s = Slot{};
+            return phip(P, e, "ah_pool_submit");
+        }
+        P->dirty = true;
+        *id = s.id;
+        return AH_OK;
+    });
 }
 
 int ah_pool_advance(ah_pool* P, int32_t nsteps)
 {
-    if (!P || nsteps < 0) return pfail(P, AH_E_INVAL, "ah_pool_advance: bad argument");
-    Guard g(P->device);
-    if (P->dirty) {
-        int rc = rebuild(P);
-        if (rc != AH_OK) return rc;
-    }
-    for (int32_t k = 0; k < nsteps; ++k) {
-        hipError_t e = hipGraphLaunch(P->exec, P->stream);
-        if (e != hipSuccess) return phip(P, e, "ah_pool_advance graph launch");
-        ++P->graph_launches;
-    }
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!P || nsteps < 0) return pfail(P, AH_E_INVAL, "ah_pool_advance: bad argument");
+        Guard g(P->device);
+        if (P->dirty) {
+            int rc = rebuild(P);
+            if (rc != AH_OK) return rc;
+        }
+        for (int32_t k = 0; k < nsteps; ++k) {
+            hipError_t e = hipGraphLaunch(P->exec, P->stream);
+            if (e != hipSuccess) return phip(P, e, "ah_pool_advance graph launch");
+            ++P->graph_launches;
+        }
+        return AH_OK;
+    });
 }
 
 int ah_pool_poll(ah_pool* P, int64_t* done_ids, int32_t cap, int32_t* n)
 {
-    if (!P || !n || (cap > 0 && !done_ids)) return pfail(P, AH_E_INVAL, "ah_pool_poll: bad argument");
-    Guard g(P->device);
-    const size_t bytes = 2 * P->slots.size() * sizeof(int64_t);
-    hipError_t e = hipMemcpyAsync(P->h_counters, P->d_counters, bytes, hipMemcpyDeviceToHost, P->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
-    if (e != hipSuccess) return phip(P, e, "ah_pool_poll");
-    int32_t k = 0;
-    for (size_t i = 0; i < P->slots.size(); ++i) {
-        Slot& s = P->slots[i];
-        if (!s.used || s.reported) continue;
-        if (P->h_counters[2 * i] == s.nsteps + 1) {
-            if (k < cap) {
-                done_ids[k] = s.id;
-                s.reported = true;
+    return no_throw([&]() -> int {
+        if (!P || !n || (cap > 0 && !done_ids)) return pfail(P, AH_E_INVAL, "ah_pool_poll: bad argument");
+        Guard g(P->device);
+        const size_t bytes = 2 * P->slots.size() * sizeof(int64_t);
+        hipError_t e = hipMemcpyAsync(P->h_counters, P->d_counters, bytes, hipMemcpyDeviceToHost, P->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+        if (e != hipSuccess) return phip(P, e, "ah_pool_poll");
+        int32_t k = 0;
+        for (size_t i = 0; i < P->slots.size(); ++i) {
+            Slot& s = P->slots[i];
+            if (!s.used || s.reported) continue;
+            if (P->h_counters[2 * i] == s.nsteps + 1) {
+                if (k < cap) {
+                    done_ids[k] = s.id;
+                    s.reported = true;
+                }
+                ++k;
             }
-            ++k;
         }
-    }
-    *n = k < cap ? k : cap;
-    return AH_OK;
+        *n = k < cap ? k : cap;
+        return AH_OK;
+    });
 }
 
 static Slot* find_slot(ah_pool* P, int64_t id, int* index)
@@ -521,77 +543,83 @@ static Slot* find_slot(ah_pool* P, int64_t id, int* index)
 
 int ah_pool_progress(ah_pool* P, int64_t id, int64_t* step, int64_t* nsteps)
 {
-    if (!P || !step) return pfail(P, AH_E_INVAL, "ah_pool_progress: bad argument");
-    int i;
-    Slot* s = find_slot(P, id, &i);
-    if (!s) return pfail(P, AH_E_INVAL, "ah_pool_progress: unknown id");
-    Guard g(P->device);
-    int64_t c[2];
-    hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
-    if (e != hipSuccess) return phip(P, e, "ah_pool_progress");
-    *step = std::min(c[0], s->nsteps);
-    if (nsteps) *nsteps = s->nsteps;
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!P || !step) return pfail(P, AH_E_INVAL, "ah_pool_progress: bad argument");
+        int i;
+        Slot* s = find_slot(P, id, &i);
+        if (!s) return pfail(P, AH_E_INVAL, "ah_pool_progress: unknown id");
+        Guard g(P->device);
+        int64_t c[2];
+        hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+        if (e != hipSuccess) return phip(P, e, "ah_pool_progress");
+        *step = std::min(c[0], s->nsteps);
+        if (nsteps) *nsteps = s->nsteps;
+        return AH_OK;
+    });
 }
 
 int ah_pool_get_state(ah_pool* P, int64_t id, double* host_soa, int64_t* step)
 {
-    if (!P || !host_soa) return pfail(P, AH_E_INVAL, "ah_pool_get_state: bad argument");
-    int i;
-    Slot* s = find_slot(P, id, &i);
-    if (!s) return pfail(P, AH_E_INVAL, "ah_pool_get_state: unknown id");
-    Guard g(P->device);
-    int64_t c[2];
-    hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
-    if (e != hipSuccess) return phip(P, e, "ah_pool_get_state");
-    const int64_t k = std::min(c[0], s->nsteps);
-    const int cur = (int)(k & 1);
-    const size_t V = (size_t)s->p.N * s->p.N * s->p.N;
-    const size_t rb = s->p.precision == AH_FP64 ? 8 : 4;
-    void* comps[10] = {s->d.pp[cur][0], s->d.pp[cur][1], s->d.mom[0], s->d.mom[1], s->d.pp[cur][2],
-                       s->d.pp[cur][3], s->d.pp[cur][4], s->d.mom[2], s->d.mom[3], s->d.mom[4]};
-    std::vector<float> tmp(rb == 4 ? V : 0);
-    for (int cc = 0; cc < 10; ++cc) {
-        double* dst = host_soa + cc * V;
-        e = hipMemcpy(rb == 8 ? (void*)dst : (void*)tmp.data(), comps[cc], V * rb, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return phip(P, e, "ah_pool_get_state copy");
-        if (rb == 4)
-            for (size_t q = 0; q < V; ++q) dst[q] = (double)tmp[q];
-    }
-    if (step) *step = k;
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!P || !host_soa) return pfail(P, AH_E_INVAL, "ah_pool_get_state: bad argument");
+        int i;
+        Slot* s = find_slot(P, id, &i);
+        if (!s) return pfail(P, AH_E_INVAL, "ah_pool_get_state: unknown id");
+        Guard g(P->device);
+        int64_t c[2];
+        hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+        if (e != hipSuccess) return phip(P, e, "ah_pool_get_state");
+        const int64_t k = std::min(c[0], s->nsteps);
+        const int cur = (int)(k & 1);
+        const size_t V = (size_t)s->p.N * s->p.N * s->p.N;
+        const size_t rb = s->p.precision == AH_FP64 ? 8 : 4;
+        void* comps[10] = {s->d.pp[cur][0], s->d.pp[cur][1], s->d.mom[0], s->d.mom[1], s->d.pp[cur][2],
+                           s->d.pp[cur][3], s->d.pp[cur][4], s->d.mom[2], s->d.mom[3], s->d.mom[4]};
+        std::vector<float> tmp(rb == 4 ? V : 0);
+        for (int cc = 0; cc < 10; ++cc) {
+            double* dst = host_soa + cc * V;
+            e = hipMemcpy(rb == 8 ? (void*)dst : (void*)tmp.data(), comps[cc], V * rb, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return phip(P, e, "ah_pool_get_state copy");
+            if (rb == 4)
+                for (size_t q = 0; q < V; ++q) dst[q] = (double)tmp[q];
+        }
+        if (step) *step = k;
+        return AH_OK;
+    });
 }
 
 int ah_pool_results(ah_pool* P, int64_t id, ah_measurement* series, int32_t cap, int32_t* n)
 {
-    if (!P || !n || (cap > 0 && !series)) return pfail(P, AH_E_INVAL, "ah_pool_results: bad argument");
-    int i;
-    Slot* s = find_slot(P, id, &i);
-    if (!s) return pfail(P, AH_E_INVAL, "ah_pool_results: unknown id");
-    Guard g(P->device);
-    int64_t c[2];
-    hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
-    if (e != hipSuccess) return phip(P, e, "ah_pool_results");
-    if (c[0] != s->nsteps + 1) return pfail(P, AH_E_AGAIN, "ah_pool_results: the lattice has not finished");
-    const int64_t nm = std::min(c[1], s->d.series_cap);
-    std::vector<double> raw((size_t)nm * kSeriesStride);
-    if (nm > 0) {
-        e = hipMemcpy(raw.data(), s->d.series, raw.size() * sizeof(double), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return phip(P, e, "ah_pool_results copy");
-    }
-    const int64_t V = (int64_t)s->p.N * s->p.N * s->p.N;
-    const int32_t m = (int32_t)std::min<int64_t>(nm, cap);
-    for (int32_t k = 0; k < m; ++k)
-        to_measurement(s->p, (int64_t)raw[(size_t)k * kSeriesStride + M_COUNT], raw.data() + (size_t)k * kSeriesStride,
-                       V, &series[k]);
-    *n = m;
-    arena_free(P, s->off, s->bytes);
-    *s = Slot{};
-    P->dirty = true;
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!P || !n || (cap > 0 && !series)) return pfail(P, AH_E_INVAL, "ah_pool_results: bad argument");
+        int i;
+        Slot* s = find_slot(P, id, &i);
+        if (!s) return pfail(P, AH_E_INVAL, "ah_pool_results: unknown id");
+        Guard g(P->device);
+        int64_t c[2];
+        hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+        if (e != hipSuccess) return phip(P, e, "ah_pool_results");
+        if (c[0] != s->nsteps + 1) return pfail(P, AH_E_AGAIN, "ah_pool_results: the lattice has not finished");
+        const int64_t nm = std::min(c[1], s->d.series_cap);
+        std::vector<double> raw((size_t)nm * kSeriesStride);
+        if (nm > 0) {
+            e = hipMemcpy(raw.data(), s->d.series, raw.size() * sizeof(double), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return phip(P, e, "ah_pool_results copy");
+        }
+        const int64_t V = (int64_t)s->p.N * s->p.N * s->p.N;
+        const int32_t m = (int32_t)std::min<int64_t>(nm, cap);
+        for (int32_t k = 0; k < m; ++k)
+            to_measurement(s->p, (int64_t)raw[(size_t)k * kSeriesStride + M_COUNT], raw.data() + (size_t)k * kSeriesStride,
+                           V, &series[k]);
+        *n = m;
+        arena_free(P, s->off, s->bytes);
+        *s = Slot{};
+        P->dirty = true;
+        return AH_OK;
+    });
 }
 
 int ah_pool_stats(const ah_pool* P, ah_pool_info* info)
@@ -614,11 +642,13 @@ int ah_pool_stats(const ah_pool* P, ah_pool_info* info)
 
 int ah_pool_synchronize(ah_pool* P)
 {
-    if (!P) return AH_E_INVAL;
-    Guard g(P->device);
-    hipError_t e = hipStreamSynchronize(P->stream);
-    if (e != hipSuccess) return phip(P, e, "ah_pool_synchronize");
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!P) return AH_E_INVAL;
+        Guard g(P->device);
+        hipError_t e = hipStreamSynchronize(P->stream);
+        if (e != hipSuccess) return phip(P, e, "ah_pool_synchronize");
+        return AH_OK;
+    });
 }
 
 const char* ah_pool_last_error(const ah_pool* P) { return P ? P->err.c_str() : ""; }

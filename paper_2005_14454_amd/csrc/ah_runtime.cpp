@@ -516,110 +516,118 @@ int ah_params_default(ah_params* p)
 
 int ah_stability_margin(const ah_params* p, int64_t step, double* mu)
 {
-    std::string why;
-    if (validate(p, &why) != AH_OK || step < 0 || !mu) return AH_E_INVAL;
-    *mu = stability_margin(*p, step);
-    return AH_OK;
+    return no_throw([&]() -> int {
+        std::string why;
+        if (validate(p, &why) != AH_OK || step < 0 || !mu) return AH_E_INVAL;
+        *mu = stability_margin(*p, step);
+        return AH_OK;
+    });
 }
 
 int ah_required_bytes(const ah_params* p, size_t* bytes)
 {
-    std::string why;
-    int rc = validate(p, &why);
-    if (rc != AH_OK) return rc;
-    if (!bytes) return AH_E_INVAL;
-    *bytes = required_bytes(*p);
-    return AH_OK;
+    return no_throw([&]() -> int {
+        std::string why;
+        int rc = validate(p, &why);
+        if (rc != AH_OK) return rc;
+        if (!bytes) return AH_E_INVAL;
+        *bytes = required_bytes(*p);
+        return AH_OK;
+    });
 }
 
 int ah_create(const ah_params* p, void* dev_arena, size_t arena_bytes, void* hip_stream, ah_handle** out)
 {
-    if (!out) return AH_E_INVAL;
-    *out = nullptr;
-    std::string why;
-    int rc = validate(p, &why);
-    if (rc != AH_OK) {
-        std::fprintf(stderr, "ah_create: %s\n", why.c_str());
-        return rc;
-    }
-    ah_handle* h = new (std::nothrow) ah_handle;
-    if (!h) return AH_E_NOMEM;
-    h->p = *p;
-    h->stream = (hipStream_t)hip_stream;
-    h->V = (int64_t)p->N * p->N * p->N;
-    h->real_bytes = p->precision == AH_FP64 ? 8 : 4;
-    hipError_t e = hipGetDevice(&h->device);
-    if (e != hipSuccess) {
-        delete h;
-        return AH_E_DEVICE;
-    }
-    const size_t need = required_bytes(*p);
-    if (dev_arena) {
-        if (arena_bytes < need || ((uintptr_t)dev_arena % kAlign) != 0) {
-            delete h;
-            return AH_E_NOMEM;
+    return no_throw([&]() -> int {
+        if (!out) return AH_E_INVAL;
+        *out = nullptr;
+        std::string why;
+        int rc = validate(p, &why);
+        if (rc != AH_OK) {
+            std::fprintf(stderr, "ah_create: %s\n", why.c_str());
+            return rc;
         }
-        h->arena = dev_arena;
-        h->arena_bytes = arena_bytes;
-    } else {
-        e = hipMalloc(&h->arena, need);
+        ah_handle* h = new (std::nothrow) ah_handle;
+        if (!h) return AH_E_NOMEM;
+        h->p = *p;
+        h->stream = (hipStream_t)hip_stream;
+        h->V = (int64_t)p->N * p->N * p->N;
+        h->real_bytes = p->precision == AH_FP64 ? 8 : 4;
+        hipError_t e = hipGetDevice(&h->device);
         if (e != hipSuccess) {
-            (void)hipGetLastError();
             delete h;
-            return AH_E_NOMEM;
+            return AH_E_DEVICE;
         }
-        h->owns_arena = true;
-        h->arena_bytes = need;
-    }
-    char* base = (char*)h->arena;
-    const size_t fb = field_bytes(*p);
-    for (int b = 0; b < 2; ++b)
+        const size_t need = required_bytes(*p);
+        if (dev_arena) {
+            if (arena_bytes < need || ((uintptr_t)dev_arena % kAlign) != 0) {
+                delete h;
+                return AH_E_NOMEM;
+            }
+            h->arena = dev_arena;
+            h->arena_bytes = arena_bytes;
+        } else {
+            e = hipMalloc(&h->arena, need);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                delete h;
+                return AH_E_NOMEM;
+            }
+            h->owns_arena = true;
+            h->arena_bytes = need;
+        }
+        char* base = (char*)h->arena;
+        const size_t fb = field_bytes(*p);
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 5; ++c) {
+                h->pp[b][c] = base;
+                base += fb;
+            }
         for (int c = 0; c < 5; ++c) {
-            h->pp[b][c] = base;
+            h->mom[c] = base;
             base += fb;
         }
-    for (int c = 0; c < 5; ++c) {
-        h->mom[c] = base;
-        base += fb;
-    }
-    h->partials = (double*)base;
-    base += align_up(partial_records(*p) * kMeasStride * sizeof(double));
-    h->result = (double*)base;
-    base += align_up(kMeasStride * sizeof(double));
-    h->series = (double*)base;
-    e = hipHostMalloc((void**)&h->host_result, kMeasStride * sizeof(double), hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void**)&h->host_series, (size_t)kSeriesCap * kMeasStride * sizeof(double),
-                          hipHostMallocDefault);
-    if (e != hipSuccess) {
-        if (h->host_result) (void)hipHostFree(h->host_result);
-        if (h->owns_arena) (void)hipFree(h->arena);
-        delete h;
-        return AH_E_NOMEM;
-    }
-    {
-        std::string why2;
-        const ah_step_config dflt{AH_KERNEL_AUTO, 0, 0, 0};
-        if (resolve_config(h->p, dflt, &h->cfg, &why2) != AH_OK) {
-            (void)hipHostFree(h->host_result);
+        h->partials = (double*)base;
+        base += align_up(partial_records(*p) * kMeasStride * sizeof(double));
+        h->result = (double*)base;
+        base += align_up(kMeasStride * sizeof(double));
+        h->series = (double*)base;
+        e = hipHostMalloc((void**)&h->host_result, kMeasStride * sizeof(double), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&h->host_series, (size_t)kSeriesCap * kMeasStride * sizeof(double),
+                              hipHostMallocDefault);
+        if (e != hipSuccess) {
+            if (h->host_result) (void)hipHostFree(h->host_result);
             if (h->owns_arena) (void)hipFree(h->arena);
             delete h;
-            return AH_E_INVAL;
+            return AH_E_NOMEM;
         }
-    }
-    *out = h;
-    return AH_OK;
+        {
+            std::string why2;
+            const ah_step_config dflt{AH_KERNEL_AUTO, 0, 0, 0};
+            if (resolve_config(h->p, dflt, &h->cfg, &why2) != AH_OK) {
+                (void)hipHostFree(h->host_result);
+                if (h->owns_arena) (void)hipFree(h->arena);
+                delete h;
+                return AH_E_INVAL;
+            }
+        }
+        *out = h;
+        return AH_OK;
+    });
 }
 
 int ah_set_step_config(ah_handle* h, const ah_step_config* c)
 {
-    if (!h || !c) return fail(h, AH_E_INVAL, "ah_set_step_config: bad argument");
-    std::string why;
-    ah_step_config r;
-    int rc = resolve_config(h->p, *c, &r, &why);
-    if (rc != AH_OK) return fail(h, rc, "ah_set_step_config: " + why);
-    h->cfg = r;
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h || !c) return fail(h, AH_E_INVAL, "ah_set_step_config: bad argument");
+        std::string why;
+        ah_step_config r;
+        int rc = resolve_config(h->p, *c, &r, &why);
+        if (rc != AH_OK) return fail(h, rc, "ah_set_step_config: " + why);
+        h->cfg = r;
+        return AH_OK;
+    });
 }
 
 int ah_get_step_config(const ah_handle* h, ah_step_config* c)
@@ -631,106 +639,114 @@ int ah_get_step_config(const ah_handle* h, ah_step_config* c)
 
 int ah_init(ah_handle* h, uint64_t seed)
 {
-    if (!h) return AH_E_INVAL;
-    DeviceGuard g(h->device);
-    h->cur = 0;
-    h->step = 0;
-    hipError_t e = h->p.precision == AH_FP64
-                       ? launch_init<double>(fields_of<double>(h, 0), h->p.N, h->p.sigma, seed, h->stream)
-                       : launch_init<float>(fields_of<float>(h, 0), h->p.N, h->p.sigma, seed, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "ah_init launch");
-    h->ready = true;
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h) return AH_E_INVAL;
+        DeviceGuard g(h->device);
+        h->cur = 0;
+        h->step = 0;
+        hipError_t e = h->p.precision == AH_FP64
+                           ? launch_init<double>(fields_of<double>(h, 0), h->p.N, h->p.sigma, seed, h->stream)
+                           : launch_init<float>(fields_of<float>(h, 0), h->p.N, h->p.sigma, seed, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_init launch");
+        h->ready = true;
+        return AH_OK;
+    });
 }
 
 int ah_set_state(ah_handle* h, const double* host_soa, int64_t step)
 {
-    if (!h || !host_soa || step < 0) return fail(h, AH_E_INVAL, "ah_set_state: bad argument");
-    DeviceGuard g(h->device);
-    hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "ah_set_state sync");
-    h->cur = 0;
-    const size_t V = (size_t)h->V;
-    std::vector<float> tmp;
-    if (h->real_bytes == 4) tmp.resize(V);
-    for (int c = 0; c < 10; ++c) {
-        const double* src = host_soa + (size_t)c * V;
-        if (h->real_bytes == 8) {
-            e = hipMemcpyAsync(comp_ptr(h, c), src, V * 8, hipMemcpyHostToDevice, h->stream);
-        } else {
-            for (size_t i = 0; i < V; ++i) tmp[i] = (float)src[i];
-            e = hipMemcpyAsync(comp_ptr(h, c), tmp.data(), V * 4, hipMemcpyHostToDevice, h->stream);
-        }
-        if (e != hipSuccess) return hip_fail(h, e, "ah_set_state copy");
-        e = hipStreamSynchronize(h->stream);
+    return no_throw([&]() -> int {
+        if (!h || !host_soa || step < 0) return fail(h, AH_E_INVAL, "ah_set_state: bad argument");
+        DeviceGuard g(h->device);
+        hipError_t e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "ah_set_state sync");
-    }
-    h->step = step;
-    h->ready = true;
-    return AH_OK;
+        h->cur = 0;
+        const size_t V = (size_t)h->V;
+        std::vector<float> tmp;
+        if (h->real_bytes == 4) tmp.resize(V);
+        for (int c = 0; c < 10; ++c) {
+            const double* src = host_soa + (size_t)c * V;
+            if (h->real_bytes == 8) {
+                e = hipMemcpyAsync(comp_ptr(h, c), src, V * 8, hipMemcpyHostToDevice, h->stream);
+            } else {
+                for (size_t i = 0; i < V; ++i) tmp[i] = (float)src[i];
+                e = hipMemcpyAsync(comp_ptr(h, c), tmp.data(), V * 4, hipMemcpyHostToDevice, h->stream);
+            }
+            if (e != hipSuccess) return hip_fail(h, e, "ah_set_state copy");
+            e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "ah_set_state sync");
+        }
+        h->step = step;
+        h->ready = true;
+        return AH_OK;
+    });
 }
 
 int ah_get_state(ah_handle* h, double* host_soa, int64_t* step)
 {
-    if (!h || !host_soa) return fail(h, AH_E_INVAL, "ah_get_state: bad argument");
-    if (!h->ready) return fail(h, AH_E_STATE, "ah_get_state before ah_init/ah_set_state");
-    DeviceGuard g(h->device);
-    const size_t V = (size_t)h->V;
-    std::vector<float> tmp;
-    if (h->real_bytes == 4) tmp.resize(V);
-    for (int c = 0; c < 10; ++c) {
-        double* dst = host_soa + (size_t)c * V;
-        hipError_t e;
-        if (h->real_bytes == 8) {
-            e = hipMemcpyAsync(dst, comp_ptr(h, c), V * 8, hipMemcpyDeviceToHost, h->stream);
-        } else {
-            e = hipMemcpyAsync(tmp.data(), comp_ptr(h, c), V * 4, hipMemcpyDeviceToHost, h->stream);
+    return no_throw([&]() -> int {
+        if (!h || !host_soa) return fail(h, AH_E_INVAL, "ah_get_state: bad argument");
+        if (!h->ready) return fail(h, AH_E_STATE, "ah_get_state before ah_init/ah_set_state");
+        DeviceGuard g(h->device);
+        const size_t V = (size_t)h->V;
+        std::vector<float> tmp;
+        if (h->real_bytes == 4) tmp.resize(V);
+        for (int c = 0; c < 10; ++c) {
+            double* dst = host_soa + (size_t)c * V;
+            hipError_t e;
+            if (h->real_bytes == 8) {
+                e = hipMemcpyAsync(dst, comp_ptr(h, c), V * 8, hipMemcpyDeviceToHost, h->stream);
+            } else {
+                e = hipMemcpyAsync(tmp.data(), comp_ptr(h, c), V * 4, hipMemcpyDeviceToHost, h->stream);
+            }
+            if (e != hipSuccess) return hip_fail(h, e, "ah_get_state copy");
+            e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "ah_get_state sync");
+            if (h->real_bytes == 4)
+                for (size_t i = 0; i < V; ++i) dst[i] = (double)tmp[i];
         }
-        if (e != hipSuccess) return hip_fail(h, e, "ah_get_state copy");
-        e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) return hip_fail(h, e, "ah_get_state sync");
-        if (h->real_bytes == 4)
-            for (size_t i = 0; i < V; ++i) dst[i] = (double)tmp[i];
-    }
-    if (step) *step = h->step;
-    return AH_OK;
+        if (step) *step = h->step;
+        return AH_OK;
+    });
 }
 
 int ah_gather(ah_handle* h, const int64_t* sites, int64_t count, double* host_out)
 {
-    if (!h || count < 0 || (count > 0 && (!sites || !host_out))) return fail(h, AH_E_INVAL, "ah_gather: bad argument");
-    if (!h->ready) return fail(h, AH_E_STATE, "ah_gather before ah_init/ah_set_state");
-    for (int64_t k = 0; k < count; ++k)
-        if (sites[k] < 0 || sites[k] >= h->V) return fail(h, AH_E_INVAL, "ah_gather: site index out of range");
-    if (count == 0) return AH_OK;
-    DeviceGuard g(h->device);
-    void* d_sites = nullptr;
-    void* d_out = nullptr;
-    const size_t rb = h->real_bytes;
-    hipError_t e = hipMalloc(&d_sites, count * sizeof(int64_t));
-    if (e == hipSuccess) e = hipMalloc(&d_out, count * 10 * rb);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        if (d_sites) (void)hipFree(d_sites);
-        return fail(h, AH_E_NOMEM, "ah_gather: cannot allocate the temporary buffers");
-    }
-    std::vector<float> tmp(rb == 4 ? count * 10 : 0);
-    e = hipMemcpyAsync(d_sites, sites, count * sizeof(int64_t), hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-        e = rb == 8 ? launch_gather<double>(fields_of<double>(h, h->cur), (const int64_t*)d_sites, count, h->V,
-                                            (double*)d_out, h->stream)
-                    : launch_gather<float>(fields_of<float>(h, h->cur), (const int64_t*)d_sites, count, h->V,
-                                           (float*)d_out, h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(rb == 8 ? (void*)host_out : (void*)tmp.data(), d_out, count * 10 * rb,
-                           hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    (void)hipFree(d_sites);
-    (void)hipFree(d_out);
-    if (e != hipSuccess) return hip_fail(h, e, "ah_gather");
-    if (rb == 4)
-        for (int64_t q = 0; q < count * 10; ++q) host_out[q] = (double)tmp[q];
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h || count < 0 || (count > 0 && (!sites || !host_out))) return fail(h, AH_E_INVAL, "ah_gather: bad argument");
+        if (!h->ready) return fail(h, AH_E_STATE, "ah_gather before ah_init/ah_set_state");
+        for (int64_t k = 0; k < count; ++k)
+            if (sites[k] < 0 || sites[k] >= h->V) return fail(h, AH_E_INVAL, "ah_gather: site index out of range");
+        if (count == 0) return AH_OK;
+        DeviceGuard g(h->device);
+        void* d_sites = nullptr;
+        void* d_out = nullptr;
+        const size_t rb = h->real_bytes;
+        std::vector<float> tmp(rb == 4 ? count * 10 : 0);  // host staging first: a throw after hipMalloc would leak
+        hipError_t e = hipMalloc(&d_sites, count * sizeof(int64_t));
+        if (e == hipSuccess) e = hipMalloc(&d_out, count * 10 * rb);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (d_sites) (void)hipFree(d_sites);
+            return fail(h, AH_E_NOMEM, "ah_gather: cannot allocate the temporary buffers");
+        }
+        e = hipMemcpyAsync(d_sites, sites, count * sizeof(int64_t), hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess)
+            e = rb == 8 ? launch_gather<double>(fields_of<double>(h, h->cur), (const int64_t*)d_sites, count, h->V,
+                                                (double*)d_out, h->stream)
+                        : launch_gather<float>(fields_of<float>(h, h->cur), (const int64_t*)d_sites, count, h->V,
+                                               (float*)d_out, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(rb == 8 ? (void*)host_out : (void*)tmp.data(), d_out, count * 10 * rb,
+                               hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        (void)hipFree(d_sites);
+        (void)hipFree(d_out);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_gather");
+        if (rb == 4)
+            for (int64_t q = 0; q < count * 10; ++q) host_out[q] = (double)tmp[q];
+        return AH_OK;
+    });
 }
 
 int ah_get_step(const ah_handle* h, int64_t* step)
@@ -742,166 +758,182 @@ int ah_get_step(const ah_handle* h, int64_t* step)
 
 int ah_step(ah_handle* h, int64_t nsteps)
 {
-    if (!h || nsteps < 0) return fail(h, AH_E_INVAL, "ah_step: bad argument");
-    if (!h->ready) return fail(h, AH_E_STATE, "ah_step before ah_init/ah_set_state");
-    DeviceGuard g(h->device);
-    for (int64_t k = 0; k < nsteps; ++k) {
-        hipError_t e = h->p.precision == AH_FP64 ? do_step<double>(h) : do_step<float>(h);
-        if (e != hipSuccess) return hip_fail(h, e, "ah_step launch");
-    }
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h || nsteps < 0) return fail(h, AH_E_INVAL, "ah_step: bad argument");
+        if (!h->ready) return fail(h, AH_E_STATE, "ah_step before ah_init/ah_set_state");
+        DeviceGuard g(h->device);
+        for (int64_t k = 0; k < nsteps; ++k) {
+            hipError_t e = h->p.precision == AH_FP64 ? do_step<double>(h) : do_step<float>(h);
+            if (e != hipSuccess) return hip_fail(h, e, "ah_step launch");
+        }
+        return AH_OK;
+    });
 }
 
 int ah_step_measured(ah_handle* h, int64_t nsteps, int32_t measure_every, ah_measurement* series, int32_t cap,
                      int32_t* n)
 {
-    if (!h || nsteps < 0 || measure_every <= 0 || !n || (cap > 0 && !series))
-        return fail(h, AH_E_INVAL, "ah_step_measured: bad argument");
-    if (!h->ready) return fail(h, AH_E_STATE, "ah_step_measured before ah_init/ah_set_state");
-    if (h->p.gauge_action != AH_COMPACT)
-        return fail(h, AH_E_INVAL, "ah_step_measured: fused diagnostics need the compact action");
-    int64_t due = 0;
-    for (int64_t k = 0; k < nsteps; ++k)
-        if ((h->step + k) % measure_every == 0) ++due;
-    if (due > cap) return fail(h, AH_E_INVAL, "ah_step_measured: more due snapshots than cap");
-    DeviceGuard g(h->device);
-    int32_t written = 0;
-    std::vector<int64_t> steps;
-    auto flush = [&]() -> hipError_t {
-        if (steps.empty()) return hipSuccess;
-        hipError_t e = hipMemcpyAsync(h->host_series, h->series, steps.size() * kMeasStride * sizeof(double),
-                                      hipMemcpyDeviceToHost, h->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) return e;
-        for (size_t j = 0; j < steps.size(); ++j)
-            to_measurement(h->p, steps[j], h->host_series + j * kMeasStride, h->V, &series[written++]);
-        steps.clear();
-        return hipSuccess;
-    };
-    for (int64_t k = 0; k < nsteps; ++k) {
-        hipError_t e;
-        if (h->step % measure_every == 0) {
-            if ((int)steps.size() == kSeriesCap) {
-                e = flush();
-                if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured copy");
+    return no_throw([&]() -> int {
+        if (!h || nsteps < 0 || measure_every <= 0 || !n || (cap > 0 && !series))
+            return fail(h, AH_E_INVAL, "ah_step_measured: bad argument");
+        if (!h->ready) return fail(h, AH_E_STATE, "ah_step_measured before ah_init/ah_set_state");
+        if (h->p.gauge_action != AH_COMPACT)
+            return fail(h, AH_E_INVAL, "ah_step_measured: fused diagnostics need the compact action");
+        int64_t due = 0;
+        for (int64_t k = 0; k < nsteps; ++k)
+            if ((h->step + k) % measure_every == 0) ++due;
+        if (due > cap) return fail(h, AH_E_INVAL, "ah_step_measured: more due snapshots than cap");
+        DeviceGuard g(h->device);
+        int32_t written = 0;
+        std::vector<int64_t> steps;
+        auto flush = [&]() -> hipError_t {
+            if (steps.empty()) return hipSuccess;
+            hipError_t e = hipMemcpyAsync(h->host_series, h->series, steps.size() * kMeasStride * sizeof(double),
+                                          hipMemcpyDeviceToHost, h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) return e;
+            for (size_t j = 0; j < steps.size(); ++j)
+                to_measurement(h->p, steps[j], h->host_series + j * kMeasStride, h->V, &series[written++]);
+            steps.clear();
+            return hipSuccess;
+        };
+        for (int64_t k = 0; k < nsteps; ++k) {
+            hipError_t e;
+            if (h->step % measure_every == 0) {
+                if ((int)steps.size() == kSeriesCap) {
+                    e = flush();
+                    if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured copy");
+                }
+                steps.push_back(h->step);
+                double* dst = h->series + (steps.size() - 1) * kMeasStride;
+                e = h->p.precision == AH_FP64 ? measured_pass<double>(h, dst, true) : measured_pass<float>(h, dst, true);
+            } else {
+                e = h->p.precision == AH_FP64 ? do_step<double>(h) : do_step<float>(h);
             }
-            steps.push_back(h->step);
-            double* dst = h->series + (steps.size() - 1) * kMeasStride;
-            e = h->p.precision == AH_FP64 ? measured_pass<double>(h, dst, true) : measured_pass<float>(h, dst, true);
-        } else {
-            e = h->p.precision == AH_FP64 ? do_step<double>(h) : do_step<float>(h);
+            if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured launch");
         }
-        if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured launch");
-    }
-    hipError_t e = flush();
-    if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured copy");
-    *n = written;
-    return AH_OK;
+        hipError_t e = flush();
+        if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured copy");
+        *n = written;
+        return AH_OK;
+    });
 }
 
 int ah_get_timing_split(ah_handle* h, double* measured_ms, int64_t* measured_launches)
 {
-    if (!h || !measured_ms || !measured_launches) return fail(h, AH_E_INVAL, "ah_get_timing_split: bad argument");
-    DeviceGuard g(h->device);
-    hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing_split sync");
-    double tot = 0.0;
-    for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
-        if (!h->ev_measured[k / 2]) continue;
-        float ms = 0.0f;
-        e = hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]);
-        if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing_split elapsed");
-        tot += ms;
-    }
-    *measured_ms = tot;
-    *measured_launches = h->measured_launches;
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h || !measured_ms || !measured_launches) return fail(h, AH_E_INVAL, "ah_get_timing_split: bad argument");
+        DeviceGuard g(h->device);
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing_split sync");
+        double tot = 0.0;
+        for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+            if (!h->ev_measured[k / 2]) continue;
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]);
+            if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing_split elapsed");
+            tot += ms;
+        }
+        *measured_ms = tot;
+        *measured_launches = h->measured_launches;
+        return AH_OK;
+    });
 }
 
 int ah_measure(ah_handle* h, ah_measurement* out)
 {
-    if (!h || !out) return fail(h, AH_E_INVAL, "ah_measure: bad argument");
-    if (!h->ready) return fail(h, AH_E_STATE, "ah_measure before ah_init/ah_set_state");
-    DeviceGuard g(h->device);
-    const ah_params& p = h->p;
-    hipError_t e;
-    if (p.gauge_action == AH_COMPACT) {
-        e = p.precision == AH_FP64 ? measured_pass<double>(h, h->result, false)
-                                   : measured_pass<float>(h, h->result, false);
-    } else {
-        const StepCoef c = coef_at(p, h->step);
-        const MeasConst mc = meas_const(p, h->step);
-        e = p.precision == AH_FP64 ? launch_measure<double>(fields_of<double>(h, h->cur), lconst(p), c, mc,
-                                                            h->partials, h->result, h->stream)
-                                   : launch_measure<float>(fields_of<float>(h, h->cur), lconst(p), c, mc,
-                                                           h->partials, h->result, h->stream);
-    }
-    if (e != hipSuccess) return hip_fail(h, e, "ah_measure launch");
-    e = hipMemcpyAsync(h->host_result, h->result, M_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "ah_measure copy");
-    e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "ah_measure sync");
-    to_measurement(p, h->step, h->host_result, h->V, out);
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h || !out) return fail(h, AH_E_INVAL, "ah_measure: bad argument");
+        if (!h->ready) return fail(h, AH_E_STATE, "ah_measure before ah_init/ah_set_state");
+        DeviceGuard g(h->device);
+        const ah_params& p = h->p;
+        hipError_t e;
+        if (p.gauge_action == AH_COMPACT) {
+            e = p.precision == AH_FP64 ? measured_pass<double>(h, h->result, false)
+                                       : measured_pass<float>(h, h->result, false);
+        } else {
+            const StepCoef c = coef_at(p, h->step);
+            const MeasConst mc = meas_const(p, h->step);
+            e = p.precision == AH_FP64 ? launch_measure<double>(fields_of<double>(h, h->cur), lconst(p), c, mc,
+                                                                h->partials, h->result, h->stream)
+                                       : launch_measure<float>(fields_of<float>(h, h->cur), lconst(p), c, mc,
+                                                               h->partials, h->result, h->stream);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "ah_measure launch");
+        e = hipMemcpyAsync(h->host_result, h->result, M_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_measure copy");
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_measure sync");
+        to_measurement(p, h->step, h->host_result, h->V, out);
+        return AH_OK;
+    });
 }
 
 int ah_get_winding(ah_handle* h, int8_t* host_w)
 {
-    if (!h || !host_w) return fail(h, AH_E_INVAL, "ah_get_winding: bad argument");
-    if (!h->ready) return fail(h, AH_E_STATE, "ah_get_winding before ah_init/ah_set_state");
-    DeviceGuard g(h->device);
-    int8_t* d = nullptr;
-    const size_t bytes = 3 * (size_t)h->V;
-    hipError_t e = hipMalloc(&d, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(h, AH_E_NOMEM, "ah_get_winding: cannot allocate the temporary winding buffer");
-    }
-    e = h->p.precision == AH_FP64 ? launch_winding<double>(fields_of<double>(h, h->cur), lconst(h->p), d, h->stream)
-                                  : launch_winding<float>(fields_of<float>(h, h->cur), lconst(h->p), d, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(host_w, d, bytes, hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    hipError_t e2 = hipFree(d);
-    if (e != hipSuccess) return hip_fail(h, e, "ah_get_winding");
-    if (e2 != hipSuccess) return hip_fail(h, e2, "ah_get_winding free");
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h || !host_w) return fail(h, AH_E_INVAL, "ah_get_winding: bad argument");
+        if (!h->ready) return fail(h, AH_E_STATE, "ah_get_winding before ah_init/ah_set_state");
+        DeviceGuard g(h->device);
+        int8_t* d = nullptr;
+        const size_t bytes = 3 * (size_t)h->V;
+        hipError_t e = hipMalloc(&d, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, AH_E_NOMEM, "ah_get_winding: cannot allocate the temporary winding buffer");
+        }
+        e = h->p.precision == AH_FP64 ? launch_winding<double>(fields_of<double>(h, h->cur), lconst(h->p), d, h->stream)
+                                      : launch_winding<float>(fields_of<float>(h, h->cur), lconst(h->p), d, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(host_w, d, bytes, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        hipError_t e2 = hipFree(d);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_get_winding");
+        if (e2 != hipSuccess) return hip_fail(h, e2, "ah_get_winding free");
+        return AH_OK;
+    });
 }
 
 int ah_synchronize(ah_handle* h)
 {
-    if (!h) return AH_E_INVAL;
-    DeviceGuard g(h->device);
-    hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "ah_synchronize");
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h) return AH_E_INVAL;
+        DeviceGuard g(h->device);
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_synchronize");
+        return AH_OK;
+    });
 }
 
 int ah_set_timing(ah_handle* h, int enable)
 {
-    if (!h) return AH_E_INVAL;
-    h->timing = enable != 0;
-    h->ev_used = 0;
-    h->measured_launches = 0;
-    h->ev_measured.clear();
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h) return AH_E_INVAL;
+        h->timing = enable != 0;
+        h->ev_used = 0;
+        h->measured_launches = 0;
+        h->ev_measured.clear();
+        return AH_OK;
+    });
 }
 
 int ah_get_timing(ah_handle* h, double* total_ms, int64_t* launches)
 {
-    if (!h || !total_ms || !launches) return fail(h, AH_E_INVAL, "ah_get_timing: bad argument");
-    DeviceGuard g(h->device);
-    hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing sync");
-    double tot = 0.0;
-    for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
-        float ms = 0.0f;
-        e = hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]);
-        if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing elapsed");
-        tot += ms;
-    }
-    *total_ms = tot;
-    *launches = (int64_t)(h->ev_used / 2);
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!h || !total_ms || !launches) return fail(h, AH_E_INVAL, "ah_get_timing: bad argument");
+        DeviceGuard g(h->device);
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing sync");
+        double tot = 0.0;
+        for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]);
+            if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing elapsed");
+            tot += ms;
+        }
+        *total_ms = tot;
+        *launches = (int64_t)(h->ev_used / 2);
+        return AH_OK;
+    });
 }
 
 int ah_destroy(ah_handle* h)

@@ -45,128 +45,142 @@ bool tuned_config(const ah_params& p, ah_step_config* out)
 }
 }  // namespace ah
 
+using ah::no_throw;
+
 extern "C" {
 
 int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double* best_ms)
 {
-    if (!p || steps <= 0) return AH_E_INVAL;
-    if (p->gauge_action != AH_COMPACT) return AH_E_INVAL;
-    ah_handle* h = nullptr;
-    int rc = ah_create(p, nullptr, 0, nullptr, &h);
-    if (rc != AH_OK) return rc;
-    rc = ah_init(h, 0);
-    std::vector<std::pair<int, int>> tiles = {{64, 8}, {64, 4}, {32, 8}, {128, 4}};
-    if (p->precision == AH_FP32) {
-        tiles.push_back({64, 16});
-        tiles.push_back({128, 8});
-    }
-    std::vector<int> zcs = {0, p->N};
-    for (int div : {2, 4, 8})
-        if (p->N / div >= 8) zcs.push_back(p->N / div);
-    ah_step_config bcfg{};
-    double bms = 1e300;
-    for (auto& t : tiles) {
-        for (int zc : zcs) {
-            if (rc != AH_OK) break;
-            ah_step_config c{AH_KERNEL_TILE, t.first, t.second, zc};
-            if (ah_set_step_config(h, &c) != AH_OK) continue;
-            rc = ah_step(h, 2);
-            if (rc == AH_OK) rc = ah_set_timing(h, 1);
-            if (rc == AH_OK) rc = ah_step(h, steps);
-            double ms = 0.0;
-            int64_t n = 0;
-            if (rc == AH_OK) rc = ah_get_timing(h, &ms, &n);
-            if (rc == AH_OK) rc = ah_set_timing(h, 0);
-            if (rc == AH_OK && n > 0 && ms / n < bms) {
-                bms = ms / n;
-                (void)ah_get_step_config(h, &bcfg);
+    return no_throw([&]() -> int {
+        if (!p || steps <= 0) return AH_E_INVAL;
+        if (p->gauge_action != AH_COMPACT) return AH_E_INVAL;
+        ah_handle* h = nullptr;
+        int rc = ah_create(p, nullptr, 0, nullptr, &h);
+        if (rc != AH_OK) return rc;
+        rc = ah_init(h, 0);
+        std::vector<std::pair<int, int>> tiles = {{64, 8}, {64, 4}, {32, 8}, {128, 4}};
+        if (p->precision == AH_FP32) {
+            tiles.push_back({64, 16});
+            tiles.push_back({128, 8});
+        }
+        std::vector<int> zcs = {0, p->N};
+        for (int div : {2, 4, 8})
+            if (p->N / div >= 8) zcs.push_back(p->N / div);
+        ah_step_config bcfg{};
+        double bms = 1e300;
+        for (auto& t : tiles) {
+            for (int zc : zcs) {
+                if (rc != AH_OK) break;
+                ah_step_config c{AH_KERNEL_TILE, t.first, t.second, zc};
+                if (ah_set_step_config(h, &c) != AH_OK) continue;
+                rc = ah_step(h, 2);
+                if (rc == AH_OK) rc = ah_set_timing(h, 1);
+                if (rc == AH_OK) rc = ah_step(h, steps);
+                double ms = 0.0;
+                int64_t n = 0;
+                if (rc == AH_OK) rc = ah_get_timing(h, &ms, &n);
+                if (rc == AH_OK) rc = ah_set_timing(h, 0);
+                if (rc == AH_OK && n > 0 && ms / n < bms) {
+                    bms = ms / n;
+                    (void)ah_get_step_config(h, &bcfg);
+                }
             }
         }
-    }
-    ah_destroy(h);
-    if (rc != AH_OK) return rc;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_table[{p->precision, p->N}] = Entry{bcfg, bms};
-    }
-    if (best) *best = bcfg;
-    if (best_ms) *best_ms = bms;
-    return AH_OK;
+        ah_destroy(h);
+        if (rc != AH_OK) return rc;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_table[{p->precision, p->N}] = Entry{bcfg, bms};
+        }
+        if (best) *best = bcfg;
+        if (best_ms) *best_ms = bms;
+        return AH_OK;
+    });
 }
 
 int ah_tune_lookup(const ah_params* p, ah_step_config* out)
 {
-    if (!p || !out) return AH_E_INVAL;
-    return ah::tuned_config(*p, out) ? AH_OK : AH_E_AGAIN;
+    return no_throw([&]() -> int {
+        if (!p || !out) return AH_E_INVAL;
+        return ah::tuned_config(*p, out) ? AH_OK : AH_E_AGAIN;
+    });
 }
 
 int ah_tune_set(const ah_params* p, const ah_step_config* c)
 {
-    if (!p || !c) return AH_E_INVAL;
-    if (!ah::valid_entry(p->precision, p->N, *c)) return AH_E_INVAL;
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_table[{p->precision, p->N}] = Entry{*c, 0.0};
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!p || !c) return AH_E_INVAL;
+        if (!ah::valid_entry(p->precision, p->N, *c)) return AH_E_INVAL;
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table[{p->precision, p->N}] = Entry{*c, 0.0};
+        return AH_OK;
+    });
 }
 
 int ah_tune_clear(void)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_table.clear();
-    return AH_OK;
+    return no_throw([&]() -> int {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table.clear();
+        return AH_OK;
+    });
 }
 
 int ah_tune_save(const char* path)
 {
-    if (!path) return AH_E_INVAL;
-    FILE* f = std::fopen(path, "w");
-    if (!f) return AH_E_INVAL;
-    std::lock_guard<std::mutex> lk(g_mu);
-    std::fprintf(f, "{\"version\": 1, \"entries\": [\n");
-    size_t i = 0;
-    for (auto& kv : g_table) {
-        std::fprintf(f, "{\"precision\": \"%s\", \"N\": %d, \"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, \"ms\": %.6g}%s\n",
-                     kv.first.first == AH_FP64 ? "fp64" : "fp32", kv.first.second, kv.second.cfg.tile_x,
-                     kv.second.cfg.tile_y, kv.second.cfg.zchunk, kv.second.ms, ++i < g_table.size() ? "," : "");
-    }
-    std::fprintf(f, "]}\n");
-    std::fclose(f);
-    return AH_OK;
+    return no_throw([&]() -> int {
+        if (!path) return AH_E_INVAL;
+        FILE* f = std::fopen(path, "w");
+        if (!f) return AH_E_INVAL;
+        std::lock_guard<std::mutex> lk(g_mu);
+        std::fprintf(f, "{\"version\": 1, \"entries\": [\n");
+        size_t i = 0;
+        for (auto& kv : g_table) {
+            std::fprintf(f, "{\"precision\": \"%s\", \"N\": %d, \"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, \"ms\": %.6g}%s\n",
+                         kv.first.first == AH_FP64 ? "fp64" : "fp32", kv.first.second, kv.second.cfg.tile_x,
+                         kv.second.cfg.tile_y, kv.second.cfg.zchunk, kv.second.ms, ++i < g_table.size() ? "," : "");
+        }
+        std::fprintf(f, "]}\n");
+        std::fclose(f);
+        return AH_OK;
+    });
 }
 
 int ah_tune_load(const char* path)
 {
-    if (!path) return AH_E_INVAL;
-    FILE* f = std::fopen(path, "r");
-    if (!f) return AH_E_INVAL;
-    // every entry line is checked before any is taken: a file with a bad
-    // entry changes nothing
-    char line[512];
-    std::vector<std::pair<std::pair<int, int>, Entry>> got;
-    bool bad = false;
-    while (std::fgets(line, sizeof(line), f)) {
-        if (!std::strstr(line, "\"precision\"")) continue;
-        char prec[8] = {0};
-        int N, tx, ty, zc;
-        double ms;
-        if (std::sscanf(line, " {\"precision\": \"%7[a-z0-9]\", \"N\": %d, \"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, \"ms\": %lf",
-                        prec, &N, &tx, &ty, &zc, &ms) != 6) {
-            bad = true;
-            continue;
+    return no_throw([&]() -> int {
+        if (!path) return AH_E_INVAL;
+        FILE* f = std::fopen(path, "r");
+        if (!f) return AH_E_INVAL;
+        // every entry line is checked before any is taken: a file with a bad
+        // entry changes nothing
+        char line[512];
+        std::vector<std::pair<std::pair<int, int>, Entry>> got;
+        bool bad = false;
+        while (std::fgets(line, sizeof(line), f)) {
+            if (!std::strstr(line, "\"precision\"")) continue;
+            char prec[8] = {0};
+            int N, tx, ty, zc;
+            double ms;
+            if (std::sscanf(line, " {\"precision\": \"%7[a-z0-9]\", \"N\": %d, \"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, \"ms\": %lf",
+                            prec, &N, &tx, &ty, &zc, &ms) != 6) {
+                bad = true;
+                continue;
+            }
+            const int pr = std::strcmp(prec, "fp64") == 0 ? AH_FP64 : (std::strcmp(prec, "fp32") == 0 ? AH_FP32 : -1);
+            const ah_step_config c{AH_KERNEL_TILE, tx, ty, zc};
+            if (!ah::valid_entry(pr, N, c)) {
+                bad = true;
+                continue;
+            }
+            got.push_back({{pr, N}, Entry{c, ms}});
         }
-        const int pr = std::strcmp(prec, "fp64") == 0 ? AH_FP64 : (std::strcmp(prec, "fp32") == 0 ? AH_FP32 : -1);
-        const ah_step_config c{AH_KERNEL_TILE, tx, ty, zc};
-        if (!ah::valid_entry(pr, N, c)) {
-            bad = true;
-            continue;
-        }
-        got.push_back({{pr, N}, Entry{c, ms}});
-    }
-    std::fclose(f);
-    if (bad) return AH_E_INVAL;
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (auto& kv : got) g_table[kv.first] = kv.second;
-    return AH_OK;
+        std::fclose(f);
+        if (bad) return AH_E_INVAL;
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& kv : got) g_table[kv.first] = kv.second;
+        return AH_OK;
+    });
 }
 
 }  // extern "C"

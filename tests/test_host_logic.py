@@ -73,6 +73,10 @@ def test_pool_footprint_accounts_for_everything(ah):
     assert ah.pool_footprint(p32, 1000, 10) > f32  # coefficient table and series grow with steps
     with pytest.raises(ah.AHError):
         ah.pool_footprint(ah.Params(N=64, gauge_action="noncompact"), 10, 1)
+    # a step count whose coefficient table could not be addressed is refused, not wrapped round
+    for nsteps in (2 ** 62, 2 ** 63 - 1):
+        with pytest.raises(ah.AHError):
+            ah.pool_footprint(p32, nsteps, 10)
 
 
 def test_request_stream_recipe(ah):
