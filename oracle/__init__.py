@@ -7,8 +7,8 @@ leg do.  It shares no code with the GPU library.
 It follows section 2 of Correia & Martins, "Abelian-Higgs cosmic string
 evolution with multiple GPUs": the Crank-Nicolson kicks of Pi and E, the
 drifts of phi and A, link variables, the covariant Laplacian, the plaquette
-field strength, and the diagnostics xi_L, xi_W, <v^2>_phi plus energy and
-the Gauss-law residual.  All arithmetic lives in ahref.c; this module only
+field strength, and the diagnostics xi_L, xi_W, <v^2>_phi, <v^2>_omega plus
+energy and the Gauss-law residual.  All arithmetic lives in ahref.c; this module only
 marshals arguments.
 
 Pins (what fixes the oracle other than itself) live in tests/test_oracle_*.py.
@@ -51,7 +51,7 @@ class _Meas(ctypes.Structure):
         ("energy", ctypes.c_double), ("e_kin", ctypes.c_double), ("e_grad", ctypes.c_double),
         ("e_pot", ctypes.c_double), ("e_el", ctypes.c_double), ("e_mag", ctypes.c_double),
         ("gauss_rms", ctypes.c_double), ("gauss_max", ctypes.c_double), ("gauss_rel", ctypes.c_double),
-        ("nonfinite", ctypes.c_int64),
+        ("nonfinite", ctypes.c_int64), ("v2_omega", ctypes.c_double),
     ]
 
 

@@ -406,7 +406,7 @@ void ahref_gauss(const ahref_params* p, const double* st, int64_t n, double* G)
 
 enum {
     S_KIN, S_GRAD, S_POT, S_EL, S_MAG, S_L, S_KINL, S_GRADL,
-    S_G2, S_DIV2, S_CRHO2, S_GMAX, S_WABS, S_NONFIN, S_COUNT
+    S_G2, S_DIV2, S_CRHO2, S_GMAX, S_WABS, S_NONFIN, S_PL, S_RHOL, S_COUNT
 };
 
 /* Site densities of snapshot n with centred momenta (the average of the
@@ -416,7 +416,10 @@ enum {
  *   kinetic |Pi|^2, gradient sum_i |D_i^+ phi|^2, potential (lambda0 f/4)(|phi|^2-sigma^2)^2,
  *   electric sum_i E_i^2 / (2 e0^2 f), magnetic sum_{i<j} B_ij^2 / (2 e0^2 f)
  *   with B^2 = 2 (1 - cos Theta)/dx^4 (compact) or Theta^2/dx^4.
- * The Lagrangian density is kin - grad - pot + el - mag. */
+ * The Lagrangian density is kin - grad - pot + el - mag, the energy density
+ * rho = kin + grad + pot + el + mag, and the pressure p (a third of the trace
+ * of the spatial stress tensor of the scalar and gauge fields)
+ * p = kin - grad/3 - pot + (el + mag)/3. */
 static void site_measure(const ahref_params* p, const ahref_scalars* sc, const double* st, int64_t V,
                          const int x[3], double gc, double acc[S_COUNT])
 {
@@ -462,6 +465,10 @@ static void site_measure(const ahref_params* p, const ahref_scalars* sc, const d
     mag *= inv2e2f;
 
     double L = kin - grad - pot + el - mag;
+    double rho = kin + grad + pot + el + mag;
+    double pres = kin - grad / 3.0 - pot + (el + mag) / 3.0;
+    acc[S_PL] += pres * L;
+    acc[S_RHOL] += rho * L;
     acc[S_KIN] += kin;
     acc[S_GRAD] += grad;
     acc[S_POT] += pot;
@@ -536,6 +543,9 @@ void ahref_measure(const ahref_params* p, const double* st, int64_t n, ahref_mea
     out->xi_L = (out->sum_L < 0.0) ? sqrt(-TWO_PI * p->sigma * p->sigma * vol / out->sum_L) : NAN;
     out->R = tot[S_KINL] / tot[S_GRADL];
     out->v2_phi = 2.0 * out->R / (1.0 + out->R);
+    /* equation-of-state estimator (section 2): w = sum p W / sum rho W with
+     * the Lagrangian density as the weight W, <v^2>_omega = (1 + 3 w)/2 */
+    out->v2_omega = 0.5 * (1.0 + 3.0 * tot[S_PL] / tot[S_RHOL]);
     out->gauss_rms = sqrt(tot[S_G2] / (double)V);
     out->gauss_max = tot[S_GMAX];
     double den = sqrt(tot[S_DIV2] + tot[S_CRHO2]);

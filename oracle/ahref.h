@@ -61,6 +61,7 @@ typedef struct ahref_meas {
     double energy, e_kin, e_grad, e_pot, e_el, e_mag;
     double gauss_rms, gauss_max, gauss_rel;
     int64_t nonfinite;         /* sites with any non-finite field value */
+    double v2_omega;           /* equation-of-state velocity estimator */
 } ahref_meas;
 
 /* per-step scalars at snapshot n (eta_n = eta0 + n*deta) */

@@ -492,6 +492,80 @@ def test_velocity_ratio_plane_wave(oracle_mod):
     assert abs(m["energy"] - (m["e_kin"] + m["e_grad"] + m["e_pot"] + m["e_el"] + m["e_mag"])) < 1e-11 * m["energy"]
 
 
+def test_equation_of_state_velocity_single_terms(oracle_mod):
+    """<v^2>_omega = (1 + 3 w)/2 with w the L-weighted ratio of pressure to
+    energy density.  A state holding one kind of energy only has the textbook
+    equation of state of that kind: kinetic w = 1, gradient w = -1/3 (a static
+    string's transverse gradients), potential w = -1, electric and magnetic
+    radiation w = 1/3.  The stored half-step momenta are chosen so that the
+    centred ones are exactly the wanted ones (m = 0, no damping)."""
+    N, dx, deta = 6, 0.5, 0.1
+    x0, x1, x2 = grid(N)
+    # kinetic only: phi = sigma, uniform Pi, no force on Pi, no current
+    p = oracle_mod.params(N=N, m=0.0, lambda0=0.0, dx=dx, deta=deta)
+    st = np.zeros((10, N ** 3))
+    st[0], st[2], st[3] = 1.0, 0.3, -0.4
+    assert abs(oracle_mod.measure(p, st, 0)["v2_omega"] - 2.0) < 1e-13
+    # potential only: phi = 0 everywhere
+    p = oracle_mod.params(N=N, m=0.0, lambda0=2.0, sigma=1.5, dx=dx, deta=deta)
+    st = np.zeros((10, N ** 3))
+    assert abs(oracle_mod.measure(p, st, 0)["v2_omega"] + 1.0) < 1e-13
+    # electric only: phi = 0, uniform E, no curl and no current
+    p = oracle_mod.params(N=N, m=0.0, lambda0=0.0, e0=0.7, dx=dx, deta=deta)
+    st = np.zeros((10, N ** 3))
+    st[7], st[9] = 0.2, 0.1
+    assert abs(oracle_mod.measure(p, st, 0)["v2_omega"] - 1.0) < 1e-13
+    # magnetic only (compact): A_1 = c x0 with c N dx = 2 pi gives the uniform
+    # plaquette angle Theta_01 = 2 pi / N (the wrap differs by 2 pi); no curl
+    p = oracle_mod.params(N=N, m=0.0, lambda0=0.0, compact=1, dx=dx, deta=deta)
+    st = np.zeros((10, N ** 3))
+    st[5] = 2 * np.pi / (N * dx) * x0
+    m = oracle_mod.measure(p, st, 0)
+    assert abs(m["e_mag"] - N ** 3 * dx ** 3 * (1 - math.cos(2 * math.pi / N)) / dx ** 4) < 1e-12 * m["e_mag"]
+    assert abs(m["v2_omega"] - 1.0) < 1e-12
+    # gradient only: phi = exp(i q x0), A = 0; Pi^{n-1/2} = -deta F / 2 and
+    # E_0^{n-1/2} = -deta e0^2 J_0 make the centred momenta vanish, with the
+    # force F = 2 (cos q - 1) phi / dx^2 and the current J_0 = sin q / dx
+    q = 2 * np.pi * 2 / N
+    e0 = 0.8
+    p = oracle_mod.params(N=N, m=0.0, lambda0=0.0, e0=e0, dx=dx, deta=deta)
+    st = np.zeros((10, N ** 3))
+    st[0], st[1] = np.cos(q * x0), np.sin(q * x0)
+    F = 2 * (math.cos(q) - 1) / dx ** 2
+    st[2], st[3] = -0.5 * deta * F * st[0], -0.5 * deta * F * st[1]
+    st[7] = -deta * e0 ** 2 * math.sin(q) / dx
+    m = oracle_mod.measure(p, st, 0)
+    assert m["e_kin"] < 1e-25 and m["e_el"] < 1e-25
+    assert abs(m["e_grad"] - N ** 3 * dx ** 3 * 2 * (1 - math.cos(q)) / dx ** 2) < 1e-12 * m["e_grad"]
+    assert abs(m["v2_omega"]) < 1e-13
+
+
+def test_equation_of_state_velocity_weighting(oracle_mod):
+    """The sums are weighted by the Lagrangian density, which changes sign:
+    phi = c uniform (potential energy everywhere) with a centred momentum
+    Pi_bar = (u, 0) in the lower half of the box only.  Per site, lower half:
+    rho = u^2 + V, p = u^2 - V, L = u^2 - V; upper half: rho = V, p = -V,
+    L = -V (V = lambda0/4 (c^2 - sigma^2)^2).  Weighting by rho or not at all
+    gives other values."""
+    N, dx, deta, lam, c, u = 6, 0.5, 0.1, 2.0, 0.5, 0.6
+    p = oracle_mod.params(N=N, m=0.0, lambda0=lam, sigma=1.0, dx=dx, deta=deta)
+    x0, x1, x2 = grid(N)
+    lower = x2 < N // 2
+    F = -0.5 * lam * (c * c - 1.0) * c      # force on Pi (real): -(lambda0/2)(|phi|^2 - sigma^2) phi
+    st = np.zeros((10, N ** 3))
+    st[0] = c
+    st[2] = np.where(lower, u, 0.0) - 0.5 * deta * F
+    m = oracle_mod.measure(p, st, 0)
+    V = 0.25 * lam * (c * c - 1.0) ** 2
+    rho_l, p_l, L_l = u * u + V, u * u - V, u * u - V
+    rho_u, p_u, L_u = V, -V, -V
+    w = (p_l * L_l + p_u * L_u) / (rho_l * L_l + rho_u * L_u)
+    assert abs(m["v2_omega"] - 0.5 * (1 + 3 * w)) < 1e-12
+    w_rho = (p_l * rho_l + p_u * rho_u) / (rho_l ** 2 + rho_u ** 2)
+    w_flat = (p_l + p_u) / (rho_l + rho_u)
+    assert abs(0.5 * (1 + 3 * w_rho) - m["v2_omega"]) > 0.1 and abs(0.5 * (1 + 3 * w_flat) - m["v2_omega"]) > 0.1
+
+
 def test_nonfinite_counted(oracle_mod):
     N = 4
     p = oracle_mod.params(N=N)
