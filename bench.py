@@ -112,7 +112,7 @@ def run_gpu(precision, N, steps, warmup, measure_every, seed):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(precision, N, cfg["tile"]),
                      "traffic_unit": "bytes per launch", "algorithmic_bytes": BYTES_PER_SITE[precision] * V},
-        "last_measurement": {k: last[k] for k in ("step", "winding_sum_abs", "xi_W", "xi_L", "v2_phi",
+        "last_measurement": {k: last[k] for k in ("step", "winding_sum_abs", "xi_W", "xi_L", "v2_phi", "v2_omega",
                                                   "energy", "gauss_rel", "nonfinite")},
     }
 

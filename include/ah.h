@@ -22,8 +22,11 @@
  *
  * Diagnostics (section 2, string-separation and velocity estimators):
  * xi_W from gauge-invariant plaquette windings, xi_L from the Lagrangian
- * sum, <v^2>_phi = 2R/(1+R) with the Lagrangian-weighted ratio R, plus the
- * energy split and the discrete Gauss-law residual.
+ * sum, <v^2>_phi = 2R/(1+R) with the Lagrangian-weighted ratio R,
+ * <v^2>_omega = (1 + 3w)/2 with w the Lagrangian-weighted ratio of the
+ * pressure kin - grad/3 - pot + (el + mag)/3 to the energy density (the
+ * paper leaves p, rho and the weight undefined; this is the reading taken),
+ * plus the energy split and the discrete Gauss-law residual.
  *
  * Conventions
  *   - site index idx = x0 + N*(x1 + N*x2); periodic in all three directions.
@@ -103,6 +106,7 @@ typedef struct ah_measurement {
     int64_t nonfinite;          /* sites with a non-finite field value */
     uint32_t flags;             /* AH_FLAG_* */
     uint32_t reserved;
+    double v2_omega;            /* (1 + 3 w)/2, w = sum p L / sum rho L: equation-of-state estimator */
 } ah_measurement;
 
 typedef struct ah_handle ah_handle;

@@ -41,6 +41,7 @@ class ah_measurement(ctypes.Structure):
         ("e_pot", ctypes.c_double), ("e_el", ctypes.c_double), ("e_mag", ctypes.c_double),
         ("gauss_rms", ctypes.c_double), ("gauss_max", ctypes.c_double), ("gauss_rel", ctypes.c_double),
         ("nonfinite", ctypes.c_int64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("v2_omega", ctypes.c_double),
     ]
 
 

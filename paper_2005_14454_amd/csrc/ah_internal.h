@@ -56,16 +56,19 @@ struct LatticeConst {
     double dx, deta, sigma2;
 };
 
-// Diagnostics reduction slots (FP64 sums over sites unless noted).
+// Diagnostics reduction slots (FP64 sums over sites unless noted).  The
+// Lagrangian sum is kin - grad - pot + el - mag of the first five, so it has
+// no slot of its own.
 enum MeasSlot {
     M_KIN = 0,   // |Pi_bar|^2
     M_GRAD,      // sum_i |D_i^+ phi|^2
     M_POT,       // lambda0 f/4 (|phi|^2 - sigma^2)^2
     M_EL,        // sum_i E_bar_i^2 / (2 e0^2 f)
     M_MAG,       // sum_{i<j} B_ij^2 / (2 e0^2 f)
-    M_L,         // Lagrangian density
     M_KINL,      // |Pi_bar|^2 L
     M_GRADL,     // sum_i |D_i^+ phi|^2 L
+    M_PL,        // p L, with the pressure p = kin - grad/3 - pot + (el + mag)/3
+    M_RHOL,      // rho L, with the energy density rho = kin + grad + pot + el + mag
     M_G2,        // G^2
     M_DIV2,      // (div E)^2
     M_CRHO2,     // (c rho)^2
@@ -74,7 +77,9 @@ enum MeasSlot {
     M_NONFIN,    // count of sites with a non-finite value
     M_COUNT
 };
+constexpr int kMarchSums = M_RHOL + 1;  // FP64 sums the measured march forms: slots 0 .. M_RHOL
 constexpr int kMeasStride = 16;        // doubles per partial record
+static_assert(M_COUNT <= kMeasStride, "a record holds every slot");
 constexpr int kMeasBlocks = 2048;      // fixed grid of the measurement kernel
 constexpr int kMeasThreads = 256;
 
@@ -140,7 +145,8 @@ struct WorkItem {
     int lattice, tile;  // lattice < 0: an empty item (padding)
 };
 constexpr int kXcdCount = 8;           // XCDs of the device; block b runs on XCD b % 8
-constexpr int kSeriesStride = 16;      // M_COUNT sums + step index + pad
+constexpr int kSeriesStride = 18;      // M_COUNT sums + step index + pad
+static_assert(M_COUNT + 1 <= kSeriesStride, "a series record holds the sums and the step index");
 
 // ---- launchers (ah_kernels.hip, ah_step_tile.hip) -------------------------
 template <typename R>

@@ -292,9 +292,12 @@ __global__ void __launch_bounds__(kMeasThreads) k_measure(Fields<R> f, int N, in
         acc[M_POT] += pot;
         acc[M_EL] += el;
         acc[M_MAG] += mag;
-        acc[M_L] += L;
         acc[M_KINL] += kin * L;
         acc[M_GRADL] += grad * L;
+        const double pres = (kin - pot) + ((el + mag) - grad) * (1.0 / 3.0);
+        const double rho = ((kin + grad) + pot) + (el + mag);
+        acc[M_PL] += pres * L;
+        acc[M_RHOL] += rho * L;
 
         double dv = 0.0;
         for (int i = 0; i < 3; ++i) dv += (v[7 + i] - (double)elec(f, i)[at(N, shift(c, i, N, -1))]) * inv_dx;

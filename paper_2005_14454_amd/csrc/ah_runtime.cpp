@@ -344,10 +344,11 @@ void to_measurement(const ah_params& p, int64_t step, const double* r, int64_t V
     out->e_el = dx3 * r[M_EL];
     out->e_mag = dx3 * r[M_MAG];
     out->energy = out->e_kin + out->e_grad + out->e_pot + out->e_el + out->e_mag;
-    out->sum_L = dx3 * r[M_L];
+    out->sum_L = dx3 * ((((r[M_KIN] - r[M_GRAD]) - r[M_POT]) + r[M_EL]) - r[M_MAG]);
     out->xi_L = out->sum_L < 0.0 ? std::sqrt(-2.0 * M_PI * p.sigma * p.sigma * vol / out->sum_L) : NAN;
     out->R = r[M_KINL] / r[M_GRADL];
     out->v2_phi = 2.0 * out->R / (1.0 + out->R);
+    out->v2_omega = 0.5 * (1.0 + 3.0 * r[M_PL] / r[M_RHOL]);
     out->gauss_rms = std::sqrt(r[M_G2] / (double)V);
     out->gauss_max = r[M_GMAX];
     const double den = std::sqrt(r[M_DIV2] + r[M_CRHO2]);

@@ -145,7 +145,7 @@ struct MeasShared {
     float Y[2][3][RS];                  // link phases of planes z (ring of two)
     // FP64 lattices: each thread's running diagnostics sums (kept here rather
     // than in registers, which the FP64 measured march runs out of)
-    double acc[8][sizeof(R) == 8 ? TX * TY : 1];
+    double acc[kMarchSums][sizeof(R) == 8 ? TX * TY : 1];
     double red[TX * TY / 64][M_COUNT];  // block reduction
 };
 
@@ -358,9 +358,9 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         else
             return link_phase_f(cmulc(ph, cmul(U, pn)), ph, pn, av, ma.dx);
     };
-    // sums of the march: M_KIN .. M_GRADL (8 slots, FP64) and the exact
-    // counts M_WABS, M_NONFIN (integers); the Gauss slots belong to k_gauss
-    double acc_reg[8];
+    // sums of the march: M_KIN .. M_RHOL (kMarchSums slots, FP64) and the
+    // exact counts M_WABS, M_NONFIN (integers); the Gauss slots belong to k_gauss
+    double acc_reg[kMarchSums];
     auto acc = [&](int k) -> double& {
         if constexpr (sizeof(R) == 8)
             return mx->acc[k][tid];
@@ -369,7 +369,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     };
     int wabs = 0, nonfin = 0;
     if constexpr (MEAS)
-        for (int k = 0; k < 8; ++k) acc(k) = 0.0;
+        for (int k = 0; k < kMarchSums; ++k) acc(k) = 0.0;
     {
         const int64_t pm = plane_of(z0 - 1), p0 = plane_of(z0);
         const R* A[3] = {f.a0, f.a1, f.a2};
@@ -616,9 +616,13 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                     acc(M_POT) += pot_e;
                     acc(M_EL) += el;
                     acc(M_MAG) += mag;
-                    acc(M_L) += L;
                     acc(M_KINL) += kin * L;
                     acc(M_GRADL) += grad * L;
+                    // pressure and energy density for the equation-of-state estimator
+                    const double pres = (kin - pot_e) + ((el + mag) - grad) * (1.0 / 3.0);
+                    const double rho = ((kin + grad) + pot_e) + (el + mag);
+                    acc(M_PL) += pres * L;
+                    acc(M_RHOL) += rho * L;
                 }
             }
             fxz_m = fxz;
@@ -697,10 +701,10 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
 
     if constexpr (MEAS) {
         // fixed-order block reduction of the diagnostics into one record
-        static_assert(M_KIN == 0 && M_GRADL == 7, "march sums occupy slots 0..7");
+        static_assert(M_KIN == 0 && kMarchSums == M_RHOL + 1, "march sums occupy slots 0 .. M_RHOL");
         auto& red = mx->red;
         const int lane = tid & 63, wv = tid >> 6;
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < kMarchSums; ++k) {
             const double r = wave_sum(acc(k));
             if (lane == 0) red[wv][k] = r;
         }
@@ -712,7 +716,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         __syncthreads();
         if (tid < kMeasStride) {
             double r = 0.0;
-            if (tid < 8 || tid == M_WABS || tid == M_NONFIN) {
+            if (tid < kMarchSums || tid == M_WABS || tid == M_NONFIN) {
                 r = red[0][tid];
                 for (int w = 1; w < NT / 64; ++w) r += red[w][tid];
             }

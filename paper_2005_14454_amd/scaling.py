@@ -1,7 +1,8 @@
 """Scaling analysis of string networks: an ensemble of random-phase lattices
 is evolved through a constant expansion era, and the late-time rates
-d xi_L / d eta, d xi_W / d eta and the mean of <v^2>_phi are fitted over a
-conformal-time window, one value per realisation, then averaged.  This is
+d xi_L / d eta, d xi_W / d eta and the means of <v^2>_phi and <v^2>_omega are
+fitted over a conformal-time window, one value per realisation, then
+averaged.  This is
 the validation the paper runs with its code (section 3, Table 1: for 512^3
 boxes in the radiation era the window is eta in [80, 128]).
 
@@ -37,7 +38,7 @@ MANHATTAN = 1.5
 
 
 def analyse(series, window):
-    """Rates and mean velocity of one realisation over the eta window
+    """Rates and mean velocities of one realisation over the eta window
     (dxi_W_iso: the rate of xi_W with the winding count divided by the
     isotropic-orientation factor 3/2)."""
     lo, hi = window
@@ -48,6 +49,7 @@ def analyse(series, window):
     out["dxi_W"] = fit_slope(eta, np.array([m["xi_W"] for m in rows]))
     out["dxi_W_iso"] = out["dxi_W"] * math.sqrt(MANHATTAN)
     out["v2_phi"] = float(np.mean([m["v2_phi"] for m in rows]))
+    out["v2_omega"] = float(np.mean([m["v2_omega"] for m in rows]))
     return out
 
 
@@ -84,7 +86,7 @@ def run_ensemble(N=512, seeds=range(12), m=1.0, precision="fp32", every=5, windo
     fits = {s: analyse(per_seed[s], window) for s in seeds}
     out = {"N": N, "m": m, "precision": precision, "seeds": seeds, "steps": nsteps, "every": every,
            "window": list(window), "per_seed": {str(s): f for s, f in fits.items()}}
-    for k in ("dxi_L", "dxi_W", "dxi_W_iso", "v2_phi"):
+    for k in ("dxi_L", "dxi_W", "dxi_W_iso", "v2_phi", "v2_omega"):
         mu, err = mean_err([f[k] for f in fits.values()])
         out[k] = {"mean": mu, "stderr": err}
     return out

@@ -146,7 +146,8 @@ def test_config1_fp64_100_steps(oracle_mod, ah, config1_reference, config1_round
         gm = lat.measure()
         om = oracle_mod.measure(op, got, 100)
         assert gm["winding_sum_abs"] == om["winding_sum_abs"]
-        for k in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag", "sum_L", "xi_L", "R", "v2_phi", "xi_W"):
+        for k in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag", "sum_L", "xi_L", "R", "v2_phi", "v2_omega",
+                  "xi_W"):
             assert abs(gm[k] - om[k]) <= 1e-11 * abs(om[k]), (k, gm[k], om[k])
         assert gm["gauss_rel"] < 1e-12 and om["gauss_rel"] < 1e-12
         assert gm["nonfinite"] == 0 and gm["flags"] == 0
@@ -170,7 +171,7 @@ def test_config0_series_fp64_fused(oracle_mod, ah):
             st = oracle_mod.step(op, st, n - 10, 10)
         om = oracle_mod.measure(op, st, n)
         assert gm["winding_sum_abs"] == om["winding_sum_abs"], n
-        for key in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag", "sum_L", "R"):
+        for key in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag", "sum_L", "R", "v2_omega"):
             assert abs(gm[key] - om[key]) <= 1e-9 * abs(om[key]) + 1e-12, (n, key, gm[key], om[key])
         assert gm["gauss_rel"] < 1e-12 and om["gauss_rel"] < 1e-12, n
         assert gm["nonfinite"] == 0 and gm["flags"] == 0
@@ -221,6 +222,8 @@ def test_measure_on_random_snapshot(oracle_mod, ah, precision):
     for k in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag", "sum_L"):
         assert abs(gm[k] - om[k]) <= tol_e * scale, (k, gm[k], om[k])
     assert abs(gm["R"] - om["R"]) <= (1e-11 if precision == "fp64" else 1e-4) * abs(om["R"])
+    # the equation-of-state velocity: ratio of L-weighted sums, w = (2 v^2 - 1)/3
+    assert abs(gm["v2_omega"] - om["v2_omega"]) <= (1e-11 if precision == "fp64" else 1e-4) * max(1.0, abs(om["v2_omega"]))
     for k in ("gauss_rms", "gauss_max", "gauss_rel"):
         assert abs(gm[k] - om[k]) <= 1e-11 * abs(om[k]), (k, gm[k], om[k])
 

@@ -147,11 +147,11 @@ def test_scaling_fit_recovers_known_rates():
         inside = 80.0 <= eta <= 128.0
         series.append({"eta": eta, "xi_L": 0.27 * eta + 3.0 if inside else 1e3,
                        "xi_W": 0.21 * eta - 1.0 if inside else -1e3,
-                       "v2_phi": 0.268 if inside else 5.0})
+                       "v2_phi": 0.268 if inside else 5.0, "v2_omega": 0.3 if inside else -5.0})
     f = analyse(series, (80.0, 128.0))
     assert f["points"] == 97
     assert abs(f["dxi_L"] - 0.27) < 1e-12 and abs(f["dxi_W"] - 0.21) < 1e-12
     assert abs(f["dxi_W_iso"] - 0.21 * math.sqrt(1.5)) < 1e-12
-    assert abs(f["v2_phi"] - 0.268) < 1e-12
+    assert abs(f["v2_phi"] - 0.268) < 1e-12 and abs(f["v2_omega"] - 0.3) < 1e-12
     mu, err = mean_err([1.0, 2.0, 3.0, 4.0])
     assert mu == 2.5 and abs(err - math.sqrt(5.0 / 3.0) / 2.0) < 1e-15
