@@ -15,7 +15,7 @@ from ._lib import AHError, AH_FP32, AH_FP64, AH_COMPACT, AH_NONCOMPACT, AH_FLAG_
 
 __all__ = ["Params", "Lattice", "Pool", "AHError", "AH_FP32", "AH_FP64", "AH_COMPACT", "AH_NONCOMPACT",
            "AH_FLAG_NONFINITE", "AH_FLAG_UNSTABLE", "required_bytes", "autotune", "tune_lookup", "tune_set",
-           "tune_clear", "tune_save", "tune_load", "pool_footprint", "stability_margin"]
+           "tune_clear", "tune_save", "tune_load", "pool_footprint", "stability_margin", "read_dump"]
 
 
 @dataclass
@@ -196,6 +196,27 @@ class Lattice:
         self._call(self._lib.ah_get_winding, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), what="ah_get_winding")
         return w
 
+    def dump(self, path: str, windings: bool = True):
+        """Write the current snapshot to `path` (.npz): step index, parameters,
+        the ten fields in the lattice's storage precision (so the snapshot
+        comes back exactly through `restore`) and the plaquette windings W_ij
+        (int8, orientations xy, xz, yz; site index x0 + N (x1 + N x2))."""
+        import json
+        from dataclasses import asdict
+        st = self.get_state()
+        out = {"step": np.int64(self.step_index), "params": np.array(json.dumps(asdict(self.params))),
+               "fields": st.astype(np.float32) if self.params.precision == "fp32" else st}
+        if windings:
+            out["windings"] = self.winding()
+        np.savez_compressed(path, **out)
+
+    def restore(self, path: str):
+        """Load the snapshot of a dump written by `dump` for the same N."""
+        d = read_dump(path)
+        if d["params"].N != self.N:
+            raise ValueError(f"dump is for N = {d['params'].N}, this lattice has N = {self.N}")
+        self.set_state(d["fields"].astype(np.float64), d["step"])
+
     # -- kernel choice ---------------------------------------------------------
     def set_step_config(self, kernel="auto", tile=(0, 0), zchunk=0):
         """kernel: "auto", "site" or "tile"; tile: (tile_x, tile_y); zchunk: planes per workgroup."""
@@ -225,6 +246,17 @@ class Lattice:
         n = ctypes.c_int64()
         self._call(self._lib.ah_get_timing_split, ctypes.byref(ms), ctypes.byref(n), what="ah_get_timing_split")
         return ms.value, n.value
+
+
+def read_dump(path: str) -> dict:
+    """Contents of a lattice dump: step, params (Params), fields (10, N^3) and,
+    if written, windings (3, N^3).  Plain arrays only; nothing is unpickled."""
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        d = {"step": int(z["step"]), "params": Params(**json.loads(str(z["params"]))), "fields": z["fields"]}
+        if "windings" in z.files:
+            d["windings"] = z["windings"]
+    return d
 
 
 # ----------------------------------------------------------------- autotuner

@@ -298,6 +298,33 @@ def test_deterministic_and_resumable(ah):
     assert ma == mc
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_dump_and_restore(oracle_mod, ah, tmp_path, precision):
+    """A dump holds the snapshot exactly (storage precision) with its windings,
+    and a lattice restored from it continues bitwise like the original."""
+    from paper_2005_14454_amd import Params, read_dump
+    gp = Params(N=20, precision=precision, m=2.0)
+    path = str(tmp_path / "snap.npz")
+    with ah.Lattice(gp) as a:
+        a.init(9)
+        a.step(12)
+        a.dump(path)
+        st = a.get_state()
+        a.step(5)
+        after = a.get_state()
+    d = read_dump(path)
+    assert d["step"] == 12 and d["params"] == gp
+    assert d["fields"].dtype == (np.float32 if precision == "fp32" else np.float64)
+    assert np.array_equal(d["fields"].astype(np.float64), st)
+    op = oracle_mod.params(N=20, m=2.0)
+    assert np.array_equal(d["windings"], oracle_mod.winding(op, st).astype(np.int8))
+    with ah.Lattice(gp) as b:
+        b.restore(path)
+        assert b.step_index == 12
+        b.step(5)
+        assert np.array_equal(b.get_state(), after)
+
+
 def test_errors_and_edge_cases(ah):
     from paper_2005_14454_amd import Params, _lib
     with pytest.raises(ah.AHError):
