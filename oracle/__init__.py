@@ -36,6 +36,7 @@ class _Params(ctypes.Structure):
         ("m", ctypes.c_double), ("alpha", ctypes.c_double),
         ("s_early", ctypes.c_double), ("s_late", ctypes.c_double), ("eta_switch", ctypes.c_double),
         ("eta0", ctypes.c_double), ("eta_ref", ctypes.c_double),
+        ("damp_gamma", ctypes.c_double), ("eta_damp", ctypes.c_double),
     ]
 
 
@@ -86,7 +87,7 @@ def _load():
 
 
 DEFAULTS = dict(N=16, compact=1, dx=0.5, deta=0.1, lambda0=2.0, e0=1.0, sigma=1.0, m=1.0, alpha=2.0,
-                s_early=0.0, s_late=0.0, eta_switch=math.inf, eta0=1.0, eta_ref=0.0)
+                s_early=0.0, s_late=0.0, eta_switch=math.inf, eta0=1.0, eta_ref=0.0, damp_gamma=0.0, eta_damp=0.0)
 
 
 def params(**kw) -> dict:

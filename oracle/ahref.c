@@ -37,6 +37,10 @@ void ahref_scalars_at(const ahref_params* p, int64_t n, ahref_scalars* out)
     double a = pow(eta / p->eta_ref, p->m);
     double f = pow(a, 2.0 * s);
     double delta = 0.5 * p->alpha * p->m * p->deta / eta;
+    /* artificial damping phase (section 2 mentions the capability): the
+     * friction coefficient of the momentum equations is a constant gamma in
+     * place of the Hubble term, so its Crank-Nicolson form has delta = gamma deta / 2 */
+    if (p->damp_gamma > 0.0 && eta < p->eta_damp) delta = 0.5 * p->damp_gamma * p->deta;
     out->eta = eta;
     out->s = s;
     out->a = a;

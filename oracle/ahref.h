@@ -46,6 +46,8 @@ typedef struct ahref_params {
     double alpha;       /* damping multiplier; 2 gives Crank-Nicolson Hubble friction */
     double s_early, s_late, eta_switch;
     double eta0, eta_ref;
+    double damp_gamma;  /* artificial damping phase: friction gamma for eta < eta_damp (0: none) */
+    double eta_damp;
 } ahref_params;
 
 typedef struct ahref_scalars {

@@ -206,6 +206,35 @@ def test_hubble_damping_telescopes(oracle_mod, m):
     assert np.all(out[7] == 0.4)
 
 
+def test_artificial_damping_phase(oracle_mod):
+    """A damping phase (friction gamma while eta < eta_damp, then the Hubble
+    term again): zero-force uniform Pi and E decay by ((1 - g)/(1 + g))^K1
+    with g = gamma deta / 2 over the K1 steps of the phase, then by the
+    telescoping Hubble product (m = 1) from there on."""
+    N, deta, gamma, eta_damp, K = 4, 0.1, 3.0, 3.05, 60
+    p = oracle_mod.params(N=N, m=1.0, lambda0=0.0, damp_gamma=gamma, eta_damp=eta_damp)
+    eta = lambda n: 1.0 + n * deta
+    K1 = sum(1 for n in range(K) if eta(n) < eta_damp)
+    assert K1 == 21
+    g = 0.5 * gamma * deta
+    want = ((1 - g) / (1 + g)) ** K1 * eta(K1 - 1) * eta(K1) / (eta(K - 1) * eta(K))
+    st = np.zeros((10, N ** 3))
+    st[0], st[1], st[2], st[3] = 0.1, 0.05, 0.3, -0.2
+    out = oracle_mod.step(p, st, 0, K)
+    assert abs(out[2, 0] / 0.3 - want) < 1e-13 and abs(out[3, 0] / -0.2 - want) < 1e-13
+    st = np.zeros((10, N ** 3))
+    st[7], st[9] = 0.4, 0.25
+    out = oracle_mod.step(p, st, 0, K)
+    assert abs(out[7, 3] / 0.4 - want) < 1e-13 and abs(out[9, 3] / 0.25 - want) < 1e-13
+    # damping the random-phase start keeps Gauss's law (s = 0) and drains energy faster than without
+    p0 = oracle_mod.params(N=8, m=1.0)
+    pd = oracle_mod.params(N=8, m=1.0, damp_gamma=gamma, eta_damp=eta_damp)
+    a = oracle_mod.step(p0, oracle_mod.init(p0, 3), 0, 30)
+    b = oracle_mod.step(pd, oracle_mod.init(pd, 3), 0, 30)
+    ma, mb = oracle_mod.measure(p0, a, 30), oracle_mod.measure(pd, b, 30)
+    assert mb["gauss_rel"] < 1e-13 and mb["energy"] < ma["energy"]
+
+
 @pytest.mark.parametrize("m,s,eta_ref", [(2.0, 1.0, 5.0), (1.0, -1.0, 2.0)])
 def test_homogeneous_mode_reduces_to_scalar_recurrence(oracle_mod, m, s, eta_ref):
     """Uniform real phi with A = E = 0: every stencil term cancels and the lattice
