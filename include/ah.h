@@ -86,11 +86,14 @@ typedef struct ah_params {
     double s_early, s_late, eta_switch; /* s = s_early for eta < eta_switch, else s_late */
     double eta0;          /* initial conformal time (section 2: 1) */
     double eta_ref;       /* a(eta_ref) = 1; <= 0 selects the half light-crossing time dx*N/2 */
+    double damp_gamma;    /* artificial damping phase: while eta < eta_damp the momentum equations */
+    double eta_damp;      /*   have the constant friction damp_gamma in place of the Hubble term
+                           *   (delta = damp_gamma deta / 2, omega = (1 - s) delta); 0: no such phase */
 } ah_params;
 
 /* Fill *p with the paper's standard choices (section 2): N = 64, FP64,
  * compact, dx = 0.5, deta = 0.1, lambda0 = 2, e0 = 1, sigma = 1, m = 1,
- * alpha = 2, s = 0 throughout, eta0 = 1, eta_ref = dx*N/2. */
+ * alpha = 2, s = 0 throughout, eta0 = 1, eta_ref = dx*N/2, no damping phase. */
 int ah_params_default(ah_params* p);
 
 /* ---------------------------------------------------------- measurement */

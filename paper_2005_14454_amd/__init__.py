@@ -23,7 +23,9 @@ class Params:
     """Lattice and model parameters (section 2 standard choices as defaults).
 
     precision: "fp64" or "fp32"; gauge_action: "compact" or "noncompact";
-    eta_ref <= 0 selects a(dx*N/2) = 1."""
+    eta_ref <= 0 selects a(dx*N/2) = 1.  damp_gamma > 0 adds an artificial
+    damping phase: while eta < eta_damp the friction of the momentum equations
+    is the constant damp_gamma instead of the Hubble term."""
     N: int = 64
     precision: str = "fp64"
     gauge_action: str = "compact"
@@ -39,6 +41,8 @@ class Params:
     eta_switch: float = math.inf
     eta0: float = 1.0
     eta_ref: float = 0.0
+    damp_gamma: float = 0.0
+    eta_damp: float = 0.0
 
     def to_c(self) -> _lib.ah_params:
         c = _lib.ah_params()

@@ -29,6 +29,7 @@ class ah_params(ctypes.Structure):
         ("m", ctypes.c_double), ("alpha", ctypes.c_double),
         ("s_early", ctypes.c_double), ("s_late", ctypes.c_double), ("eta_switch", ctypes.c_double),
         ("eta0", ctypes.c_double), ("eta_ref", ctypes.c_double),
+        ("damp_gamma", ctypes.c_double), ("eta_damp", ctypes.c_double),
     ]
 
 

@@ -79,6 +79,8 @@ Scalars scalars_at(const ah_params& p, int64_t n)
     r.a = std::pow(r.eta / eta_ref_of(p), p.m);
     r.f = std::pow(r.a, 2.0 * r.s);
     r.delta = 0.5 * p.alpha * p.m * p.deta / r.eta;
+    // artificial damping phase: a constant friction gamma replaces the Hubble term
+    if (p.damp_gamma > 0.0 && r.eta < p.eta_damp) r.delta = 0.5 * p.damp_gamma * p.deta;
     r.omega = (1.0 - r.s) * r.delta;
     return r;
 }
@@ -153,6 +155,10 @@ int validate_params(const ah_params* p, std::string* why)
         !std::isfinite(p->alpha) || !std::isfinite(p->s_early) || !std::isfinite(p->s_late) ||
         std::isnan(p->eta_switch) || !std::isfinite(p->eta_ref)) {
         *why = "non-finite or invalid coupling / expansion parameter (e0 must be > 0)";
+        return AH_E_INVAL;
+    }
+    if (!(p->damp_gamma >= 0.0) || !std::isfinite(p->damp_gamma) || std::isnan(p->eta_damp)) {
+        *why = "damp_gamma must be finite and >= 0, eta_damp not NaN";
         return AH_E_INVAL;
     }
     return AH_OK;
@@ -512,6 +518,8 @@ int ah_params_default(ah_params* p)
     p->eta_switch = HUGE_VAL;
     p->eta0 = 1.0;
     p->eta_ref = 0.0;
+    p->damp_gamma = 0.0;  // no artificial damping phase
+    p->eta_damp = 0.0;
     return AH_OK;
 }
 

@@ -71,6 +71,28 @@ def test_one_step_fp64(oracle_mod, ah, N, m, s, kernel):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_artificial_damping_phase(oracle_mod, ah, precision, tol):
+    """Random-phase start damped with friction 3 until eta = 3.05 (21 steps),
+    then the radiation-era Hubble damping: 60 steps against the oracle, and the
+    diagnostics of the last snapshot (Gauss's law stays exact for s = 0)."""
+    op, gp = both_params(oracle_mod, 24, precision, m=1.0, damp_gamma=3.0, eta_damp=3.05)
+    ic = oracle_mod.init(op, 4)
+    ref = oracle_mod.step(op, ic, 0, 60)
+    with ah.Lattice(gp) as lat:
+        lat.set_state(ic, 0)
+        lat.step(60)
+        got = lat.get_state()
+        gm = lat.measure()
+    err = field_scaled_error(got, ref)
+    print(f"damping phase {precision}: {err}")
+    assert max(err.values()) <= tol, err
+    om = oracle_mod.measure(op, got, 60)
+    assert gm["winding_sum_abs"] == om["winding_sum_abs"]
+    assert abs(gm["energy"] - om["energy"]) <= (1e-11 if precision == "fp64" else 1e-6) * om["energy"]
+    assert gm["gauss_rel"] < (1e-12 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_core_growth_negative_s(oracle_mod, ah, precision, tol):
     """s = -1 (the cores grow with a, the paper's option for resolving them
     early) switching to s = 1 at eta = 3, radiation era, 40 steps from the

@@ -57,7 +57,8 @@ def test_parameter_validation(ah):
     good = ah.Params(N=16).to_c()
     assert lib.ah_required_bytes(ctypes.byref(good), ctypes.byref(n)) == 0
     for field, value in (("N", 3), ("precision", 7), ("gauge_action", 5), ("reserved", 1), ("dx", 0.0),
-                         ("deta", -0.1), ("eta0", 0.0), ("e0", 0.0), ("lambda0", float("nan"))):
+                         ("deta", -0.1), ("eta0", 0.0), ("e0", 0.0), ("lambda0", float("nan")),
+                         ("damp_gamma", -1.0), ("damp_gamma", float("inf")), ("eta_damp", float("nan"))):
         bad = ah.Params(N=16).to_c()
         setattr(bad, field, value)
         assert lib.ah_required_bytes(ctypes.byref(bad), ctypes.byref(n)) == _lib.AH_E_INVAL, field
