@@ -304,11 +304,16 @@ int ah_pool_poll(ah_pool* pool, int64_t* done_ids, int32_t cap, int32_t* n);
 /* Current step of a request and its target (nsteps may be NULL). */
 int ah_pool_progress(ah_pool* pool, int64_t id, int64_t* step, int64_t* nsteps);
 
-/* Current snapshot of a request as FP64 SoA (10 N^3 doubles) and its step. */
+/* Current snapshot of a request as FP64 SoA and its step: host_soa must hold
+ * 10 N^3 doubles for the N that request was submitted with (the call writes
+ * that many; it cannot check the buffer).  Synchronous.  AH_E_INVAL for an
+ * unknown id. */
 int ah_pool_get_state(ah_pool* pool, int64_t id, double* host_soa, int64_t* step);
 
 /* Measurement series of a finished request (at most cap records; *n written)
- * and release of its slot and memory.  AH_E_AGAIN if it has not finished. */
+ * and release of its slot and memory.  A request with measure_every = k > 0
+ * has nsteps/k + 2 records at most (every k-th step and the final one); with
+ * k = 0, one.  AH_E_AGAIN if it has not finished. */
 int ah_pool_results(ah_pool* pool, int64_t id, ah_measurement* series, int32_t cap, int32_t* n);
 
 /* Occupancy figures. */

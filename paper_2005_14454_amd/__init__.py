@@ -349,6 +349,7 @@ class Pool:
             _lib.check(self._lib.ah_pool_create(hbm_budget, max_slots, None, ctypes.byref(h)), what="ah_pool_create")
         self._h = h
         self.max_slots = max_slots
+        self._req = {}  # id -> (params, nsteps, measure_every) of the lattices in the pool
 
     def _call(self, fn, *args, what=""):
         with self._torch.cuda.device(self.device):
@@ -381,6 +382,7 @@ class Pool:
         if rc == _lib.AH_E_AGAIN:
             return None
         _lib.check(rc, what="ah_pool_submit", pool=self._h)
+        self._req[rid.value] = (p, nsteps, measure_every)
         return rid.value
 
     def advance(self, nsteps: int = 1):
@@ -397,17 +399,28 @@ class Pool:
         self._call(self._lib.ah_pool_progress, rid, ctypes.byref(s), ctypes.byref(n), what="ah_pool_progress")
         return s.value, n.value
 
-    def get_state(self, rid: int, N: int) -> np.ndarray:
-        st = np.empty((10, N ** 3), dtype=np.float64)
+    def get_state(self, rid: int, N: int = None) -> np.ndarray:
+        """Fields of lattice rid at its current step; the buffer is sized from
+        the lattice's own N (a given N must match it)."""
+        if rid not in self._req:
+            raise KeyError(f"no lattice {rid} in the pool")
+        n_own = self._req[rid][0].N
+        if N is not None and N != n_own:
+            raise ValueError(f"lattice {rid} has N = {n_own}, not {N}")
+        st = np.empty((10, n_own ** 3), dtype=np.float64)
         s = ctypes.c_int64()
         self._call(self._lib.ah_pool_get_state, rid, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                    ctypes.byref(s), what="ah_pool_get_state")
         return st
 
-    def results(self, rid: int, cap: int = 100000):
+    def results(self, rid: int):
+        """Diagnostics series of a finished lattice; frees its slot."""
+        _, nsteps, every = self._req.get(rid, (None, 0, 0))
+        cap = (nsteps // every + 1 if every > 0 else 0) + 1
         arr = (_lib.ah_measurement * cap)()
         n = ctypes.c_int32()
         self._call(self._lib.ah_pool_results, rid, arr, cap, ctypes.byref(n), what="ah_pool_results")
+        self._req.pop(rid, None)
         return [_meas_dict(arr[k]) for k in range(n.value)]
 
     def stats(self) -> dict:
