@@ -11,7 +11,7 @@ diagnostics (windings, energy split, Lagrangian estimators, Gauss residual),
 formed in the same pass as its step, inside the timed region.
 
 Prints one JSON line.  Flags: --gpus N (only 1 is supported), --steps K,
---warmup W, --no-cpu-baseline, --cpu-sweep, --no-fp64, --no-batched,
+--warmup W, --no-cpu-baseline, --cpu-sweep, --pcie, --no-fp64, --no-batched,
 --no-served, --no-copy-probe.
 """
 import argparse
@@ -115,6 +115,35 @@ def run_gpu(precision, N, steps, warmup, measure_every, seed):
         "last_measurement": {k: last[k] for k in ("step", "winding_sum_abs", "xi_W", "xi_L", "v2_phi", "v2_omega",
                                                   "energy", "gauss_rel", "nonfinite")},
     }
+
+
+def pcie_job(N, seed, steps, precision="fp32"):
+    """The same stepping with the state handed over in host memory: upload a
+    FP64 host snapshot (ah_set_state), `steps` plain steps, download it
+    again (ah_get_state); each part timed on the host clock."""
+    import torch
+    import paper_2005_14454_amd as ah
+
+    p = ah.Params(N=N, precision=precision, m=1.0)
+    tiling(ah, p)
+    with ah.Lattice(p) as lat:
+        lat.init(seed)
+        host = lat.get_state()
+        lat.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.set_state(host, 0)
+        t1 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out = lat.get_state()
+        t3 = time.perf_counter()
+    del host, out
+    V = N ** 3
+    return {"steps": steps, "upload_s": t1 - t0, "step_s": t2 - t1, "download_s": t3 - t2,
+            "value": V * steps / (t3 - t0), "unit": "site-updates/s",
+            "host_bytes_each_way": 10 * 8 * V}
 
 
 def single_rate(N, precision="fp32", steps=10):
@@ -292,6 +321,8 @@ def main():
     ap.add_argument("--N", type=int, default=512)
     ap.add_argument("--measure-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pcie", action="store_true",
+                    help="also time a job whose state is uploaded from and downloaded to host memory")
     ap.add_argument("--cpu-sweep", action="store_true",
                     help="also time the oracle at 64^3, 128^3 and 256^3 on all host threads and on one")
     ap.add_argument("--no-fp64", action="store_true")
@@ -330,6 +361,11 @@ def main():
         print(f"# served: {serv['throughput_su_per_s']:.4e} su/s, p50 {serv['ttc_p50_s']:.2f} s, "
               f"p99 {serv['ttc_p99_s']:.2f} s", file=sys.stderr, flush=True)
     probe = None if args.no_copy_probe else copy_probe()
+    pcie = pcie_job(args.N, seed, args.steps) if args.pcie else None
+    if pcie:
+        print(f"# pcie-inclusive: {pcie['value']:.4e} su/s (upload {pcie['upload_s']:.2f} s, "
+              f"{pcie['steps']} steps {pcie['step_s']:.2f} s, download {pcie['download_s']:.2f} s)",
+              file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.N, seed)
     if cpu is not None and args.cpu_sweep:
         cpu["sweep"] = cpu_sweep(seed)
@@ -353,6 +389,7 @@ def main():
         "roofline": fp32["roofline"],
         "cpu_baseline": cpu,
         "hbm_copy_probe": probe,
+        **({"pcie_inclusive": pcie} if pcie else {}),
         "batched": batched,
         "batched_small": batched_small,
         "served": serv,
