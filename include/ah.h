@@ -258,10 +258,10 @@ int ah_tune_load(const char* path);
  * node per precision and tile shape, one block per (lattice, tile) work
  * item) and a counter update.  Pool lattices run the tuned (else default)
  * tile shape with FP32 1024-thread shapes halved in y and FP64 on 32 x 8,
- * and z-chunks of at least 64 planes.  Every lattice takes the coefficients
- * of its own step from its own FP64 table, so its fields and diagnostics are
- * bitwise identical to the same lattice run alone through ah_step /
- * ah_measure with the same tiling.  Requests enter and leave between
+ * and z-chunks of at least 16 planes (ah_pool_step_config reports them).
+ * Every lattice takes the coefficients of its own step from its own FP64
+ * table, so its fields and diagnostics are bitwise identical to the same
+ * lattice run alone through ah_step / ah_measure with the same tiling.  Requests enter and leave between
  * advances (continuous batching); the graph is rebuilt when the set changes.
  * A pool is used from one host thread at a time. */
 typedef struct ah_pool ah_pool;
@@ -300,6 +300,12 @@ int ah_pool_advance(ah_pool* pool, int32_t nsteps);
 /* Ids of lattices that finished since the last poll (at most cap; *n is the
  * number written).  Synchronises with the pool stream. */
 int ah_pool_poll(ah_pool* pool, int64_t* done_ids, int32_t cap, int32_t* n);
+
+/* Tile shape and z-chunk a request is stepped with (kernel AH_KERNEL_TILE).
+ * The pool takes the tuned configuration of the request's (precision, N), or
+ * the default one, with z-chunks of at least 16 planes and one tile shape
+ * for its plain and measured steps.  Host only.  AH_E_INVAL for an unknown id. */
+int ah_pool_step_config(const ah_pool* pool, int64_t id, ah_step_config* out);
 
 /* Current step of a request and its target (nsteps may be NULL). */
 int ah_pool_progress(ah_pool* pool, int64_t id, int64_t* step, int64_t* nsteps);

@@ -394,6 +394,13 @@ class Pool:
         self._call(self._lib.ah_pool_poll, ids, cap, ctypes.byref(n), what="ah_pool_poll")
         return [ids[k] for k in range(n.value)]
 
+    def step_config(self, rid: int) -> dict:
+        """Tile shape and z-chunk lattice rid is stepped with."""
+        c = _lib.ah_step_config()
+        _lib.check(self._lib.ah_pool_step_config(self._h, rid, ctypes.byref(c)), what="ah_pool_step_config",
+                   pool=self._h)
+        return _cfg_dict(c)
+
     def progress(self, rid: int):
         s, n = ctypes.c_int64(), ctypes.c_int64()
         self._call(self._lib.ah_pool_progress, rid, ctypes.byref(s), ctypes.byref(n), what="ah_pool_progress")

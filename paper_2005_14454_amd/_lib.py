@@ -123,6 +123,7 @@ def load():
         "ah_pool_advance": ([vp, ctypes.c_int32], ctypes.c_int),
         "ah_pool_poll": ([vp, P(i64), ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
         "ah_pool_progress": ([vp, i64, P(i64), P(i64)], ctypes.c_int),
+        "ah_pool_step_config": ([vp, i64, P(ah_step_config)], ctypes.c_int),
         "ah_pool_get_state": ([vp, i64, P(ctypes.c_double), P(i64)], ctypes.c_int),
         "ah_pool_results": ([vp, i64, P(ah_measurement), ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
         "ah_pool_stats": ([vp, P(ah_pool_info)], ctypes.c_int),

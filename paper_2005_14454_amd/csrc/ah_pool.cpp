@@ -346,9 +346,13 @@ int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_po
     });
 }
 
-// Tile configuration of a pool lattice: the tuned (or default) tile shape,
-// with whole-column z-chunks of at least 64 planes (the pool supplies the
-// parallelism that small z-chunks buy a lattice run alone).
+// Tile configuration of a pool lattice: the tuned (or default) tile shape
+// and z-chunk, with z-chunks of at least 16 planes.  The pool supplies much
+// of the parallelism that short z-chunks buy a lattice run alone; 16 planes
+// keep enough work items for ensembles of small lattices (measured on
+// MI355X: 128 lattices of N in {32, 48, 64} run 11% faster than with
+// 64-plane chunks, a mix of N in 64 .. 256 2% faster; 8 and 32 planes are
+// slower than 16).
 static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why)
 {
     ah_step_config t{AH_KERNEL_TILE, 0, 0, 0};
@@ -360,7 +364,7 @@ static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why
     // on 32 x 8 (as fast as any FP64 shape for the plain step)
     if (p.precision == AH_FP32 && cfg->tile_x * cfg->tile_y == 1024) cfg->tile_y /= 2;
     if (p.precision == AH_FP64) (void)measured_tile(p.precision, &cfg->tile_x, &cfg->tile_y);
-    int zc = cfg->zchunk < 64 ? 64 : cfg->zchunk;
+    int zc = cfg->zchunk < 16 ? 16 : cfg->zchunk;
     if (zc > p.N) zc = p.N;
     cfg->zchunk = zc;
     return AH_OK;
@@ -539,6 +543,17 @@ static Slot* find_slot(ah_pool* P, int64_t id, int* index)
             return &P->slots[i];
         }
     return nullptr;
+}
+
+int ah_pool_step_config(const ah_pool* P, int64_t id, ah_step_config* out)
+{
+    if (!P || !out) return AH_E_INVAL;
+    for (const Slot& s : P->slots)
+        if (s.used && s.id == id) {
+            *out = s.cfg;
+            return AH_OK;
+        }
+    return AH_E_INVAL;
 }
 
 int ah_pool_progress(ah_pool* P, int64_t id, int64_t* step, int64_t* nsteps)

@@ -36,6 +36,7 @@ class Request:
     admitted: float = math.nan
     done: float = math.nan
     pool_id: int = -1
+    step_config: dict = None   # tile shape and z-chunk the pool stepped it with
     series: list = field(default_factory=list)
 
 
@@ -91,6 +92,7 @@ def run_stream(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 2, log=
                     continue
                 r.admitted = time.perf_counter() - t0
                 r.pool_id = pid
+                r.step_config = pool.step_config(pid)
                 by_pool[pid] = r
             waiting = still
             if by_pool:

@@ -49,12 +49,6 @@ def same_record(a: dict, b: dict) -> bool:
     return True
 
 
-def pool_tile(precision: str):
-    """Tile shape the pool runs a lattice of this precision on (for N < 128 and
-    no tuned entry): 64 x 8 for FP32, 32 x 8 for FP64."""
-    return (32, 8) if precision == "fp64" else (64, 8)
-
-
 def run_alone(gp, seed, nsteps, every, tile, zchunk):
     """One lattice run alone through ah_step / ah_measure: its fields after
     nsteps and its diagnostics series (every `every` steps and the last)."""

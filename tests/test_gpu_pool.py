@@ -12,7 +12,7 @@
 import numpy as np
 import pytest
 
-from helpers import both_params, field_scaled_error, pool_tile, run_alone, same_record
+from helpers import both_params, field_scaled_error, run_alone, same_record
 
 pytestmark = pytest.mark.gpu
 
@@ -36,6 +36,7 @@ def test_pool_alone_vs_mix_bitwise(ah):
     with ah.Pool(hbm_budget=1 << 30, max_slots=16) as pool:
         ids = [pool.submit(p, seed, n, every) for p, seed, n, every in reqs]
         assert all(i is not None for i in ids)
+        cfgs = {rid: pool.step_config(rid) for rid in ids}
         states, series = {}, {}
         finished = []
         for step in range(40):
@@ -47,12 +48,14 @@ def test_pool_alone_vs_mix_bitwise(ah):
                 series[rid] = pool.results(rid)
         assert sorted(finished) == sorted(ids)
         assert pool.stats()["active"] == 0 and pool.stats()["bytes_in_use"] == 0
-    # the pool runs whole-column z-chunks (>= 64 planes) on 64 x 8 tiles (FP32)
-    # or 32 x 8 tiles (FP64, whose 512-thread measured march would spill);
-    # alone with the same tiling the diagnostics records are summed in the
-    # same order
+    # the pool runs z-chunks of at least 16 planes on 64 x 8 tiles (FP32) or
+    # 32 x 8 tiles (FP64, whose 512-thread measured march would spill); alone
+    # with the same tiling the diagnostics records are summed in the same order
     for (p, seed, n, every), rid in zip(reqs, ids):
-        st, ser = run_alone(p, seed, n, every, pool_tile(p.precision), min(p.N, 64))
+        cfg = cfgs[rid]
+        assert cfg["kernel"] == "tile" and cfg["tile"] == ((32, 8) if p.precision == "fp64" else (64, 8))
+        assert min(p.N, 16) <= cfg["zchunk"] <= p.N
+        st, ser = run_alone(p, seed, n, every, cfg["tile"], cfg["zchunk"])
         assert np.array_equal(states[rid], st), (p, seed)
         assert len(series[rid]) == len(ser)
         for a, b in zip(series[rid], ser):

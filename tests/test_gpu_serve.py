@@ -6,7 +6,7 @@ run alone with the same tiling."""
 import numpy as np
 import pytest
 
-from helpers import pool_tile, run_alone, same_record
+from helpers import run_alone, same_record
 
 pytestmark = pytest.mark.gpu
 
@@ -24,8 +24,8 @@ def test_served_results_equal_alone():
     assert out["ttc_p99_s"] >= out["ttc_p50_s"] > 0
     assert out["fp64_spot_checks"] == 2 and out["fp32_vs_fp64_snapshots_compared"] > 0
     for r in reqs:
-        _, ser = run_alone(r.params, r.seed, r.nsteps, r.measure_every, pool_tile(r.params.precision),
-                           min(r.params.N, 64))
+        _, ser = run_alone(r.params, r.seed, r.nsteps, r.measure_every, r.step_config["tile"],
+                           r.step_config["zchunk"])
         assert len(ser) == len(r.series)
         for a, b in zip(r.series, ser):
             assert same_record(a, b), (r.rid, r.params.N, a["step"])
