@@ -52,6 +52,8 @@ def measured_traffic(precision, N, tile):
             if best is None or n > best[0]:
                 best = (n, total_gb)
     return best[1] * 1e9 if best else None
+
+
 BYTES_PER_SITE = {"fp32": 80, "fp64": 160}  # read 10 reals + write 10 reals per site-update
 
 
