@@ -199,7 +199,8 @@ int ah_get_winding(ah_handle* h, int8_t* host_w);
 typedef struct ah_step_config {
     int32_t kernel;         /* AH_KERNEL_* */
     int32_t tile_x, tile_y; /* tiled kernel: (64,8), (64,4), (32,8), (128,4) (FP32 also (64,16), (128,8)); 0,0 = default */
-    int32_t zchunk;         /* x2-planes per workgroup of the tiled kernel; 0 = automatic, else >= min(8, N) */
+    int32_t zchunk;         /* x2-planes per workgroup of the tiled kernel; 0 = automatic, else >= 2
+                             * for N <= 128 and >= 8 above (the last chunk of a column may be shorter) */
 } ah_step_config;
 
 /* Select the step kernel; AH_E_INVAL for an unsupported combination. */
@@ -234,8 +235,8 @@ int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double*
 int ah_tune_lookup(const ah_params* p, ah_step_config* out);
 
 /* Record a choice by hand: kernel AH_KERNEL_TILE, a tile shape supported
- * for the precision, zchunk 0 (automatic) or >= min(8, N); AH_E_INVAL
- * otherwise. */
+ * for the precision, zchunk 0 (automatic) or at least the minimum of
+ * ah_step_config.zchunk; AH_E_INVAL otherwise. */
 int ah_tune_set(const ah_params* p, const ah_step_config* c);
 
 /* Forget every recorded choice. */

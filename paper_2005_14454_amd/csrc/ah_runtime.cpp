@@ -293,7 +293,7 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
         return AH_E_INVAL;
     }
     if (c.zchunk < 0 || (c.zchunk > 0 && c.zchunk < min_zchunk(p.N))) {
-        *why = "zchunk must be 0 (automatic) or at least min(8, N)";
+        *why = "zchunk must be 0 (automatic) or at least 2 (N <= 128) or 8 (N > 128)";
         return AH_E_INVAL;
     }
     if (c.zchunk == 0) {

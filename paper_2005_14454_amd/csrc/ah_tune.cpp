@@ -64,8 +64,8 @@ int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double*
             tiles.push_back({128, 8});
         }
         std::vector<int> zcs = {0, p->N};
-        for (int div : {2, 4, 8})
-            if (p->N / div >= 8) zcs.push_back(p->N / div);
+        for (int div : {2, 4, 8, 16, 32})
+            if (p->N / div >= ah::min_zchunk(p->N)) zcs.push_back(p->N / div);
         ah_step_config bcfg{};
         double bms = 1e300;
         for (auto& t : tiles) {

@@ -28,8 +28,8 @@ def ah():
 
 
 KERNELS = [("site", (0, 0), 0), ("tile", (64, 8), 0), ("tile", (64, 4), 8), ("tile", (32, 8), 9),
-           ("tile", (128, 4), 16)]
-KERNEL_IDS = ["site", "tile64x8", "tile64x4z8", "tile32x8z9", "tile128x4z16"]
+           ("tile", (128, 4), 16), ("tile", (64, 8), 2), ("tile", (32, 8), 3)]
+KERNEL_IDS = ["site", "tile64x8", "tile64x4z8", "tile32x8z9", "tile128x4z16", "tile64x8z2", "tile32x8z3"]
 
 
 def _run_gpu(ah, gp, state, step0, nsteps, kernel=None):
@@ -385,7 +385,8 @@ def test_tile_shapes_bitwise_identical(ah, precision):
     N = 40
     gp = Params(N=N, precision=precision, m=2.0)
     st = random_state(N, seed=9)
-    shapes = [((64, 8), 0), ((64, 4), 8), ((32, 8), 9), ((64, 8), 40), ((32, 8), 13), ((128, 4), 8)]
+    shapes = [((64, 8), 0), ((64, 4), 8), ((32, 8), 9), ((64, 8), 40), ((32, 8), 13), ((128, 4), 8),
+              ((64, 8), 2), ((32, 8), 3), ((64, 4), 5)]
     if precision == "fp32":
         shapes += [((64, 16), 11), ((128, 8), 10)]
     outs = [_run_gpu(ah, gp, st, 0, 12, ("tile", t, z)) for t, z in shapes]
@@ -393,6 +394,47 @@ def test_tile_shapes_bitwise_identical(ah, precision):
         assert np.array_equal(o, outs[0])
     again = _run_gpu(ah, gp, st, 0, 12, ("tile", (64, 8), 0))
     assert np.array_equal(again, outs[0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("zchunk", [2, 3])
+def test_short_chunks_diagnostics_vs_oracle(oracle_mod, ah, precision, zchunk):
+    """Two- and three-plane z-chunks (N = 20: a ragged last chunk for 3) in the
+    measured march, which completes each chunk's windings at its last plane:
+    the diagnostics of a generic snapshot and of a fused series against the
+    oracle."""
+    N = 20
+    op, gp = both_params(oracle_mod, N, precision, m=1.0)
+    tile = (32, 8) if precision == "fp64" else (64, 8)
+    st = random_state(N, seed=31)
+    if precision == "fp32":
+        st = st.astype(np.float32).astype(np.float64)
+    with ah.Lattice(gp) as lat:
+        lat.set_step_config("tile", tile, zchunk)
+        assert lat.get_step_config()["zchunk"] == zchunk
+        lat.set_state(st, 4)
+        gm = lat.measure()
+        assert np.array_equal(lat.winding(), oracle_mod.winding(op, st).astype(np.int8))
+        lat.init(6)
+        series = lat.step_measured(10, 5) + [lat.measure()]
+        got = lat.get_state()
+    om = oracle_mod.measure(op, st, 4)
+    scale = sum(om[k] for k in ("e_kin", "e_grad", "e_pot", "e_el", "e_mag"))
+    tol = 1e-11 if precision == "fp64" else 1e-6
+    assert gm["winding_sum_abs"] == om["winding_sum_abs"]
+    for k in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag", "sum_L"):
+        assert abs(gm[k] - om[k]) <= tol * scale, (k, gm[k], om[k])
+    ref = oracle_mod.init(op, 6)
+    for k, m in enumerate(series):
+        n = 5 * k
+        if n > 0:
+            ref = oracle_mod.step(op, ref, n - 5, 5)
+        assert m["step"] == n
+        if precision == "fp64":
+            om = oracle_mod.measure(op, ref, n)
+            assert m["winding_sum_abs"] == om["winding_sum_abs"], n
+            assert abs(m["energy"] - om["energy"]) <= 1e-9 * om["energy"], n
+    assert max(field_scaled_error(got, ref).values()) <= (1e-12 if precision == "fp64" else 1e-4)
 
 
 def test_default_kernel_choice(ah):

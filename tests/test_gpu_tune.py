@@ -26,7 +26,7 @@ def test_autotune_records_and_is_used(ah, precision):
     assert tuple(best["tile"]) in SHAPES
     if precision == "fp64":
         assert tuple(best["tile"]) not in {(64, 16), (128, 8)}
-    assert 8 <= best["zchunk"] <= 48
+    assert 2 <= best["zchunk"] <= 48
     assert ah.tune_lookup(p)["tile"] == best["tile"]
     with ah.Lattice(p) as lat:
         cfg = lat.get_step_config()

@@ -121,8 +121,11 @@ def test_tuning_table_roundtrip_and_validation(ah, tmp_path):
         assert ah.tune_lookup(p32) is None and ah.tune_lookup(p64) is None
         ah.tune_load(str(path))
         assert ah.tune_lookup(p32)["tile"] == (128, 8) and ah.tune_lookup(p64)["tile"] == (32, 8)
-        for bad in [(p64, (128, 8), 0), (p64, (64, 16), 0), (p32, (48, 8), 0), (p32, (64, 8), 3),
-                    (p32, (64, 8), -1)]:
+        ah.tune_set(p32, (64, 8), 2)                     # short chunks are for lattices up to 128
+        assert ah.tune_lookup(p32)["zchunk"] == 2
+        p256 = ah.Params(N=256, precision="fp32")
+        for bad in [(p64, (128, 8), 0), (p64, (64, 16), 0), (p32, (48, 8), 0), (p32, (64, 8), 1),
+                    (p32, (64, 8), -1), (p256, (64, 8), 4)]:
             with pytest.raises(ah.AHError):
                 ah.tune_set(*bad)
         assert ah.tune_lookup(p64)["tile"] == (32, 8)
