@@ -221,18 +221,22 @@ def batched_ensemble(sizes=(64, 96, 128, 192, 256), nlat=64, rng_seed=4, measure
             "nonfinite": sum(m["nonfinite"] for m in finals)}
 
 
-def served(nreq=40, capacity_su=3.0e10):
+def served(nreq=40):
     """A shortened request stream (the full 500-request stream is
     `python -m paper_2005_14454_amd.serve`): N log-uniform on [64, 512],
     m in {1, 2}, s in {0, 1}, FP32 with an FP64 rerun of every 10th request,
-    Poisson arrivals at 0.7 x capacity."""
+    Poisson arrivals at 0.7 x the capacity, which is the throughput the pool
+    sustains on the same requests when they all arrive at once."""
     import numpy as np
-    from paper_2005_14454_amd.serve import make_stream, run_stream
+    from paper_2005_14454_amd.serve import make_stream, run_stream, saturated_throughput
+    budget = int(200e9)
     probe = make_stream(nreq, 1.0)
     work = float(np.mean([r.params.N ** 3 * r.nsteps for r in probe]))
-    rate = 0.7 * capacity_su / work
-    out = run_stream(make_stream(nreq, rate), hbm_budget=int(200e9))
+    capacity = saturated_throughput(probe, budget)
+    rate = 0.7 * capacity / work
+    out = run_stream(make_stream(nreq, rate), hbm_budget=budget)
     out["arrival_rate_per_s"] = rate
+    out["capacity_su_per_s"] = capacity
     return out
 
 
@@ -358,7 +362,7 @@ def main():
     if batched_small:
         print(f"# batched small: {batched_small['value']:.4e} su/s over {batched_small['lattices']} lattices, "
               f"{batched_small['speedup_vs_sequential']:.2f}x vs sequential", file=sys.stderr, flush=True)
-    serv = None if args.no_served else served(args.served_requests, capacity_su=fp32["value"])
+    serv = None if args.no_served else served(args.served_requests)
     if serv:
         print(f"# served: {serv['throughput_su_per_s']:.4e} su/s, p50 {serv['ttc_p50_s']:.2f} s, "
               f"p99 {serv['ttc_p99_s']:.2f} s", file=sys.stderr, flush=True)

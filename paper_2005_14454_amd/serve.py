@@ -17,7 +17,7 @@ import math
 import sys
 import time
 from collections import deque
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -67,6 +67,15 @@ def make_stream(n: int, rate: float, seed: int = 5, nmin: int = 64, nmax: int = 
             p64 = Params(N=N, precision="fp64", m=m, s_early=s, s_late=s)
             reqs.append(Request(len(reqs), p64, lat_seed, nsteps, measure_every, t, pair_of=len(reqs) - 1))
     return reqs
+
+
+def saturated_throughput(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 2) -> float:
+    """Site-updates/s the pool sustains on this request mix when every
+    request is there from the start (the serving capacity the arrival rate
+    is set against).  The requests are copied; their records stay empty."""
+    burst = [replace(r, arrival=0.0, admitted=math.nan, done=math.nan, pool_id=-1, step_config=None, series=[])
+             for r in reqs]
+    return run_stream(burst, hbm_budget, max_slots, chunk)["throughput_su_per_s"]
 
 
 def run_stream(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 2, log=None):
@@ -150,14 +159,23 @@ def main(argv=None):
     ap.add_argument("--nmin", type=int, default=64)
     ap.add_argument("--nmax", type=int, default=512)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--capacity-su", type=float, default=3.0e10, help="site-updates/s used to set the rate")
+    ap.add_argument("--capacity-su", type=float, default=0.0,
+                    help="site-updates/s the rate is set against; 0 = measure it (all of the first "
+                         "--capacity-sample requests at once)")
+    ap.add_argument("--capacity-sample", type=int, default=60)
     args = ap.parse_args(argv)
+    budget = int(args.budget_gb * 1e9)
     probe = make_stream(args.requests, 1.0, args.seed, args.nmin, args.nmax)
     work = np.mean([r.params.N ** 3 * r.nsteps for r in probe])
-    rate = args.rate if args.rate > 0 else 0.7 * args.capacity_su / work
+    capacity = args.capacity_su
+    if args.rate <= 0 and capacity <= 0:
+        capacity = saturated_throughput(probe[:args.capacity_sample], budget)
+        print(f"capacity on the request mix: {capacity:.4e} site-updates/s", file=sys.stderr, flush=True)
+    rate = args.rate if args.rate > 0 else 0.7 * capacity / work
     reqs = make_stream(args.requests, rate, args.seed, args.nmin, args.nmax)
-    out = run_stream(reqs, int(args.budget_gb * 1e9), log=lambda s: print(s, file=sys.stderr, flush=True))
+    out = run_stream(reqs, budget, log=lambda s: print(s, file=sys.stderr, flush=True))
     out["arrival_rate_per_s"] = rate
+    out["capacity_su_per_s"] = capacity if args.rate <= 0 else None
     out["mean_site_updates_per_request"] = float(work)
     print(json.dumps(out), flush=True)
 

@@ -104,6 +104,34 @@ def test_pool_admission_by_footprint(ah):
         assert pool.submit(p, 2, 5, 0) is None             # no free slot
 
 
+def test_pool_error_paths(ah):
+    """Unknown ids and unfinished requests are refused without touching the
+    pool; a refused submission takes nothing."""
+    from paper_2005_14454_amd import AHError, Params
+    with ah.Pool(hbm_budget=256 << 20, max_slots=2) as pool:
+        rid = pool.submit(Params(N=16, precision="fp32"), 1, 4, 2)
+        before = pool.stats()
+        with pytest.raises(AHError):
+            pool.step_config(rid + 1000)
+        with pytest.raises(AHError):
+            pool.progress(rid + 1000)
+        with pytest.raises(KeyError):
+            pool.get_state(rid + 1000)
+        with pytest.raises(ValueError):
+            pool.get_state(rid, 17)                       # not the lattice's N
+        with pytest.raises(AHError):
+            pool.results(rid)                              # not finished yet
+        with pytest.raises(AHError):
+            pool.submit(Params(N=16, gauge_action="noncompact"), 1, 4, 2)
+        with pytest.raises(AHError):
+            pool.submit(Params(N=400, precision="fp64"), 1, 4, 2)   # larger than the whole budget
+        after = pool.stats()
+        assert (after["active"], after["bytes_in_use"]) == (before["active"], before["bytes_in_use"])
+        pool.advance(5)
+        assert pool.poll() == [rid]
+        assert [m["step"] for m in pool.results(rid)] == [0, 2, 4]
+
+
 def test_pool_staggered_completion_and_progress(ah):
     from paper_2005_14454_amd import Params
     with ah.Pool(hbm_budget=512 << 20, max_slots=8) as pool:
