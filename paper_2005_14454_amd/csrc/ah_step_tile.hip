@@ -25,6 +25,9 @@
 #include "ah_device.h"
 #include "ah_internal.h"
 
+#define AH_SINCOS_QUAL __device__
+#include "ah_sincos.h"
+
 #pragma clang fp contract(off)
 
 namespace ah {
@@ -63,7 +66,25 @@ __device__ inline Cx<R> cmulc(Cx<R> a, Cx<R> b)  // conj(a) * b
     return {fm(a.r, b.r, a.i * b.i), fm(a.r, b.i, -(a.i * b.r))};
 }
 
-__device__ inline void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+// FP64 links: the reduced-range sincos (accurate to ~2 ulp for |x| <= 1e9),
+// the library routine beyond that (out of line: a link phase past 1e9 is a
+// lattice long blown up, and inlined it would cost the march registers)
+__device__ __noinline__ double2 sincos_far(double x)
+{
+    double2 v;
+    sincos(x, &v.x, &v.y);
+    return v;
+}
+__device__ inline void sincos_t(double x, double* s, double* c)
+{
+    if (fabs(x) <= 1e9) {
+        sincos_reduced(x, s, c);
+    } else {
+        const double2 v = sincos_far(x);
+        *s = v.x;
+        *c = v.y;
+    }
+}
 __device__ inline void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
 
 // link U = exp(-i dx A) = (cos(dx A), -sin(dx A))
