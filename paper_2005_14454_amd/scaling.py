@@ -60,29 +60,34 @@ def mean_err(values):
 
 
 def run_ensemble(N=512, seeds=range(12), m=1.0, precision="fp32", every=5, window=(80.0, 128.0), nsteps=None,
-                 log=None):
+                 log=None, batch=None):
     """Evolve one lattice per seed to eta0 + nsteps deta (default: half a
-    light crossing, eta = dx N / 2) and fit each over the window."""
+    light crossing, eta = dx N / 2) and fit each over the window.  batch: at
+    most that many lattices resident at once (one pool per batch, in turn;
+    at 1024^3 FP32 a lattice takes 64 GB), default all."""
     seeds = list(seeds)
     p = Params(N=N, precision=precision, m=m)
     if nsteps is None:
         nsteps = int(round(0.5 * p.dx * N / p.deta))
-    budget = len(seeds) * pool_footprint(p, nsteps, every) + (256 << 20)
+    batch = len(seeds) if not batch else batch
     per_seed = {}
-    with Pool(budget, max_slots=len(seeds)) as pool:
-        ids = {pool.submit(p, s, nsteps, every): s for s in seeds}
-        if None in ids:
-            raise RuntimeError("the ensemble does not fit the pool")
-        left = set(ids)
-        done = 0
-        while left:
-            pool.advance(10)
-            done += 10
-            for rid in pool.poll():
-                left.discard(rid)
-                per_seed[ids[rid]] = pool.results(rid)
-            if log and done % 200 == 0:
-                log(f"step {done} of {nsteps}")
+    for b0 in range(0, len(seeds), batch):
+        group = seeds[b0:b0 + batch]
+        budget = len(group) * pool_footprint(p, nsteps, every) + (256 << 20)
+        with Pool(budget, max_slots=len(group)) as pool:
+            ids = {pool.submit(p, s, nsteps, every): s for s in group}
+            if None in ids:
+                raise RuntimeError("the ensemble does not fit the pool")
+            left = set(ids)
+            done = 0
+            while left:
+                pool.advance(10)
+                done += 10
+                for rid in pool.poll():
+                    left.discard(rid)
+                    per_seed[ids[rid]] = pool.results(rid)
+                if log and done % 200 == 0:
+                    log(f"seeds {group}: step {done} of {nsteps}")
     fits = {s: analyse(per_seed[s], window) for s in seeds}
     out = {"N": N, "m": m, "precision": precision, "seeds": seeds, "steps": nsteps, "every": every,
            "window": list(window), "per_seed": {str(s): f for s, f in fits.items()}}
@@ -100,9 +105,12 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--every", type=int, default=5)
     ap.add_argument("--window", type=float, nargs=2, default=(80.0, 128.0))
+    ap.add_argument("--first-seed", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=0, help="lattices resident at once (0: all)")
     args = ap.parse_args(argv)
-    out = run_ensemble(args.N, range(1, args.seeds + 1), args.m, args.precision, args.every, tuple(args.window),
-                       log=lambda s: print(s, file=sys.stderr, flush=True))
+    seeds = range(args.first_seed, args.first_seed + args.seeds)
+    out = run_ensemble(args.N, seeds, args.m, args.precision, args.every, tuple(args.window),
+                       log=lambda s: print(s, file=sys.stderr, flush=True), batch=args.batch or None)
     print(json.dumps(out), flush=True)
 
 
