@@ -67,3 +67,10 @@ def test_host_only_entry_points(lib):
     assert lib.ah_required_bytes(ctypes.byref(bad), ctypes.byref(n)) == _lib.AH_E_INVAL
     assert lib.ah_strerror(_lib.AH_E_AGAIN).decode()
     assert lib.ah_last_error(None).decode() == ""
+    # argument checks that come before any device work
+    c, r, w = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    assert lib.ah_hbm_probe(1000, 1, ctypes.byref(c), ctypes.byref(r), ctypes.byref(w)) == _lib.AH_E_INVAL
+    assert lib.ah_hbm_probe(1 << 26, 0, ctypes.byref(c), ctypes.byref(r), ctypes.byref(w)) == _lib.AH_E_INVAL
+    assert lib.ah_hbm_probe(1 << 26, 1, None, ctypes.byref(r), ctypes.byref(w)) == _lib.AH_E_INVAL
+    cfg = _lib.ah_step_config()
+    assert lib.ah_pool_step_config(None, 1, ctypes.byref(cfg)) == _lib.AH_E_INVAL
