@@ -3,7 +3,7 @@ is evolved through a constant expansion era, and the late-time rates
 d xi_L / d eta, d xi_W / d eta and the means of <v^2>_phi and <v^2>_omega are
 fitted over a conformal-time window, one value per realisation, then
 averaged.  This is
-the validation the paper runs with its code (section 3, Table 1: for 512^3
+the validation the paper runs with its code (section 4, Table 1: for 512^3
 boxes in the radiation era the window is eta in [80, 128]).
 
 All realisations are resident at once in a lattice pool and advance

@@ -1,7 +1,7 @@
 """Physics sanity of the whole path (step and diagnostics together): three
 512^3 random-phase lattices through the radiation era to eta = 129, fitted
-over eta in [80, 128] as the paper does for its 512^3 boxes (section 3,
-Table 1).  Every realisation must show a scaling network: the separations
+over eta in [80, 128] as the paper does for its 512^3 boxes (section 4,
+code validation, and Table 1).  Every realisation must show a scaling network: the separations
 grow at the rates the paper's simulations find (about 0.25 - 0.32 per unit
 conformal time), the mean velocity squared from phi sits near 0.27 - 0.31
 and the equation-of-state estimate above it (Table 1: about 10% higher).

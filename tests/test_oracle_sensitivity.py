@@ -1,7 +1,7 @@
 """Sensitivity of the evolution to rounding (CPU, oracle only).
 
 The random-phase network is chaotic: a difference of one unit in the last
-place of phi in the initial condition (section 3's random-phase start,
+place of phi in the initial condition (section 2's random-phase start,
 64^3 radiation era, seed 0) grows step by step.  How far it has grown by
 step 100 is the floor below which no two correct FP64 implementations, which
 round differently, can be expected to agree on that run; the FP64 parity
