@@ -17,7 +17,8 @@
  * the compact plaquette field strength F_ij = sin(Theta_ij)/dx^2 with
  * Theta_ij^x = dx (A_i^x + A_j^{x+i} - A_i^{x+j} - A_j^x) (or Theta/dx^2 for
  * the non-compact action), a(eta) = (eta/eta_ref)^m, f = a^(2s),
- * delta = (alpha/2) m deta/eta and omega = (1-s) delta (section 2, damping
+ * delta = (alpha/2) m deta/eta (damp_gamma deta/2 during an optional
+ * artificial damping phase) and omega = (1-s) delta (section 2, damping
  * coefficients and coupling scaling).
  *
  * Diagnostics (section 2, string-separation and velocity estimators):
