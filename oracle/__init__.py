@@ -11,9 +11,9 @@ field strength, and the diagnostics xi_L, xi_W, <v^2>_phi, <v^2>_omega plus
 energy and the Gauss-law residual.  All arithmetic lives in ahref.c; this module only
 marshals arguments.
 
-Pins (what fixes the oracle other than itself) live in tests/test_oracle_*.py.
-Parity unpinned: xi_L, R and <v^2>_phi beyond the energy split that feeds
-them (no closed form or printed value exists for them).
+Pins (what fixes the oracle other than itself) live in tests/test_oracle_*.py;
+every output has one (closed forms, invariants, brute force, a published
+test vector).
 """
 import ctypes
 import math

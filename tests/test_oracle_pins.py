@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import torch
 
-from inputs import grid, random_gauge, random_state
+from inputs import grid, near_cut_state, random_gauge, random_state, sample_sites
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -313,6 +313,94 @@ def test_gauss_residual_detects_violation(oracle_mod):
     nz = np.flatnonzero(G)
     assert set(nz.tolist()) == {0, 1}
     assert abs(G[0] - 0.02) < 1e-17 and abs(G[1] + 0.02) < 1e-17
+
+
+@pytest.mark.parametrize("n", [0, 3])
+def test_gauss_norms_closed_form(oracle_mod, n):
+    """The three Gauss norms of a hand-built state, in closed form.
+
+    phi = sigma everywhere, E_0 = eps at the origin only and Pi = i kappa at
+    the origin only.  The residual of section 2's Gauss law is then non-zero
+    at two sites: G = eps/dx - c sigma kappa at the origin (divergence minus
+    coupled charge) and G = -eps/dx at the +x neighbour (divergence only).
+    With a = eps/dx and b = c sigma kappa:
+        gauss_max = max(|a - b|, a),
+        gauss_rms = sqrt(((a - b)^2 + a^2) / N^3),
+        gauss_rel = sqrt((a - b)^2 + a^2) / sqrt(a^2 + a^2 + b^2).
+    c is the coupling that keeps the law exact under the kick, 2 e0^2 f_0 at
+    the start and 2 e0^2 f_{n-1} (1 + delta_{n-1}) / (1 + omega_{n-1}) after
+    it; that this c is the right one is pinned separately by the exactness of
+    the law along evolved runs (s = 1 with m = 1 is among them).  dx, e0 and
+    sigma differ from 1 and f from 1 (s = 1), so a wrong power of dx, a
+    dropped coupling factor, a mean over N instead of N^3 or a relative norm
+    without its charge term fails here."""
+    N, dx, e0, sigma, deta, eta0, eta_ref = 6, 0.7, 0.8, 1.3, 0.1, 1.0, 2.0
+    p = oracle_mod.params(N=N, dx=dx, e0=e0, sigma=sigma, m=1.0, s_early=1.0, s_late=1.0,
+                          eta0=eta0, eta_ref=eta_ref, deta=deta)
+    eps, kappa = 0.05, 0.2
+    st = np.zeros((10, N ** 3))
+    st[0] = sigma
+    st[7, 0] = eps
+    st[3, 0] = kappa
+    if n == 0:
+        f = (eta0 / eta_ref) ** 2
+        c = 2 * e0 ** 2 * f
+    else:
+        eta = eta0 + (n - 1) * deta
+        f = (eta / eta_ref) ** 2
+        delta = deta / eta  # (alpha/2) m deta / eta with alpha = 2, m = 1; omega = 0 at s = 1
+        c = 2 * e0 ** 2 * f * (1 + delta)
+    a, b = eps / dx, c * sigma * kappa
+    G = oracle_mod.gauss(p, st, n)
+    assert set(np.flatnonzero(G).tolist()) == {0, 1}
+    assert abs(G[0] - (a - b)) < 1e-15 and abs(G[1] + a) < 1e-15
+    m = oracle_mod.measure(p, st, n)
+    assert abs(m["gauss_max"] - max(abs(a - b), a)) < 1e-15
+    assert abs(m["gauss_rms"] - math.sqrt(((a - b) ** 2 + a ** 2) / N ** 3)) < 1e-15
+    want_rel = math.sqrt((a - b) ** 2 + a ** 2) / math.sqrt(2 * a ** 2 + b ** 2)
+    assert abs(m["gauss_rel"] - want_rel) < 1e-14
+    # no violation, no denominator: the relative norm is defined as 0
+    vac = np.zeros((10, N ** 3))
+    vac[0] = sigma
+    mv = oracle_mod.measure(p, vac, n)
+    assert mv["gauss_rel"] == 0.0 and mv["gauss_rms"] == 0.0 and mv["gauss_max"] == 0.0
+
+
+@pytest.mark.parametrize("N,dx,sigma,lambda0", [(5, 0.7, 1.3, 1.5), (6, 0.5, 0.6, 2.0)])
+def test_xi_L_closed_form_false_vacuum(oracle_mod, N, dx, sigma, lambda0):
+    """xi_L of section 2 (sqrt(-mu V / sum_x L_x), mu = 2 pi sigma^2, V the
+    comoving volume, the sum carrying the cell volume dx^3) on the symmetric
+    state phi = Pi = A = E = 0.  Nothing moves (every force is proportional
+    to phi or to a field that is zero), so the Lagrangian density is minus
+    the potential, -(lambda0 f / 4) sigma^4, at every site: sum_L =
+    -(lambda0 f/4) sigma^4 (N dx)^3 and xi_L = sqrt(8 pi / (lambda0 f sigma^2)),
+    independent of N and dx.  sigma, lambda0, dx and f (s = 1, a = 1/2) all
+    differ from 1, so a wrong mu, a missing cell or box volume or a dropped
+    f fails here."""
+    p = oracle_mod.params(N=N, dx=dx, sigma=sigma, lambda0=lambda0, m=1.0, s_early=1.0, s_late=1.0,
+                          eta0=1.0, eta_ref=2.0)
+    f = 0.25
+    m = oracle_mod.measure(p, np.zeros((10, N ** 3)), 0)
+    assert abs(m["f"] - f) < 1e-16
+    want_L = -(lambda0 * f / 4) * sigma ** 4 * (N * dx) ** 3
+    assert abs(m["sum_L"] - want_L) < 1e-13 * abs(want_L)
+    assert abs(m["xi_L"] - math.sqrt(8 * math.pi / (lambda0 * f * sigma ** 2))) < 1e-13
+    # a positive Lagrangian sum (pure kinetic energy in the vacuum) has no xi_L
+    st = np.zeros((10, N ** 3))
+    st[0] = sigma
+    st[2] = 0.3
+    assert math.isnan(oracle_mod.measure(p, st, 0)["xi_L"])
+
+
+def test_winding_sites_matches_full_winding(oracle_mod):
+    """The per-site winding query returns the full winding array's entries."""
+    N = 7
+    p = oracle_mod.params(N=N)
+    for st in (random_state(N, seed=61), near_cut_state(N, seed=62)):
+        W = oracle_mod.winding(p, st)
+        sites = sample_sites(N, 60, seed=63)
+        assert np.array_equal(oracle_mod.winding_sites(p, st, sites), W[:, sites].T)
+        assert np.abs(W).sum() > 0
 
 
 @pytest.mark.parametrize("compact", [1, 0])
