@@ -156,6 +156,17 @@ int ah_get_state(ah_handle* h, double* host_soa, int64_t* step);
  * device buffers (count*8 and count*10*sizeof(real) bytes).  Synchronous. */
 int ah_gather(ah_handle* h, const int64_t* sites, int64_t count, double* host_out);
 
+/* ah_gather without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, checks and results as ah_gather, with
+ * count <= 65536 (AH_E_INVAL above that, before any device work).  The site
+ * indices and gathered values are staged in a fixed device scratch array of
+ * 5.5 MB per GPU, held by the library until the process ends; the call makes
+ * no device (or host) allocation.  Every call on a GPU uses that GPU's one
+ * array, so calls that overlap on one GPU (from several host threads, or on
+ * several streams) race: the caller serialises them.  Synchronous. */
+int ah_gather_noalloc(ah_handle* h, const int64_t* sites, int64_t count, double* host_out);
+
 /* Current snapshot index (host-side counter; no synchronisation). */
 int ah_get_step(const ah_handle* h, int64_t* step);
 

@@ -195,6 +195,15 @@ class Lattice:
                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), what="ah_gather")
         return out
 
+    def gather_noalloc(self, sites) -> np.ndarray:
+        """As gather(), staged in the library's fixed device scratch (no device
+        allocation; at most 65536 sites per call)."""
+        s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+        out = np.empty((len(s), 10), dtype=np.float64)
+        self._call(self._lib.ah_gather_noalloc, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(s),
+                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), what="ah_gather_noalloc")
+        return out
+
     def winding(self) -> np.ndarray:
         w = np.empty((3, self.V), dtype=np.int8)
         self._call(self._lib.ah_get_winding, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), what="ah_get_winding")

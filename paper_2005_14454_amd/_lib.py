@@ -99,6 +99,7 @@ def load():
         "ah_get_state": ([vp, P(ctypes.c_double), P(i64)], ctypes.c_int),
         "ah_get_step": ([vp, P(i64)], ctypes.c_int),
         "ah_gather": ([vp, P(i64), i64, P(ctypes.c_double)], ctypes.c_int),
+        "ah_gather_noalloc": ([vp, P(i64), i64, P(ctypes.c_double)], ctypes.c_int),
         "ah_step": ([vp, i64], ctypes.c_int),
         "ah_measure": ([vp, P(ah_measurement)], ctypes.c_int),
         "ah_step_measured": ([vp, i64, ctypes.c_int32, P(ah_measurement), ctypes.c_int32, P(ctypes.c_int32)],

@@ -152,6 +152,15 @@ constexpr int kXcdCount = 8;           // XCDs of the device; block b runs on XC
 constexpr int kSeriesStride = 18;      // M_COUNT sums + step index + pad
 static_assert(M_COUNT + 1 <= kSeriesStride, "a series record holds the sums and the step index");
 
+// ---- fixed device scratch (ah_scratch.hip) ---------------------------------
+// Sites one ah_gather_noalloc call may ask for, and the scratch that holds
+// their indices and their FP64-sized values.
+constexpr int64_t kGatherMax = 65536;
+constexpr size_t kScratchBytes = (size_t)kGatherMax * sizeof(int64_t) + (size_t)kGatherMax * 10 * sizeof(double);
+// Device address of `device`'s copy of the scratch (looked up on the first
+// call for that device, with it current).
+hipError_t scratch_ptr(int device, void** out);
+
 // ---- launchers (ah_kernels.hip, ah_step_tile.hip) -------------------------
 template <typename R>
 hipError_t launch_init(const Fields<R>& f, int N, double sigma, uint64_t seed, hipStream_t s);

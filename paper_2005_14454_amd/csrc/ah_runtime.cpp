@@ -758,6 +758,46 @@ int ah_gather(ah_handle* h, const int64_t* sites, int64_t count, double* host_ou
     });
 }
 
+int ah_gather_noalloc(ah_handle* h, const int64_t* sites, int64_t count, double* host_out)
+{
+    return no_throw([&]() -> int {
+        if (!h || count < 0 || (count > 0 && (!sites || !host_out)))
+            return fail(h, AH_E_INVAL, "ah_gather_noalloc: bad argument");
+        if (count > kGatherMax)
+            return fail(h, AH_E_INVAL, "ah_gather_noalloc: more than 65536 sites in one call");
+        if (!h->ready) return fail(h, AH_E_STATE, "ah_gather_noalloc before ah_init/ah_set_state");
+        for (int64_t k = 0; k < count; ++k)
+            if (sites[k] < 0 || sites[k] >= h->V)
+                return fail(h, AH_E_INVAL, "ah_gather_noalloc: site index out of range");
+        if (count == 0) return AH_OK;
+        DeviceGuard g(h->device);
+        void* base = nullptr;
+        hipError_t e = scratch_ptr(h->device, &base);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_gather_noalloc: scratch lookup");
+        // scratch layout: kGatherMax site indices, then the gathered values
+        int64_t* d_sites = (int64_t*)base;
+        void* d_out = (char*)base + (size_t)kGatherMax * sizeof(int64_t);
+        const size_t rb = h->real_bytes;
+        e = hipMemcpyAsync(d_sites, sites, count * sizeof(int64_t), hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess)
+            e = rb == 8 ? launch_gather<double>(fields_of<double>(h, h->cur), d_sites, count, h->V, (double*)d_out,
+                                                h->stream)
+                        : launch_gather<float>(fields_of<float>(h, h->cur), d_sites, count, h->V, (float*)d_out,
+                                               h->stream);
+        // FP32 values land in the first half of host_out and are widened in
+        // place, last first, so no host staging buffer is needed either
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host_out, d_out, count * 10 * rb, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_gather_noalloc");
+        if (rb == 4) {
+            const float* src = (const float*)host_out;
+            for (int64_t q = count * 10 - 1; q >= 0; --q) host_out[q] = (double)src[q];
+        }
+        return AH_OK;
+    });
+}
+
 int ah_get_step(const ah_handle* h, int64_t* step)
 {
     if (!h || !step) return AH_E_INVAL;
