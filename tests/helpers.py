@@ -49,6 +49,26 @@ def same_record(a: dict, b: dict) -> bool:
     return True
 
 
+def close_record(a: dict, b: dict, rtol: float) -> bool:
+    """Equality of two measurement dicts up to the rounding of their FP64
+    sums (a diagnostics pass over other workgroup shapes adds the same site
+    values in another order): integers and flags exactly, every float within
+    rtol of the larger magnitude of the pair (NaN equals NaN)."""
+    if a.keys() != b.keys():
+        return False
+    for k in a:
+        x, y = a[k], b[k]
+        if isinstance(x, float) and isinstance(y, float):
+            if math.isnan(x) or math.isnan(y):
+                if not (math.isnan(x) and math.isnan(y)):
+                    return False
+            elif abs(x - y) > rtol * max(abs(x), abs(y)):
+                return False
+        elif x != y:
+            return False
+    return True
+
+
 def run_alone(gp, seed, nsteps, every, tile, zchunk):
     """One lattice run alone through ah_step / ah_measure: its fields after
     nsteps and its diagnostics series (every `every` steps and the last)."""

@@ -12,7 +12,7 @@
 import numpy as np
 import pytest
 
-from helpers import both_params, field_scaled_error, run_alone, same_record
+from helpers import both_params, close_record, field_scaled_error, run_alone, same_record
 
 pytestmark = pytest.mark.gpu
 
@@ -174,3 +174,68 @@ def test_pool_after_host_only_calls_in_a_fresh_process():
             "print('ok', flush=True)\n")
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "ok" in r.stdout, r.stderr[-3000:]
+
+
+def test_pool_recorded_tiles_match_alone_and_oracle(oracle_mod, ah):
+    """The tile shapes the pool runs for the ensemble workloads (FP32 64 x 4
+    at N = 48 and 96 class sizes, FP32 32 x 8 at N = 32, FP32 128 x 4 -- a
+    tuned 128 x 8 halved -- and FP64 32 x 8), forced through the tuning table
+    on small and ragged N, plain and measured steps mixed in one pool.  Each
+    lattice's fields equal the same lattice's run alone bitwise; so do its
+    diagnostics where the lone lattice measures on the pool's tile shape
+    (FP64 32 x 8), while elsewhere (a lone FP32 lattice measures on 64 x 8)
+    the same site values are summed over other workgroups, so the FP64 sums
+    agree to their rounding (1e-11) and the winding counts exactly;
+    after 40 steps its fields are within the scope's tolerance of the oracle
+    (FP32 1e-4, FP64 1e-10, field-scaled), its windings equal the oracle's on
+    the same snapshot, and its other diagnostics agree with the oracle's
+    measurement of that snapshot."""
+    from helpers import both_params
+    cases = [  # (N, precision, tile recorded, tile the pool runs, m, seed)
+        (48, "fp32", (64, 4), (64, 4), 1.0, 21),
+        (36, "fp32", (64, 4), (64, 4), 2.0, 22),
+        (32, "fp32", (32, 8), (32, 8), 1.0, 23),
+        (20, "fp32", (32, 8), (32, 8), 2.0, 24),
+        (40, "fp32", (128, 8), (128, 4), 1.0, 25),
+        (24, "fp64", (32, 8), (32, 8), 2.0, 26),
+    ]
+    nsteps, every = 40, 8
+    ah.tune_clear()
+    try:
+        reqs = []
+        for N, prec, rec, _, m, seed in cases:
+            op, gp = both_params(oracle_mod, N, prec, m=m)
+            ah.tune_set(gp, rec, 0)
+            reqs.append((op, gp, seed))
+        with ah.Pool(hbm_budget=1 << 30, max_slots=8) as pool:
+            ids = [pool.submit(gp, seed, nsteps, every) for _, gp, seed in reqs]
+            assert all(i is not None for i in ids)
+            cfgs = [pool.step_config(rid) for rid in ids]
+            pool.advance(nsteps + 1)
+            assert sorted(pool.poll()) == sorted(ids)
+            states = [pool.get_state(rid, gp.N) for rid, (_, gp, _) in zip(ids, reqs)]
+            series = [pool.results(rid) for rid in ids]
+    finally:
+        ah.tune_clear()
+    for (N, prec, rec, runs, m, seed), (op, gp, _), cfg, st, ser in zip(cases, reqs, cfgs, states, series):
+        assert cfg["tile"] == runs, (N, prec, cfg)
+        alone_st, alone_ser = run_alone(gp, seed, nsteps, every, cfg["tile"], cfg["zchunk"])
+        assert np.array_equal(st, alone_st), (N, prec, runs)
+        assert len(ser) == len(alone_ser) == nsteps // every + 1
+        same_shape = runs == ((32, 8) if prec == "fp64" else (64, 8))
+        for a, b in zip(ser, alone_ser):
+            if same_shape:
+                assert same_record(a, b), (N, prec, a["step"])
+            else:
+                assert close_record(a, b, 1e-11), (N, prec, a["step"], a, b)
+        ref = oracle_mod.step(op, oracle_mod.init(op, seed), 0, nsteps)
+        err = max(field_scaled_error(st, ref).values())
+        assert err <= (1e-10 if prec == "fp64" else 1e-4), (N, prec, err)
+        om = oracle_mod.measure(op, st, nsteps)
+        last = ser[-1]
+        assert last["step"] == nsteps
+        assert last["winding_sum_abs"] == om["winding_sum_abs"], (N, prec)
+        rtol = 1e-11 if prec == "fp64" else 1e-5
+        for k in ("energy", "e_kin", "e_grad", "e_pot", "e_el", "e_mag"):
+            assert abs(last[k] - om[k]) <= rtol * abs(om["energy"]), (N, prec, k, last[k], om[k])
+        assert abs(last["gauss_rms"] - om["gauss_rms"]) <= (1e-12 if prec == "fp64" else 1e-5), (N, prec)
