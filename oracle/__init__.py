@@ -22,7 +22,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libahref.so")
+# AHREF_LIB names another build of ahref.c (the planted-mistake tests load
+# deliberately broken copies this way)
+LIB_PATH = os.environ.get("AHREF_LIB") or os.path.join(HERE, "libahref.so")
 
 NCOMP = 10
 COMPONENTS = ("phi_re", "phi_im", "pi_re", "pi_im", "A0", "A1", "A2", "E0", "E1", "E2")

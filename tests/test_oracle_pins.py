@@ -609,6 +609,38 @@ def test_velocity_ratio_plane_wave(oracle_mod):
     assert abs(m["energy"] - (m["e_kin"] + m["e_grad"] + m["e_pot"] + m["e_el"] + m["e_mag"])) < 1e-11 * m["energy"]
 
 
+def test_velocity_ratio_weighted_by_lagrangian(oracle_mod):
+    """R of section 2 weights |Pi|^2 and |D+ phi|^2 with the site Lagrangian:
+    R = sum_x |Pi_bar|^2 L_x / sum_x |D+ phi|^2 L_x.  Plane wave phi = exp(i k x0)
+    (|phi| = sigma: no potential), A = E = 0, m = 0, and Pi^{n-1/2} = c(x) phi
+    with c = c1 on the lower half of the x2 planes and c2 on the upper half.
+    Per site: gradient G = 4 sin^2(k dx/2)/dx^2; the kick adds -deta G phi, so
+    the centred momentum is (c - deta G/2) phi; the current J_x = sin(k dx)/dx
+    gives E^{n+1/2} = deta 2 e0^2 J_x, so the electric density is
+    (E^{n+1/2}/2)^2 / (2 e0^2); no magnetic field.  The Lagrangian differs
+    between the halves, so the weighted ratio differs from the plain one."""
+    N, dx, deta = 8, 0.5, 0.1
+    p = oracle_mod.params(N=N, m=0.0, dx=dx, deta=deta)
+    x0, x1, x2 = grid(N)
+    k = 2 * np.pi / (N * dx)
+    ph = k * x0 * dx
+    c = np.where(x2 < N // 2, 2.0, 0.0)
+    st = np.zeros((10, N ** 3))
+    st[0], st[1] = np.cos(ph), np.sin(ph)
+    st[2], st[3] = c * st[0], c * st[1]
+    G = 4 * math.sin(k * dx / 2) ** 2 / dx ** 2
+    kin = (c - deta * G / 2) ** 2
+    Ehalf = deta * 2.0 * math.sin(k * dx) / dx
+    el = (Ehalf / 2) ** 2 / 2.0
+    L = kin - G + el
+    R = float(np.sum(kin * L) / np.sum(G * L))
+    assert abs(R - float(np.sum(kin) / (G * N ** 3))) > 0.1  # the weighting matters here
+    m = oracle_mod.measure(p, st, 0)
+    assert abs(m["R"] - R) < 1e-12 * abs(R), (m["R"], R)
+    assert abs(m["v2_phi"] - 2 * R / (1 + R)) < 1e-12
+    assert abs(m["sum_L"] - float(np.sum(L)) * dx ** 3) < 1e-12 * abs(float(np.sum(L)) * dx ** 3)
+
+
 def test_equation_of_state_velocity_single_terms(oracle_mod):
     """<v^2>_omega = (1 + 3 w)/2 with w the L-weighted ratio of pressure to
     energy density.  A state holding one kind of energy only has the textbook
