@@ -122,8 +122,10 @@ typedef struct ah_handle ah_handle;
  * mu >= 2.  AH_E_INVAL on bad parameters or step < 0. */
 int ah_stability_margin(const ah_params* p, int64_t step, double* mu);
 
-/* Device bytes one lattice needs: 15 field arrays (10 state + phi/A ping-pong)
- * of N^3 reals each, plus reduction scratch.  AH_E_INVAL on bad params. */
+/* Device bytes one lattice needs: 20 field arrays (the 10 state fields twice:
+ * a single step drifts phi and A into the other buffer, a two-step pass writes
+ * all ten) of N^3 reals each, plus reduction scratch.  AH_E_INVAL on bad
+ * params. */
 int ah_required_bytes(const ah_params* p, size_t* bytes);
 
 /* Create a handle on the current HIP device.
@@ -204,13 +206,20 @@ int ah_get_winding(ah_handle* h, int8_t* host_w);
 #define AH_KERNEL_AUTO 0 /* tiled kernel for the compact action, site kernel otherwise */
 #define AH_KERNEL_SITE 1 /* one thread per site, every neighbour read from global memory */
 #define AH_KERNEL_TILE 2 /* z-marching tiles with links shared through LDS (compact action only) */
+#define AH_KERNEL_TILE2 3 /* as AH_KERNEL_TILE, with two steps per pass over the fields wherever two plain
+                           * steps follow each other: the step n -> n+1 is formed on the tile plus a
+                           * one-site ring and kept in LDS, the step n+1 -> n+2 on the tile from it, so
+                           * the fields are read and written once per two steps.  Bitwise equal to two
+                           * single steps.  Tiles (32,8), (64,4), FP32 also (64,8); the single steps it
+                           * leaves (an odd count, diagnostics) run the tiled kernel on the same tile */
 
 /* Performance knobs of the step; they do not change the equations.  The
  * tiled kernel gives bitwise-identical results for every tile shape and
  * z-chunk; the site kernel agrees with it to rounding. */
 typedef struct ah_step_config {
     int32_t kernel;         /* AH_KERNEL_* */
-    int32_t tile_x, tile_y; /* tiled kernel: (64,8), (64,4), (32,8), (128,4) (FP32 also (64,16), (128,8)); 0,0 = default */
+    int32_t tile_x, tile_y; /* tiled kernel: (64,8), (64,4), (32,8), (128,4) (FP32 also (64,16), (128,8));
+                             * two-step kernel: see AH_KERNEL_TILE2; 0,0 = default */
     int32_t zchunk;         /* x2-planes per workgroup of the tiled kernel; 0 = automatic, else >= 2
                              * for N <= 128 and >= 8 above (the last chunk of a column may be shorter) */
 } ah_step_config;
@@ -227,7 +236,9 @@ int ah_synchronize(ah_handle* h);
 /* Step-kernel timing with HIP events on the handle's stream.  While enabled
  * every step-kernel launch is bracketed by an event pair; ah_get_timing
  * synchronises and returns the summed kernel time (ms) and the number of
- * timed launches since the last enable.  Lattice results do not change. */
+ * steps those launches advanced since the last enable (a two-step pass counts
+ * two), so total_ms / launches is the kernel time per step.  Lattice results
+ * do not change. */
 int ah_set_timing(ah_handle* h, int enable);
 int ah_get_timing(ah_handle* h, double* total_ms, int64_t* launches);
 
@@ -235,10 +246,11 @@ int ah_get_timing(ah_handle* h, double* total_ms, int64_t* launches);
 int ah_destroy(ah_handle* h);
 
 /* ------------------------------------------------------------- autotuner */
-/* Time every supported tile shape and z-chunk of the tiled step for
- * (p->precision, p->N) on a scratch lattice (library-allocated: 15 N^3 reals,
+/* Time every supported tile shape and z-chunk of the tiled step, with one
+ * and with two steps per pass (AH_KERNEL_TILE, AH_KERNEL_TILE2), for
+ * (p->precision, p->N) on a scratch lattice (library-allocated: 20 N^3 reals,
  * freed before returning; `steps` timed steps per candidate) and record the
- * fastest in the process-wide tuning table.  Handles created afterwards with
+ * fastest per step in the process-wide tuning table.  Handles created afterwards with
  * the automatic configuration, and lattices submitted to a pool, use the
  * recorded choice.  Synchronous.  AH_E_INVAL for the non-compact action. */
 int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double* best_ms);
@@ -246,16 +258,18 @@ int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double*
 /* Recorded choice for (p->precision, p->N); AH_E_AGAIN if none. */
 int ah_tune_lookup(const ah_params* p, ah_step_config* out);
 
-/* Record a choice by hand: kernel AH_KERNEL_TILE, a tile shape supported
- * for the precision, zchunk 0 (automatic) or at least the minimum of
- * ah_step_config.zchunk; AH_E_INVAL otherwise. */
+/* Record a choice by hand: kernel AH_KERNEL_TILE or AH_KERNEL_TILE2, a tile
+ * shape that kernel supports for the precision, zchunk 0 (automatic) or at
+ * least the minimum of ah_step_config.zchunk; AH_E_INVAL otherwise.  Pool
+ * lattices take the tile shape of a two-step entry and step once per replay. */
 int ah_tune_set(const ah_params* p, const ah_step_config* c);
 
 /* Forget every recorded choice. */
 int ah_tune_clear(void);
 
 /* Save / load the tuning table as JSON (one entry per line:
- * {"precision": "fp32", "N": 128, "tile_x": 64, "tile_y": 8, "zchunk": 32, "ms": 0.01}).
+ * {"precision": "fp32", "N": 128, "tile_x": 64, "tile_y": 8, "zchunk": 32, "ms": 0.01, "kernel": "tile"};
+ * "kernel" is "tile" or "tile2", "tile" when absent).
  * Loading adds to (and overrides entries of) the table.  AH_E_INVAL if the
  * file cannot be opened or holds an entry that does not parse or that
  * ah_tune_set would refuse; the table is then unchanged. */
@@ -301,18 +315,30 @@ int ah_pool_footprint(const ah_params* p, int64_t nsteps, int32_t measure_every,
  * diagnostics of snapshots 0, measure_every, 2 measure_every, ... and always
  * of the final snapshot (measure_every = 0: the final one only).  Returns the
  * request id.  AH_E_AGAIN when no slot or not enough contiguous free memory is
- * available now; AH_E_NOMEM when the request exceeds the whole budget.
- * Synchronous (waits for the pool stream). */
+ * available now; AH_E_NOMEM when the request exceeds the whole budget.  The
+ * uploads and the initial condition are queued on the pool stream after the
+ * replays already there (through pinned staging; the call does not wait for
+ * them unless a coefficient table exceeds 16 MB). */
 int ah_pool_submit(ah_pool* pool, const ah_params* p, uint64_t seed, int64_t nsteps, int32_t measure_every,
                    int64_t* id);
 
-/* Enqueue nsteps graph replays (one step of every active lattice each).
- * Asynchronous. */
+/* Enqueue nsteps graph replays (one step of every active lattice each) and a
+ * copy of the step counters behind them.  Asynchronous, with at most eight
+ * replays queued ahead of the host: past that it waits until the GPU has
+ * reached a replay four or more behind the newest (never for the whole
+ * queue).  A set of lattices changed by submit or results gets a new graph
+ * here, built while earlier replays still run. */
 int ah_pool_advance(ah_pool* pool, int32_t nsteps);
 
 /* Ids of lattices that finished since the last poll (at most cap; *n is the
  * number written).  Synchronises with the pool stream. */
 int ah_pool_poll(ah_pool* pool, int64_t* done_ids, int32_t cap, int32_t* n);
+
+/* As ah_pool_poll without waiting: reports the lattices that the newest
+ * counter copy already on the host shows finished (the copies queued by
+ * ah_pool_advance land as the GPU reaches them).  For serving loops that keep
+ * the GPU busy while they admit and collect requests. */
+int ah_pool_poll_async(ah_pool* pool, int64_t* done_ids, int32_t cap, int32_t* n);
 
 /* Tile shape and z-chunk a request is stepped with (kernel AH_KERNEL_TILE).
  * The pool takes the tuned configuration of the request's (precision, N), or
@@ -332,7 +358,9 @@ int ah_pool_get_state(ah_pool* pool, int64_t id, double* host_soa, int64_t* step
 /* Measurement series of a finished request (at most cap records; *n written)
  * and release of its slot and memory.  A request with measure_every = k > 0
  * has nsteps/k + 2 records at most (every k-th step and the final one); with
- * k = 0, one.  AH_E_AGAIN if it has not finished. */
+ * k = 0, one.  AH_E_AGAIN if it has not finished.  For a request a poll has
+ * reported, the series is read on a side stream without waiting for the
+ * replays queued on the pool stream. */
 int ah_pool_results(ah_pool* pool, int64_t id, ah_measurement* series, int32_t cap, int32_t* n);
 
 /* Occupancy figures. */

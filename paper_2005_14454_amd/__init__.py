@@ -232,15 +232,18 @@ class Lattice:
 
     # -- kernel choice ---------------------------------------------------------
     def set_step_config(self, kernel="auto", tile=(0, 0), zchunk=0):
-        """kernel: "auto", "site" or "tile"; tile: (tile_x, tile_y); zchunk: planes per workgroup."""
-        k = {"auto": _lib.AH_KERNEL_AUTO, "site": _lib.AH_KERNEL_SITE, "tile": _lib.AH_KERNEL_TILE}[kernel]
+        """kernel: "auto", "site", "tile" or "tile2" (two steps per pass); tile: (tile_x, tile_y);
+        zchunk: planes per workgroup."""
+        k = {"auto": _lib.AH_KERNEL_AUTO, "site": _lib.AH_KERNEL_SITE, "tile": _lib.AH_KERNEL_TILE,
+             "tile2": _lib.AH_KERNEL_TILE2}[kernel]
         c = _lib.ah_step_config(k, tile[0], tile[1], zchunk)
         self._call(self._lib.ah_set_step_config, ctypes.byref(c), what="ah_set_step_config")
 
     def get_step_config(self) -> dict:
         c = _lib.ah_step_config()
         _lib.check(self._lib.ah_get_step_config(self._h, ctypes.byref(c)))
-        name = {_lib.AH_KERNEL_SITE: "site", _lib.AH_KERNEL_TILE: "tile"}.get(c.kernel, "auto")
+        name = {_lib.AH_KERNEL_SITE: "site", _lib.AH_KERNEL_TILE: "tile",
+                _lib.AH_KERNEL_TILE2: "tile2"}.get(c.kernel, "auto")
         return {"kernel": name, "tile": (c.tile_x, c.tile_y), "zchunk": c.zchunk}
 
     # -- timing ----------------------------------------------------------------
@@ -275,7 +278,8 @@ def read_dump(path: str) -> dict:
 # ----------------------------------------------------------------- autotuner
 
 def _cfg_dict(c) -> dict:
-    return {"kernel": {_lib.AH_KERNEL_SITE: "site", _lib.AH_KERNEL_TILE: "tile"}.get(c.kernel, "auto"),
+    return {"kernel": {_lib.AH_KERNEL_SITE: "site", _lib.AH_KERNEL_TILE: "tile",
+                       _lib.AH_KERNEL_TILE2: "tile2"}.get(c.kernel, "auto"),
             "tile": (c.tile_x, c.tile_y), "zchunk": c.zchunk}
 
 
@@ -303,9 +307,11 @@ def tune_lookup(p: Params):
     return _cfg_dict(c)
 
 
-def tune_set(p: Params, tile, zchunk: int = 0):
+def tune_set(p: Params, tile, zchunk: int = 0, kernel: str = "tile"):
+    """Record a tiling by hand; kernel "tile" (one step per pass) or "tile2" (two)."""
     lib = _lib.load()
-    c = _lib.ah_step_config(_lib.AH_KERNEL_TILE, tile[0], tile[1], zchunk)
+    k = {"tile": _lib.AH_KERNEL_TILE, "tile2": _lib.AH_KERNEL_TILE2}[kernel]
+    c = _lib.ah_step_config(k, tile[0], tile[1], zchunk)
     _lib.check(lib.ah_tune_set(ctypes.byref(p.to_c()), ctypes.byref(c)), what="ah_tune_set")
 
 
@@ -401,6 +407,13 @@ class Pool:
         ids = (ctypes.c_int64 * cap)()
         n = ctypes.c_int32()
         self._call(self._lib.ah_pool_poll, ids, cap, ctypes.byref(n), what="ah_pool_poll")
+        return [ids[k] for k in range(n.value)]
+
+    def poll_async(self, cap: int = 4096):
+        """Finished lattices the newest counter copy on the host shows (no wait)."""
+        ids = (ctypes.c_int64 * cap)()
+        n = ctypes.c_int32()
+        self._call(self._lib.ah_pool_poll_async, ids, cap, ctypes.byref(n), what="ah_pool_poll_async")
         return [ids[k] for k in range(n.value)]
 
     def step_config(self, rid: int) -> dict:

@@ -49,6 +49,7 @@ class ah_measurement(ctypes.Structure):
 AH_KERNEL_AUTO = 0
 AH_KERNEL_SITE = 1
 AH_KERNEL_TILE = 2
+AH_KERNEL_TILE2 = 3
 
 
 class ah_step_config(ctypes.Structure):
@@ -123,6 +124,7 @@ def load():
         "ah_pool_submit": ([vp, P(ah_params), ctypes.c_uint64, i64, ctypes.c_int32, P(i64)], ctypes.c_int),
         "ah_pool_advance": ([vp, ctypes.c_int32], ctypes.c_int),
         "ah_pool_poll": ([vp, P(i64), ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
+        "ah_pool_poll_async": ([vp, P(i64), ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
         "ah_pool_progress": ([vp, i64, P(i64), P(i64)], ctypes.c_int),
         "ah_pool_step_config": ([vp, i64, P(ah_step_config)], ctypes.c_int),
         "ah_pool_get_state": ([vp, i64, P(ctypes.c_double), P(i64)], ctypes.c_int),

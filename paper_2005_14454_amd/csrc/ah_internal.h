@@ -105,6 +105,14 @@ inline bool tile_supported(int precision, int tx, int ty)
     return false;
 }
 
+// Tile shapes of the two-step pass (its LDS holds two regions of links per
+// workgroup, so the FP64 shapes are the smaller ones).
+inline bool tile2_supported(int precision, int tx, int ty)
+{
+    if ((tx == 32 && ty == 8) || (tx == 64 && ty == 4)) return true;
+    return tx == 64 && ty == 8 && precision == AH_FP32;
+}
+
 // Smallest z-chunk the tiled kernels accept for a lattice of side N.  Short
 // chunks pay for themselves only on small lattices, which they give enough
 // workgroups (64^3 FP32 on MI355X: 2-plane chunks step in 11.4 us, 8-plane
@@ -176,6 +184,12 @@ template <typename R>
 hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2, const LatticeConst& L,
                             const StepCoef& c, const TileConfig& tc, const MeasConst* mc, double* partials,
                             bool write, hipStream_t s);
+
+// Two steps in one pass: snapshot n of `in` to snapshot n+2 of `out` (all
+// ten fields in other buffers), with the coefficients of steps n and n+1.
+template <typename R>
+hipError_t launch_step2_tile(const Fields<R>& in, const Fields<R>& out, const LatticeConst& L, const StepCoef& c0,
+                             const StepCoef& c1, const TileConfig& tc, hipStream_t s);
 
 // workgroups (= diagnostics records) of one tiled launch
 int step_tile_blocks(int N, const TileConfig& tc);

@@ -10,6 +10,14 @@
 //     precision and tile shape) -> advance counters
 // and every kernel reads the lattice's own counter, so the same graph serves
 // every step until the set of lattices changes.
+//
+// The host never drains the stream in the serving path: uploads (coefficient
+// tables, descriptors, work lists) go through a pinned staging ring and are
+// ordered on the pool stream after the replays already queued; each advance
+// queues a copy of the step counters into pinned memory behind an event, and
+// ah_pool_poll_async reads the newest copy that has landed; series downloads
+// run on a side stream.  At most kMaxInflight replays are queued ahead of the
+// host, so a request admitted now joins within that many steps.
 #include "ah.h"
 #include "ah_internal.h"
 
@@ -19,6 +27,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <new>
 #include <string>
@@ -41,9 +50,14 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+constexpr int64_t kMaxInflight = 8;  // graph replays queued ahead of the host
+constexpr int kSnapshots = 16;       // counter copies in flight (> kMaxInflight)
+constexpr size_t kStageBytes = 32u << 20;
+
 struct Slot {
     bool used = false;
     int64_t id = -1;
+    int64_t seq = 0;  // admission order: counter copies issued before it do not describe it
     ah_params p{};
     int64_t nsteps = 0;
     int measure_every = 0;
@@ -84,10 +98,38 @@ Footprint footprint(const ah_params& p, const ah_step_config& cfg, int64_t nstep
 
 }  // namespace
 
+struct StageChunk {
+    size_t off, len;
+    hipEvent_t ev;
+};
+struct Snapshot {
+    int64_t* h = nullptr;    // pinned copy of the counters
+    hipEvent_t ev = nullptr;
+    int64_t launches = 0;    // replays queued before the copy
+    int64_t seq = 0;         // admissions made before the copy
+};
+struct Retired {
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+    void* buf;
+    hipEvent_t ev;  // recorded after the last work that could use them
+};
+
 struct ah_pool {
     int device = 0;
     hipStream_t stream = nullptr;
     bool owns_stream = false;
+    hipStream_t side = nullptr;  // series downloads of finished lattices
+    char* stage = nullptr;       // pinned staging ring for uploads
+    size_t stage_head = 0;
+    std::deque<StageChunk> stage_busy;
+    std::vector<hipEvent_t> free_events;
+    std::vector<Snapshot> snaps;
+    std::deque<int> snap_order;           // issued, not yet read, oldest first
+    std::vector<int64_t> host_counters;   // newest counters read back
+    int64_t launches_done = 0;            // replays known to have finished
+    int64_t seq = 0;                      // admissions so far
+    std::vector<Retired> retired;
     void* arena = nullptr;
     size_t budget = 0;
     std::vector<std::pair<size_t, size_t>> free_list;  // (offset, size), sorted by offset
@@ -95,7 +137,6 @@ struct ah_pool {
     int64_t next_id = 1;
     PoolLattice* d_lat = nullptr;
     int64_t* d_counters = nullptr;
-    int64_t* h_counters = nullptr;  // pinned
     WorkItem* d_work = nullptr;
     size_t work_cap = 0;
     hipGraph_t graph = nullptr;
@@ -167,11 +208,142 @@ size_t largest_free(const ah_pool* P)
     return m;
 }
 
-// Rebuild descriptors, work lists and the per-step graph.
+hipError_t take_event(ah_pool* P, hipEvent_t* ev)
+{
+    if (!P->free_events.empty()) {
+        *ev = P->free_events.back();
+        P->free_events.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreateWithFlags(ev, hipEventDisableTiming);
+}
+
+// Release staging chunks whose copies have run (wait = also the oldest one).
+hipError_t stage_reclaim(ah_pool* P, bool wait)
+{
+    while (!P->stage_busy.empty()) {
+        StageChunk& c = P->stage_busy.front();
+        hipError_t e = wait ? hipEventSynchronize(c.ev) : hipEventQuery(c.ev);
+        if (e == hipErrorNotReady) return hipSuccess;
+        if (e != hipSuccess) return e;
+        P->free_events.push_back(c.ev);
+        P->stage_busy.pop_front();
+        wait = false;
+    }
+    return hipSuccess;
+}
+
+// Upload n bytes from host memory to device memory dst on the pool stream,
+// through the staging ring (waiting only for staging space, which earlier
+// copies free as they run).  Copies larger than half the ring go directly
+// and wait for the stream.
+hipError_t stage_upload(ah_pool* P, void* dst, const void* src, size_t n)
+{
+    if (n == 0) return hipSuccess;
+    hipError_t e;
+    if (n > kStageBytes / 2) {
+        e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, P->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+        return e;
+    }
+    const size_t len = align_up(n);
+    if (P->stage_head + len > kStageBytes) P->stage_head = 0;
+    const size_t lo = P->stage_head, hi = lo + len;
+    for (;;) {
+        bool overlap = false;
+        for (const StageChunk& c : P->stage_busy)
+            if (c.off < hi && lo < c.off + c.len) overlap = true;
+        if (!overlap) break;
+        e = stage_reclaim(P, true);
+        if (e != hipSuccess) return e;
+    }
+    std::memcpy(P->stage + lo, src, n);
+    e = hipMemcpyAsync(dst, P->stage + lo, n, hipMemcpyHostToDevice, P->stream);
+    hipEvent_t ev = nullptr;
+    if (e == hipSuccess) e = take_event(P, &ev);
+    if (e == hipSuccess) e = hipEventRecord(ev, P->stream);
+    if (e != hipSuccess) return e;
+    P->stage_busy.push_back({lo, len, ev});
+    P->stage_head = hi;
+    return hipSuccess;
+}
+
+// Read the counter copies that have landed (wait = block for the oldest
+// one); the newest becomes the host's view of every lattice admitted before it.
+hipError_t read_snapshots(ah_pool* P, bool wait)
+{
+    while (!P->snap_order.empty()) {
+        Snapshot& sn = P->snaps[P->snap_order.front()];
+        hipError_t e = wait ? hipEventSynchronize(sn.ev) : hipEventQuery(sn.ev);
+        if (e == hipErrorNotReady) break;
+        if (e != hipSuccess) return e;
+        for (size_t i = 0; i < P->slots.size(); ++i)
+            if (P->slots[i].used && P->slots[i].seq <= sn.seq) {
+                P->host_counters[2 * i] = sn.h[2 * i];
+                P->host_counters[2 * i + 1] = sn.h[2 * i + 1];
+            }
+        P->launches_done = std::max(P->launches_done, sn.launches);
+        P->snap_order.pop_front();
+        wait = false;
+    }
+    // retired graphs and buffers whose last user has run
+    for (size_t k = 0; k < P->retired.size();) {
+        Retired& r = P->retired[k];
+        const hipError_t q = hipEventQuery(r.ev);
+        if (q == hipSuccess) {
+            if (r.exec) (void)hipGraphExecDestroy(r.exec);
+            if (r.graph) (void)hipGraphDestroy(r.graph);
+            if (r.buf) (void)hipFree(r.buf);
+            P->free_events.push_back(r.ev);
+            P->retired.erase(P->retired.begin() + k);
+        } else {
+            ++k;
+        }
+    }
+    return hipSuccess;
+}
+
+// Queue a copy of the counters behind the replays queued so far.
+hipError_t queue_snapshot(ah_pool* P)
+{
+    if ((int)P->snap_order.size() >= kSnapshots) {
+        hipError_t e = read_snapshots(P, true);
+        if (e != hipSuccess) return e;
+    }
+    int j = 0;
+    for (; j < kSnapshots; ++j) {
+        bool busy = false;
+        for (int k : P->snap_order) busy |= (k == j);
+        if (!busy) break;
+    }
+    Snapshot& sn = P->snaps[j];
+    hipError_t e = hipMemcpyAsync(sn.h, P->d_counters, 2 * P->slots.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                  P->stream);
+    if (e == hipSuccess) e = hipEventRecord(sn.ev, P->stream);
+    if (e != hipSuccess) return e;
+    sn.launches = P->graph_launches;
+    sn.seq = P->seq;
+    P->snap_order.push_back(j);
+    return hipSuccess;
+}
+
+// Keep a graph (or a buffer) until the work queued so far has run.
+hipError_t retire(ah_pool* P, hipGraphExec_t exec, hipGraph_t graph, void* buf)
+{
+    hipEvent_t ev = nullptr;
+    hipError_t e = take_event(P, &ev);
+    if (e == hipSuccess) e = hipEventRecord(ev, P->stream);
+    if (e != hipSuccess) return e;
+    P->retired.push_back({exec, graph, buf, ev});
+    return hipSuccess;
+}
+
+// Rebuild descriptors, work lists and the per-step graph.  Nothing here
+// waits for the stream: the uploads are ordered after the replays already
+// queued, which keep reading the old descriptors until then.
 int rebuild(ah_pool* P)
 {
-    hipError_t e = hipStreamSynchronize(P->stream);
-    if (e != hipSuccess) return phip(P, e, "pool rebuild sync");
+    hipError_t e;
     const int nslot = (int)P->slots.size();
     std::vector<PoolLattice> desc(nslot);
     for (int i = 0; i < nslot; ++i) {
@@ -239,7 +411,11 @@ int rebuild(ah_pool* P)
         if (len) step_groups.push_back(g);
     }
     if (work.size() > P->work_cap) {
-        if (P->d_work) (void)hipFree(P->d_work);
+        // the queued replays may still read the old list: it is freed once they have run
+        if (P->d_work) {
+            e = retire(P, nullptr, nullptr, P->d_work);
+            if (e != hipSuccess) return phip(P, e, "pool work list retire");
+        }
         P->d_work = nullptr;
         size_t cap = std::max<size_t>(work.size() * 2, 4096);
         e = hipMalloc(&P->d_work, cap * sizeof(WorkItem));
@@ -249,13 +425,14 @@ int rebuild(ah_pool* P)
         }
         P->work_cap = cap;
     }
-    e = hipMemcpy(P->d_lat, desc.data(), nslot * sizeof(PoolLattice), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !work.empty())
-        e = hipMemcpy(P->d_work, work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    e = stage_upload(P, P->d_lat, desc.data(), nslot * sizeof(PoolLattice));
+    if (e == hipSuccess && !work.empty()) e = stage_upload(P, P->d_work, work.data(), work.size() * sizeof(WorkItem));
     if (e != hipSuccess) return phip(P, e, "pool descriptor upload");
 
-    if (P->exec) (void)hipGraphExecDestroy(P->exec);
-    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->exec || P->graph) {
+        e = retire(P, P->exec, P->graph, nullptr);
+        if (e != hipSuccess) return phip(P, e, "pool graph retire");
+    }
     P->exec = nullptr;
     P->graph = nullptr;
     e = hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed);
@@ -329,18 +506,20 @@ int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_po
         P->slots.resize(max_slots);
         e = hipMalloc(&P->d_lat, max_slots * sizeof(PoolLattice));
         if (e == hipSuccess) e = hipMalloc(&P->d_counters, 2 * max_slots * sizeof(int64_t));
-        if (e == hipSuccess) e = hipHostMalloc((void**)&P->h_counters, 2 * max_slots * sizeof(int64_t), hipHostMallocDefault);
         if (e == hipSuccess) e = hipMemset(P->d_counters, 0, 2 * max_slots * sizeof(int64_t));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&P->stage, kStageBytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking);
+        P->snaps.resize(kSnapshots);
+        for (int j = 0; j < kSnapshots && e == hipSuccess; ++j) {
+            e = hipHostMalloc((void**)&P->snaps[j].h, 2 * max_slots * sizeof(int64_t), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&P->snaps[j].ev, hipEventDisableTiming);
+        }
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            if (P->d_lat) (void)hipFree(P->d_lat);
-            if (P->d_counters) (void)hipFree(P->d_counters);
-            if (P->h_counters) (void)hipHostFree(P->h_counters);
-            (void)hipFree(P->arena);
-            if (P->owns_stream) (void)hipStreamDestroy(P->stream);
-            delete P;
+            (void)ah_pool_destroy(P);
             return AH_E_NOMEM;
         }
+        P->host_counters.assign(2 * (size_t)max_slots, 0);
         *out = P;
         return AH_OK;
     });
@@ -357,6 +536,7 @@ static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why
 {
     ah_step_config t{AH_KERNEL_TILE, 0, 0, 0};
     (void)tuned_config(p, &t);
+    t.kernel = AH_KERNEL_TILE;  // the pool steps one step per replay; a two-step entry lends its tile
     const int rc = resolve_step_config(p, t, cfg, why);
     if (rc != AH_OK) return rc;
     // one tile shape serves both nodes, so it must be one whose measured march
@@ -419,6 +599,9 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         s = Slot{};
         s.used = true;
         s.id = P->next_id++;
+        s.seq = ++P->seq;
+        P->host_counters[2 * slot] = 0;
+        P->host_counters[2 * slot + 1] = 0;
         s.p = *p;
         s.nsteps = nsteps;
         s.measure_every = measure_every;
@@ -460,9 +643,10 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         d.deta = p->deta;
         d.sigma2 = p->sigma * p->sigma;
 
-        // enqueue on the pool stream (after any graph replays already queued),
-        // then wait so that the host staging vector can go
-        hipError_t e = hipMemcpyAsync(coef, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice, P->stream);
+        // enqueued on the pool stream after the graph replays already queued
+        // (the slot's previous lattice, if any, has finished, so they leave
+        // its memory and counter alone); nothing waits for them
+        hipError_t e = stage_upload(P, coef, rows.data(), rows.size() * sizeof(double));
         if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 2 * sizeof(int64_t), P->stream);
         if (e == hipSuccess) {
             Fields<double> f64;
@@ -479,7 +663,6 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
                 e = launch_init<float>(f32, p->N, p->sigma, seed, P->stream);
             }
         }
-        if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
         if (e != hipSuccess) {
             arena_free(P, s.off, s.bytes);
             s = Slot{};
@@ -500,13 +683,50 @@ int ah_pool_advance(ah_pool* P, int32_t nsteps)
             int rc = rebuild(P);
             if (rc != AH_OK) return rc;
         }
+        hipError_t e = hipSuccess;
         for (int32_t k = 0; k < nsteps; ++k) {
-            hipError_t e = hipGraphLaunch(P->exec, P->stream);
+            // keep at most kMaxInflight replays queued ahead of the host: wait
+            // for the counter copy queued after an earlier replay (one is
+            // queued every kMaxInflight / 2 replays, so the wait leaves at
+            // least that many queued)
+            while (e == hipSuccess && P->graph_launches - P->launches_done >= kMaxInflight) {
+                if (P->snap_order.empty()) e = queue_snapshot(P);
+                if (e == hipSuccess) e = read_snapshots(P, true);
+            }
+            if (e == hipSuccess) e = hipGraphLaunch(P->exec, P->stream);
             if (e != hipSuccess) return phip(P, e, "ah_pool_advance graph launch");
             ++P->graph_launches;
+            if (k + 1 < nsteps && P->graph_launches % (kMaxInflight / 2) == 0) {
+                e = queue_snapshot(P);
+                if (e != hipSuccess) return phip(P, e, "ah_pool_advance counter copy");
+            }
+        }
+        if (nsteps > 0) {
+            e = queue_snapshot(P);
+            if (e == hipSuccess) e = stage_reclaim(P, false);
+            if (e != hipSuccess) return phip(P, e, "ah_pool_advance counter copy");
         }
         return AH_OK;
     });
+}
+
+// Ids of lattices the host view shows finished and not yet reported.
+static int report_done(ah_pool* P, int64_t* done_ids, int32_t cap, int32_t* n)
+{
+    int32_t k = 0;
+    for (size_t i = 0; i < P->slots.size(); ++i) {
+        Slot& s = P->slots[i];
+        if (!s.used || s.reported) continue;
+        if (P->host_counters[2 * i] == s.nsteps + 1) {
+            if (k < cap) {
+                done_ids[k] = s.id;
+                s.reported = true;
+            }
+            ++k;
+        }
+    }
+    *n = k < cap ? k : cap;
+    return AH_OK;
 }
 
 int ah_pool_poll(ah_pool* P, int64_t* done_ids, int32_t cap, int32_t* n)
@@ -514,24 +734,22 @@ int ah_pool_poll(ah_pool* P, int64_t* done_ids, int32_t cap, int32_t* n)
     return no_throw([&]() -> int {
         if (!P || !n || (cap > 0 && !done_ids)) return pfail(P, AH_E_INVAL, "ah_pool_poll: bad argument");
         Guard g(P->device);
-        const size_t bytes = 2 * P->slots.size() * sizeof(int64_t);
-        hipError_t e = hipMemcpyAsync(P->h_counters, P->d_counters, bytes, hipMemcpyDeviceToHost, P->stream);
+        hipError_t e = queue_snapshot(P);
         if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+        if (e == hipSuccess) e = read_snapshots(P, true);
         if (e != hipSuccess) return phip(P, e, "ah_pool_poll");
-        int32_t k = 0;
-        for (size_t i = 0; i < P->slots.size(); ++i) {
-            Slot& s = P->slots[i];
-            if (!s.used || s.reported) continue;
-            if (P->h_counters[2 * i] == s.nsteps + 1) {
-                if (k < cap) {
-                    done_ids[k] = s.id;
-                    s.reported = true;
-                }
-                ++k;
-            }
-        }
-        *n = k < cap ? k : cap;
-        return AH_OK;
+        return report_done(P, done_ids, cap, n);
+    });
+}
+
+int ah_pool_poll_async(ah_pool* P, int64_t* done_ids, int32_t cap, int32_t* n)
+{
+    return no_throw([&]() -> int {
+        if (!P || !n || (cap > 0 && !done_ids)) return pfail(P, AH_E_INVAL, "ah_pool_poll_async: bad argument");
+        Guard g(P->device);
+        hipError_t e = read_snapshots(P, false);
+        if (e != hipSuccess) return phip(P, e, "ah_pool_poll_async");
+        return report_done(P, done_ids, cap, n);
     });
 }
 
@@ -613,15 +831,22 @@ int ah_pool_results(ah_pool* P, int64_t id, ah_measurement* series, int32_t cap,
         Slot* s = find_slot(P, id, &i);
         if (!s) return pfail(P, AH_E_INVAL, "ah_pool_results: unknown id");
         Guard g(P->device);
-        int64_t c[2];
-        hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
-        if (e != hipSuccess) return phip(P, e, "ah_pool_results");
-        if (c[0] != s->nsteps + 1) return pfail(P, AH_E_AGAIN, "ah_pool_results: the lattice has not finished");
+        hipError_t e;
+        int64_t c[2] = {P->host_counters[2 * i], P->host_counters[2 * i + 1]};
+        if (c[0] != s->nsteps + 1) {
+            // not seen finished yet: read the counters after the queued work
+            e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+            if (e != hipSuccess) return phip(P, e, "ah_pool_results");
+            if (c[0] != s->nsteps + 1) return pfail(P, AH_E_AGAIN, "ah_pool_results: the lattice has not finished");
+        }
+        // a finished lattice is no longer written, so its series is read on
+        // the side stream while the pool stream runs on
         const int64_t nm = std::min(c[1], s->d.series_cap);
         std::vector<double> raw((size_t)nm * kSeriesStride);
         if (nm > 0) {
-            e = hipMemcpy(raw.data(), s->d.series, raw.size() * sizeof(double), hipMemcpyDeviceToHost);
+            e = hipMemcpyAsync(raw.data(), s->d.series, raw.size() * sizeof(double), hipMemcpyDeviceToHost, P->side);
+            if (e == hipSuccess) e = hipStreamSynchronize(P->side);
             if (e != hipSuccess) return phip(P, e, "ah_pool_results copy");
         }
         const int64_t V = (int64_t)s->p.N * s->p.N * s->p.N;
@@ -661,6 +886,7 @@ int ah_pool_synchronize(ah_pool* P)
         if (!P) return AH_E_INVAL;
         Guard g(P->device);
         hipError_t e = hipStreamSynchronize(P->stream);
+        if (e == hipSuccess) e = read_snapshots(P, true);
         if (e != hipSuccess) return phip(P, e, "ah_pool_synchronize");
         return AH_OK;
     });
@@ -672,13 +898,27 @@ int ah_pool_destroy(ah_pool* P)
 {
     if (!P) return AH_E_INVAL;
     Guard g(P->device);
-    (void)hipStreamSynchronize(P->stream);
+    if (P->stream) (void)hipStreamSynchronize(P->stream);
+    if (P->side) (void)hipStreamSynchronize(P->side);
+    for (Retired& r : P->retired) {
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        if (r.graph) (void)hipGraphDestroy(r.graph);
+        if (r.buf) (void)hipFree(r.buf);
+        (void)hipEventDestroy(r.ev);
+    }
+    for (StageChunk& c : P->stage_busy) (void)hipEventDestroy(c.ev);
+    for (hipEvent_t ev : P->free_events) (void)hipEventDestroy(ev);
+    for (Snapshot& sn : P->snaps) {
+        if (sn.h) (void)hipHostFree(sn.h);
+        if (sn.ev) (void)hipEventDestroy(sn.ev);
+    }
+    if (P->stage) (void)hipHostFree(P->stage);
+    if (P->side) (void)hipStreamDestroy(P->side);
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->d_work) (void)hipFree(P->d_work);
     if (P->d_lat) (void)hipFree(P->d_lat);
     if (P->d_counters) (void)hipFree(P->d_counters);
-    if (P->h_counters) (void)hipHostFree(P->h_counters);
     if (P->arena) (void)hipFree(P->arena);
     if (P->owns_stream) (void)hipStreamDestroy(P->stream);
     delete P;

@@ -24,9 +24,13 @@ struct ah_handle {
     size_t arena_bytes = 0;
     int64_t V = 0;
     size_t real_bytes = 8;
-    // ping-pong phi/A buffers [2][5] (phr, phi, a0, a1, a2), then pir, pii, e0, e1, e2
+    // ping-pong phi/A buffers [2][5] (phr, phi, a0, a1, a2) and Pi/E buffers
+    // [2][5] (pir, pii, e0, e1, e2).  A single step drifts phi and A into the
+    // other buffer and kicks Pi and E in place; a two-step pass writes all
+    // ten fields into the other buffers.
     void* pp[2][5] = {};
-    void* mom[5] = {};
+    void* mom[2][5] = {};
+    int curm = 0;  // current Pi/E buffer
     double* partials = nullptr;
     double* result = nullptr;
     double* series = nullptr;       // kSeriesCap folded records (ah_step_measured)
@@ -41,6 +45,7 @@ struct ah_handle {
     ah_step_config cfg{AH_KERNEL_AUTO, 0, 0, 0};
     int64_t measured_launches = 0;  // timed launches that also formed diagnostics
     std::vector<char> ev_measured;  // per event pair: 1 if that launch formed diagnostics
+    std::vector<char> ev_steps;     // per event pair: steps the launch advanced (1 or 2)
     std::string err;
 };
 
@@ -198,7 +203,7 @@ constexpr int kSeriesCap = 1024;  // device measurement records per ah_step_meas
 
 size_t required_bytes(const ah_params& p)
 {
-    return 15 * field_bytes(p) + align_up(partial_records(p) * kMeasStride * sizeof(double)) +
+    return 20 * field_bytes(p) + align_up(partial_records(p) * kMeasStride * sizeof(double)) +
            align_up(kMeasStride * sizeof(double)) + align_up((size_t)kSeriesCap * kMeasStride * sizeof(double));
 }
 
@@ -211,11 +216,11 @@ Fields<R> fields_of(const ah_handle* h, int buf)
     f.a0 = (R*)h->pp[buf][2];
     f.a1 = (R*)h->pp[buf][3];
     f.a2 = (R*)h->pp[buf][4];
-    f.pir = (R*)h->mom[0];
-    f.pii = (R*)h->mom[1];
-    f.e0 = (R*)h->mom[2];
-    f.e1 = (R*)h->mom[3];
-    f.e2 = (R*)h->mom[4];
+    f.pir = (R*)h->mom[h->curm][0];
+    f.pii = (R*)h->mom[h->curm][1];
+    f.e0 = (R*)h->mom[h->curm][2];
+    f.e1 = (R*)h->mom[h->curm][3];
+    f.e2 = (R*)h->mom[h->curm][4];
     return f;
 }
 
@@ -236,12 +241,12 @@ void* comp_ptr(ah_handle* h, int c)
     switch (c) {
     case 0: return h->pp[h->cur][0];
     case 1: return h->pp[h->cur][1];
-    case 2: return h->mom[0];
-    case 3: return h->mom[1];
+    case 2: return h->mom[h->curm][0];
+    case 3: return h->mom[h->curm][1];
     case 4: return h->pp[h->cur][2];
     case 5: return h->pp[h->cur][3];
     case 6: return h->pp[h->cur][4];
-    default: return h->mom[c - 5];
+    default: return h->mom[h->curm][c - 5];
     }
 }
 
@@ -268,7 +273,7 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
 {
     ah_step_config c = in;
     if (c.kernel == AH_KERNEL_AUTO) c.kernel = p.gauge_action == AH_COMPACT ? AH_KERNEL_TILE : AH_KERNEL_SITE;
-    if (c.kernel != AH_KERNEL_SITE && c.kernel != AH_KERNEL_TILE) {
+    if (c.kernel != AH_KERNEL_SITE && c.kernel != AH_KERNEL_TILE && c.kernel != AH_KERNEL_TILE2) {
         *why = "unknown kernel";
         return AH_E_INVAL;
     }
@@ -284,11 +289,13 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
     if (c.tile_x == 0 && c.tile_y == 0) {
         // FP32: 128-wide rows halve the x-halo line fetches per site.  FP64:
         // 32 x 8, as fast as 64 x 8 for the plain step, and its measured
-        // march, unlike that of 512-thread tiles, does not spill
-        c.tile_x = p.precision == AH_FP32 ? (p.N >= 128 ? 128 : 64) : 32;
+        // march, unlike that of 512-thread tiles, does not spill.  Two-step
+        // passes: 32 x 8 in both precisions
+        c.tile_x = c.kernel == AH_KERNEL_TILE2 ? 32 : (p.precision == AH_FP32 ? (p.N >= 128 ? 128 : 64) : 32);
         c.tile_y = 8;
     }
-    if (!tile_supported(p.precision, c.tile_x, c.tile_y)) {
+    if (c.kernel == AH_KERNEL_TILE2 ? !tile2_supported(p.precision, c.tile_x, c.tile_y)
+                                    : !tile_supported(p.precision, c.tile_x, c.tile_y)) {
         *why = "unsupported tile shape";
         return AH_E_INVAL;
     }
@@ -301,7 +308,7 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
         // one resident round (256) of 1024-thread workgroups, whose z-chunks
         // are then as long as possible
         const int64_t per_chunk = (int64_t)((p.N + c.tile_x - 1) / c.tile_x) * ((p.N + c.tile_y - 1) / c.tile_y);
-        const int64_t target = c.tile_x * c.tile_y >= 1024 ? 256 : 1024;
+        const int64_t target = (c.kernel == AH_KERNEL_TILE && c.tile_x * c.tile_y >= 1024) ? 256 : 1024;
         int64_t zc = (int64_t)p.N * per_chunk / target;
         if (zc < 8) zc = 8;
         if (zc > p.N) zc = p.N;
@@ -397,7 +404,7 @@ TileConfig meas_tiles(const ah_handle* h)
 {
     ah_step_config d;
     std::string why;
-    if (h->cfg.kernel == AH_KERNEL_TILE) {
+    if (h->cfg.kernel == AH_KERNEL_TILE || h->cfg.kernel == AH_KERNEL_TILE2) {
         int tx = h->cfg.tile_x, ty = h->cfg.tile_y;
         if (!measured_tile(h->p.precision, &tx, &ty)) return TileConfig{tx, ty, h->cfg.zchunk};
         (void)resolve_step_config(h->p, ah_step_config{AH_KERNEL_TILE, tx, ty, 0}, &d, &why);
@@ -447,6 +454,7 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
         h->ev_used += 2;
         h->measured_launches += 1;
         h->ev_measured.push_back(1);
+        h->ev_steps.push_back(1);
     }
     e = launch_measure_final(h->partials, nb + gauss_blocks(p.N), dst, h->stream);
     if (e != hipSuccess) return e;
@@ -457,26 +465,45 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
     return hipSuccess;
 }
 
+// Brackets a step launch with an event pair while timing is on.
+struct TimedLaunch {
+    ah_handle* h;
+    int steps;
+    hipError_t begin()
+    {
+        if (!h->timing) return hipSuccess;
+        if (h->ev_used + 2 > h->ev.size()) {
+            for (int k = 0; k < 2; ++k) {
+                hipEvent_t ev;
+                const hipError_t e = hipEventCreate(&ev);
+                if (e != hipSuccess) return e;
+                h->ev.push_back(ev);
+            }
+        }
+        return hipEventRecord(h->ev[h->ev_used], h->stream);
+    }
+    hipError_t end()
+    {
+        if (!h->timing) return hipSuccess;
+        const hipError_t e = hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+        if (e != hipSuccess) return e;
+        h->ev_used += 2;
+        h->ev_measured.push_back(0);
+        h->ev_steps.push_back((char)steps);
+        return hipSuccess;
+    }
+};
+
 template <typename R>
 hipError_t do_step(ah_handle* h)
 {
     const Fields<R> in = fields_of<R>(h, h->cur);
     const Fields<R> out = fields_of<R>(h, h->cur ^ 1);
     const StepCoef c = coef_at(h->p, h->step);
-    hipError_t e;
-    if (h->timing) {
-        if (h->ev_used + 2 > h->ev.size()) {
-            for (int k = 0; k < 2; ++k) {
-                hipEvent_t ev;
-                e = hipEventCreate(&ev);
-                if (e != hipSuccess) return e;
-                h->ev.push_back(ev);
-            }
-        }
-        e = hipEventRecord(h->ev[h->ev_used], h->stream);
-        if (e != hipSuccess) return e;
-    }
-    if (h->cfg.kernel == AH_KERNEL_TILE) {
+    TimedLaunch t{h, 1};
+    hipError_t e = t.begin();
+    if (e != hipSuccess) return e;
+    if (h->cfg.kernel == AH_KERNEL_TILE || h->cfg.kernel == AH_KERNEL_TILE2) {
         const TileConfig tc{h->cfg.tile_x, h->cfg.tile_y, h->cfg.zchunk};
         e = launch_step_tile<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, tc, nullptr, nullptr,
                                 true, h->stream);
@@ -484,14 +511,57 @@ hipError_t do_step(ah_handle* h)
         e = launch_step<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, h->stream);
     }
     if (e != hipSuccess) return e;
-    if (h->timing) {
-        e = hipEventRecord(h->ev[h->ev_used + 1], h->stream);
-        if (e != hipSuccess) return e;
-        h->ev_used += 2;
-        h->ev_measured.push_back(0);
-    }
+    e = t.end();
+    if (e != hipSuccess) return e;
     h->cur ^= 1;
     h->step += 1;
+    return hipSuccess;
+}
+
+// Two steps in one pass (kernel AH_KERNEL_TILE2): reads snapshot n from the
+// current buffers and writes snapshot n+2 into the other phi/A and Pi/E ones.
+template <typename R>
+hipError_t do_step2(ah_handle* h)
+{
+    Fields<R> in = fields_of<R>(h, h->cur);
+    Fields<R> out = fields_of<R>(h, h->cur ^ 1);
+    const int om = h->curm ^ 1;
+    out.pir = (R*)h->mom[om][0];
+    out.pii = (R*)h->mom[om][1];
+    out.e0 = (R*)h->mom[om][2];
+    out.e1 = (R*)h->mom[om][3];
+    out.e2 = (R*)h->mom[om][4];
+    const StepCoef c0 = coef_at(h->p, h->step), c1 = coef_at(h->p, h->step + 1);
+    const TileConfig tc{h->cfg.tile_x, h->cfg.tile_y, h->cfg.zchunk};
+    TimedLaunch t{h, 2};
+    hipError_t e = t.begin();
+    if (e != hipSuccess) return e;
+    e = launch_step2_tile<R>(in, out, lconst(h->p), c0, c1, tc, h->stream);
+    if (e != hipSuccess) return e;
+    e = t.end();
+    if (e != hipSuccess) return e;
+    h->cur ^= 1;
+    h->curm ^= 1;
+    h->step += 2;
+    return hipSuccess;
+}
+
+// nsteps plain steps: two-step passes while at least two remain when the
+// handle's kernel is AH_KERNEL_TILE2, single steps otherwise.
+hipError_t plain_steps(ah_handle* h, int64_t nsteps)
+{
+    const bool two = h->cfg.kernel == AH_KERNEL_TILE2;
+    while (nsteps > 0) {
+        hipError_t e;
+        if (two && nsteps >= 2) {
+            e = h->p.precision == AH_FP64 ? do_step2<double>(h) : do_step2<float>(h);
+            nsteps -= 2;
+        } else {
+            e = h->p.precision == AH_FP64 ? do_step<double>(h) : do_step<float>(h);
+            nsteps -= 1;
+        }
+        if (e != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
@@ -592,10 +662,11 @@ int ah_create(const ah_params* p, void* dev_arena, size_t arena_bytes, void* hip
                 h->pp[b][c] = base;
                 base += fb;
             }
-        for (int c = 0; c < 5; ++c) {
-            h->mom[c] = base;
-            base += fb;
-        }
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 5; ++c) {
+                h->mom[b][c] = base;
+                base += fb;
+            }
         h->partials = (double*)base;
         base += align_up(partial_records(*p) * kMeasStride * sizeof(double));
         h->result = (double*)base;
@@ -652,6 +723,7 @@ int ah_init(ah_handle* h, uint64_t seed)
         if (!h) return AH_E_INVAL;
         DeviceGuard g(h->device);
         h->cur = 0;
+        h->curm = 0;
         h->step = 0;
         hipError_t e = h->p.precision == AH_FP64
                            ? launch_init<double>(fields_of<double>(h, 0), h->p.N, h->p.sigma, seed, h->stream)
@@ -670,6 +742,7 @@ int ah_set_state(ah_handle* h, const double* host_soa, int64_t step)
         hipError_t e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "ah_set_state sync");
         h->cur = 0;
+        h->curm = 0;
         const size_t V = (size_t)h->V;
         std::vector<float> tmp;
         if (h->real_bytes == 4) tmp.resize(V);
@@ -811,10 +884,8 @@ int ah_step(ah_handle* h, int64_t nsteps)
         if (!h || nsteps < 0) return fail(h, AH_E_INVAL, "ah_step: bad argument");
         if (!h->ready) return fail(h, AH_E_STATE, "ah_step before ah_init/ah_set_state");
         DeviceGuard g(h->device);
-        for (int64_t k = 0; k < nsteps; ++k) {
-            hipError_t e = h->p.precision == AH_FP64 ? do_step<double>(h) : do_step<float>(h);
-            if (e != hipSuccess) return hip_fail(h, e, "ah_step launch");
-        }
+        const hipError_t e = plain_steps(h, nsteps);
+        if (e != hipSuccess) return hip_fail(h, e, "ah_step launch");
         return AH_OK;
     });
 }
@@ -846,7 +917,8 @@ int ah_step_measured(ah_handle* h, int64_t nsteps, int32_t measure_every, ah_mea
             steps.clear();
             return hipSuccess;
         };
-        for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t end = h->step + nsteps;
+        while (h->step < end) {
             hipError_t e;
             if (h->step % measure_every == 0) {
                 if ((int)steps.size() == kSeriesCap) {
@@ -857,7 +929,9 @@ int ah_step_measured(ah_handle* h, int64_t nsteps, int32_t measure_every, ah_mea
                 double* dst = h->series + (steps.size() - 1) * kMeasStride;
                 e = h->p.precision == AH_FP64 ? measured_pass<double>(h, dst, true) : measured_pass<float>(h, dst, true);
             } else {
-                e = h->p.precision == AH_FP64 ? do_step<double>(h) : do_step<float>(h);
+                // the plain steps up to the next due snapshot (or the end)
+                const int64_t next = (h->step / measure_every + 1) * measure_every;
+                e = plain_steps(h, (next < end ? next : end) - h->step);
             }
             if (e != hipSuccess) return hip_fail(h, e, "ah_step_measured launch");
         }
@@ -961,6 +1035,7 @@ int ah_set_timing(ah_handle* h, int enable)
         h->ev_used = 0;
         h->measured_launches = 0;
         h->ev_measured.clear();
+        h->ev_steps.clear();
         return AH_OK;
     });
 }
@@ -979,8 +1054,10 @@ int ah_get_timing(ah_handle* h, double* total_ms, int64_t* launches)
             if (e != hipSuccess) return hip_fail(h, e, "ah_get_timing elapsed");
             tot += ms;
         }
+        int64_t steps = 0;
+        for (size_t k = 0; k < h->ev_used / 2; ++k) steps += h->ev_steps[k];
         *total_ms = tot;
-        *launches = (int64_t)(h->ev_used / 2);
+        *launches = steps;
         return AH_OK;
     });
 }

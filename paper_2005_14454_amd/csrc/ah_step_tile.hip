@@ -24,102 +24,13 @@
 // bitwise reproducible across launch configurations.
 #include "ah_device.h"
 #include "ah_internal.h"
-
-#define AH_SINCOS_QUAL __device__
-#include "ah_sincos.h"
+#include "ah_stencil.h"
 
 #pragma clang fp contract(off)
 
 namespace ah {
 namespace {
 
-__device__ inline float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ inline double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// Streaming accesses: Pi and E are read and written once per step at their
-// own site, phi and A are written once into the other ping-pong buffer; none
-// of it is reused from cache within a step, so they bypass it and leave L2 to
-// the phi / A halo lines that neighbouring tiles read again.
-template <typename R>
-__device__ inline R ld_stream(const R* p)
-{
-    return __builtin_nontemporal_load(p);
-}
-template <typename R>
-__device__ inline void st_stream(R* p, R v)
-{
-    __builtin_nontemporal_store(v, p);
-}
-
-template <typename R>
-struct Cx {
-    R r, i;
-};
-template <typename R>
-__device__ inline Cx<R> cmul(Cx<R> a, Cx<R> b)
-{
-    return {fm(a.r, b.r, -(a.i * b.i)), fm(a.r, b.i, a.i * b.r)};
-}
-template <typename R>
-__device__ inline Cx<R> cmulc(Cx<R> a, Cx<R> b)  // conj(a) * b
-{
-    return {fm(a.r, b.r, a.i * b.i), fm(a.r, b.i, -(a.i * b.r))};
-}
-
-// FP64 links: the reduced-range sincos (accurate to ~2 ulp for |x| <= 1e9),
-// the library routine beyond that (out of line: a link phase past 1e9 is a
-// lattice long blown up, and inlined it would cost the march registers)
-__device__ __noinline__ double2 sincos_far(double x)
-{
-    double2 v;
-    sincos(x, &v.x, &v.y);
-    return v;
-}
-__device__ inline void sincos_t(double x, double* s, double* c)
-{
-    if (fabs(x) <= 1e9) {
-        sincos_reduced(x, s, c);
-    } else {
-        const double2 v = sincos_far(x);
-        *s = v.x;
-        *c = v.y;
-    }
-}
-__device__ inline void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
-
-// link U = exp(-i dx A) = (cos(dx A), -sin(dx A))
-template <typename R>
-__device__ inline Cx<R> link(R dx, R a)
-{
-    R s, c;
-    sincos_t(dx * a, &s, &c);
-    return {c, -s};
-}
-
-// -Im(p conj(q)) with p = U_i^x U_j^{x+i}, q = U_i^{x+j} U_j^x: sin(Theta_ij)
-template <typename R>
-__device__ inline R plaq_sin(Cx<R> ui_x, Cx<R> uj_xi, Cx<R> ui_xj, Cx<R> uj_x)
-{
-    const Cx<R> p = cmul(ui_x, uj_xi);
-    const Cx<R> q = cmul(ui_xj, uj_x);
-    return fm(p.r, q.i, -(p.i * q.r));
-}
-
-__device__ inline int wrapi(int v, int N)
-{
-    // v in [-1, 2N + TX]: periodic image in [0, N)
-    if (v < 0) return v + N;
-    return v < N ? v : v % N;
-}
-
-// Place tiles so that the blocks the hardware sends to one XCD (block b goes
-// to XCD b % 8) cover a contiguous range of tile indices.
-__device__ inline int xcd_tile(int b, int nb)
-{
-    const int per = nb / kXcdCount, rem = nb % kXcdCount;
-    const int xcd = b % kXcdCount, k = b / kXcdCount;
-    return xcd * per + (xcd < rem ? xcd : rem) + k;
-}
 
 template <typename R, int TX, int TY>
 struct TileGeom {
@@ -231,7 +142,8 @@ __device__ __attribute__((noinline)) float link_phase_near_cut(Cx<float> ph, Cx<
 // Link phase of an FP32 lattice from z = conj(ph) (U pn), formed in FP32 from
 // the link the step itself uses; its angle, taken in FP32, is within
 //   |dx A| 2^-22 (rounding of dx A, in the link's phase)
-//   + 1e-5        (sincosf, the two complex products, atan2_fast)
+//   + 1e-5        (the link's sine and cosine, within 3e-7; the two complex
+//                  products; atan2_fast)
 // of the FP64 value, so unless it lies that close to the cut at +-pi it is on
 // the same side of it.  Near the cut, where |z| leaves the range in which
 // FP32 keeps its relative precision (or is not finite), and where |dx A|
@@ -327,6 +239,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     const bool active = gx < N && gy < N;
     const int gxw = wrapi(gx, N), gyw = wrapi(gy, N);
     const int64_t own_xy = (int64_t)gxw + (int64_t)N * gyw;
+    const uint32_t ob = (uint32_t)own_xy;  // 32-bit in-plane offset (N^2 < 2^32)
     const int ro = (ly + 1) * RW + (lx + 1);  // own region slot
 
     // halo ring site of this thread (if any)
@@ -350,6 +263,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         rh = hry * RW + hrx;
         halo_xy = (int64_t)wrapi(x0 - 1 + hrx, N) + (int64_t)N * wrapi(y0 - 1 + hry, N);
     }
+    const uint32_t hb = (uint32_t)halo_xy;
     // halo sites whose link phases the windings of the tile read
     const bool halo_top = has_halo && hry == TY + 1 && hrx >= 1 && hrx <= TX;    // Y_x, Y_z
     const bool halo_right = has_halo && hrx == TX + 1 && hry >= 1 && hry <= TY;  // Y_y, Y_z
@@ -396,25 +310,25 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         const R* A[3] = {f.a0, f.a1, f.a2};
         Cx<R> um[3];
         for (int d = 0; d < 3; ++d) {
-            um[d] = link(dx, A[d][pm + own_xy]);
+            um[d] = link(dx, at(A[d], pm, ob));
             sU[1][d][ro] = um[d];
-            Ac[d] = A[d][p0 + own_xy];
+            Ac[d] = at(A[d], p0, ob);
             Uc[d] = link(dx, Ac[d]);
             sU[0][d][ro] = Uc[d];
         }
         if (has_halo)
             for (int d = 0; d < 3; ++d) {
-                sU[1][d][rh] = link(dx, A[d][pm + halo_xy]);
-                const R ah = A[d][p0 + halo_xy];
+                sU[1][d][rh] = link(dx, at(A[d], pm, hb));
+                const R ah = at(A[d], p0, hb);
                 sU[0][d][rh] = link(dx, ah);
                 if constexpr (MEAS) mx->A[0][d][rh] = ah;
             }
         if constexpr (MEAS)
             for (int d = 0; d < 3; ++d) mx->A[0][d][ro] = Ac[d];
-        phi_m = {f.phr[pm + own_xy], f.phi[pm + own_xy]};
-        phi_c = {f.phr[p0 + own_xy], f.phi[p0 + own_xy]};
+        phi_m = {at(f.phr, pm, ob), at(f.phi, pm, ob)};
+        phi_c = {at(f.phr, p0, ob), at(f.phi, p0, ob)};
         sPhi[ro] = phi_c;
-        if (has_halo) sPhi[rh] = Cx<R>{f.phr[p0 + halo_xy], f.phi[p0 + halo_xy]};
+        if (has_halo) sPhi[rh] = Cx<R>{at(f.phr, p0, hb), at(f.phi, p0, hb)};
         uz_m = um[2];
         __syncthreads();
         // F_xz, F_yz of the own column at plane z0-1
@@ -424,25 +338,25 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         // U(z0+1) into slot 1
         const int64_t p1 = plane_of(z0 + 1);
         for (int d = 0; d < 3; ++d) {
-            Ap[d] = A[d][p1 + own_xy];
+            Ap[d] = at(A[d], p1, ob);
             Up[d] = link(dx, Ap[d]);
             sU[1][d][ro] = Up[d];
         }
         if (has_halo)
             for (int d = 0; d < 3; ++d) {
-                const R ah = A[d][p1 + halo_xy];
+                const R ah = at(A[d], p1, hb);
                 sU[1][d][rh] = link(dx, ah);
                 if constexpr (MEAS) mx->A[1][d][rh] = ah;
             }
         if constexpr (MEAS)
             for (int d = 0; d < 3; ++d) mx->A[1][d][ro] = Ap[d];
-        phi_p = {f.phr[p1 + own_xy], f.phi[p1 + own_xy]};
+        phi_p = {at(f.phr, p1, ob), at(f.phi, p1, ob)};
         __syncthreads();
     }
 
-    const int64_t pz0 = (int64_t)z0 * NN + own_xy;
-    R pr_c = ld_stream(f.pir + pz0), pi_c = ld_stream(f.pii + pz0);
-    R e_c[3] = {ld_stream(f.e0 + pz0), ld_stream(f.e1 + pz0), ld_stream(f.e2 + pz0)};
+    const int64_t pz0 = (int64_t)z0 * NN;
+    R pr_c = ld_stream(f.pir + pz0 + ob), pi_c = ld_stream(f.pii + pz0 + ob);
+    R e_c[3] = {ld_stream(f.e0 + pz0 + ob), ld_stream(f.e1 + pz0 + ob), ld_stream(f.e2 + pz0 + ob)};
 
     // Operands prefetched for iteration t: A of plane t+2 (own and halo), phi
     // of plane t+1 (halo) and t+2 (own), Pi and E of plane t+1 (own).  The
@@ -462,21 +376,21 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     };
     auto prefetch = [&](int t, Pre& q) {
         const int64_t p2 = plane_of(t + 2), p1 = plane_of(t + 1);
-        q.a[0] = f.a0[p2 + own_xy];
-        q.a[1] = f.a1[p2 + own_xy];
-        q.a[2] = f.a2[p2 + own_xy];
+        q.a[0] = at(f.a0, p2, ob);
+        q.a[1] = at(f.a1, p2, ob);
+        q.a[2] = at(f.a2, p2, ob);
         if (has_halo) {
-            q.ha[0] = f.a0[p2 + halo_xy];
-            q.ha[1] = f.a1[p2 + halo_xy];
-            q.ha[2] = f.a2[p2 + halo_xy];
-            q.hphi = {f.phr[p1 + halo_xy], f.phi[p1 + halo_xy]};
+            q.ha[0] = at(f.a0, p2, hb);
+            q.ha[1] = at(f.a1, p2, hb);
+            q.ha[2] = at(f.a2, p2, hb);
+            q.hphi = {at(f.phr, p1, hb), at(f.phi, p1, hb)};
         }
-        q.phi2 = {f.phr[p2 + own_xy], f.phi[p2 + own_xy]};
-        q.pr = ld_stream(f.pir + p1 + own_xy);
-        q.pi = ld_stream(f.pii + p1 + own_xy);
-        q.e[0] = ld_stream(f.e0 + p1 + own_xy);
-        q.e[1] = ld_stream(f.e1 + p1 + own_xy);
-        q.e[2] = ld_stream(f.e2 + p1 + own_xy);
+        q.phi2 = {at(f.phr, p2, ob), at(f.phi, p2, ob)};
+        q.pr = ld_stream(f.pir + p1 + ob);
+        q.pi = ld_stream(f.pii + p1 + ob);
+        q.e[0] = ld_stream(f.e0 + p1 + ob);
+        q.e[1] = ld_stream(f.e1 + p1 + ob);
+        q.e[2] = ld_stream(f.e2 + p1 + ob);
     };
     Pre q1, q2;
     if constexpr (D2) prefetch(z0, q1);
@@ -500,7 +414,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             // halo link phases of this plane), so it is loaded here
             if (has_halo) {
                 const int64_t p1 = plane_of(z + 1);
-                hphi = Cx<R>{f.phr[p1 + halo_xy], f.phi[p1 + halo_xy]};
+                hphi = Cx<R>{at(f.phr, p1, hb), at(f.phi, p1, hb)};
             }
         }
         const Cx<R> rphi = phi_p;
@@ -598,17 +512,17 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             const R ne1 = fm(cE1, e_c[1], cE2 * fm(kappa, jy, -cy));
             const R ne2 = fm(cE1, e_c[2], cE2 * fm(kappa, jz, -cz));
             if (write && active) {
-                const int64_t o = (int64_t)z * NN + own_xy;
-                st_stream(f.pir + o, npr);
-                st_stream(f.pii + o, npi);
-                st_stream(f.e0 + o, ne0);
-                st_stream(f.e1 + o, ne1);
-                st_stream(f.e2 + o, ne2);
-                st_stream(ophr + o, fm(deta, npr, phi_c.r));
-                st_stream(ophi + o, fm(deta, npi, phi_c.i));
-                st_stream(oa0 + o, fm(deta, ne0, Ac[0]));
-                st_stream(oa1 + o, fm(deta, ne1, Ac[1]));
-                st_stream(oa2 + o, fm(deta, ne2, Ac[2]));
+                const int64_t o = (int64_t)z * NN;  // plane offset (uniform); + ob: the site
+                st_stream(f.pir + o + ob, npr);
+                st_stream(f.pii + o + ob, npi);
+                st_stream(f.e0 + o + ob, ne0);
+                st_stream(f.e1 + o + ob, ne1);
+                st_stream(f.e2 + o + ob, ne2);
+                st_stream(ophr + o + ob, fm(deta, npr, phi_c.r));
+                st_stream(ophi + o + ob, fm(deta, npi, phi_c.i));
+                st_stream(oa0 + o + ob, fm(deta, ne0, Ac[0]));
+                st_stream(oa1 + o + ob, fm(deta, ne1, Ac[1]));
+                st_stream(oa2 + o + ob, fm(deta, ne2, Ac[2]));
             }
             if constexpr (MEAS) {
                 if (active) {

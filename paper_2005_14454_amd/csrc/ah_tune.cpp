@@ -1,7 +1,8 @@
-// Autotuner of libah: picks the tile shape and z-chunk of the tiled step for
-// a (precision, N) by timing candidates on a scratch lattice, and keeps the
-// choices in a process-wide table that can be saved to and loaded from a
-// small JSON file (one entry per line).
+// Autotuner of libah: picks the kernel (one step per pass, or two), the tile
+// shape and the z-chunk of the tiled step for a (precision, N) by timing
+// candidates on a scratch lattice, and keeps the choices in a process-wide
+// table that can be saved to and loaded from a small JSON file (one entry
+// per line).
 #include "ah.h"
 #include "ah_internal.h"
 
@@ -10,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -29,8 +31,10 @@ namespace ah {
 // that is automatic (0) or at least the minimum.
 static bool valid_entry(int precision, int N, const ah_step_config& c)
 {
-    return (precision == AH_FP32 || precision == AH_FP64) && N >= 4 && c.kernel == AH_KERNEL_TILE &&
-           tile_supported(precision, c.tile_x, c.tile_y) && c.zchunk >= 0 &&
+    const bool shape = c.kernel == AH_KERNEL_TILE    ? tile_supported(precision, c.tile_x, c.tile_y)
+                       : c.kernel == AH_KERNEL_TILE2 ? tile2_supported(precision, c.tile_x, c.tile_y)
+                                                     : false;
+    return (precision == AH_FP32 || precision == AH_FP64) && N >= 4 && shape && c.zchunk >= 0 &&
            (c.zchunk == 0 || c.zchunk >= min_zchunk(N));
 }
 
@@ -58,20 +62,25 @@ int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double*
         int rc = ah_create(p, nullptr, 0, nullptr, &h);
         if (rc != AH_OK) return rc;
         rc = ah_init(h, 0);
-        std::vector<std::pair<int, int>> tiles = {{64, 8}, {64, 4}, {32, 8}, {128, 4}};
+        // (kernel, tile x, tile y): single steps on every tile shape, two-step
+        // passes on theirs (timed per step)
+        std::vector<std::tuple<int, int, int>> shapes = {{AH_KERNEL_TILE, 64, 8}, {AH_KERNEL_TILE, 64, 4},
+                                                         {AH_KERNEL_TILE, 32, 8}, {AH_KERNEL_TILE, 128, 4},
+                                                         {AH_KERNEL_TILE2, 32, 8}, {AH_KERNEL_TILE2, 64, 4}};
         if (p->precision == AH_FP32) {
-            tiles.push_back({64, 16});
-            tiles.push_back({128, 8});
+            shapes.push_back({AH_KERNEL_TILE, 64, 16});
+            shapes.push_back({AH_KERNEL_TILE, 128, 8});
+            shapes.push_back({AH_KERNEL_TILE2, 64, 8});
         }
         std::vector<int> zcs = {0, p->N};
         for (int div : {2, 4, 8, 16, 32})
             if (p->N / div >= ah::min_zchunk(p->N)) zcs.push_back(p->N / div);
         ah_step_config bcfg{};
         double bms = 1e300;
-        for (auto& t : tiles) {
+        for (auto& t : shapes) {
             for (int zc : zcs) {
                 if (rc != AH_OK) break;
-                ah_step_config c{AH_KERNEL_TILE, t.first, t.second, zc};
+                ah_step_config c{std::get<0>(t), std::get<1>(t), std::get<2>(t), zc};
                 if (ah_set_step_config(h, &c) != AH_OK) continue;
                 rc = ah_step(h, 2);
                 if (rc == AH_OK) rc = ah_set_timing(h, 1);
@@ -136,9 +145,12 @@ int ah_tune_save(const char* path)
         std::fprintf(f, "{\"version\": 1, \"entries\": [\n");
         size_t i = 0;
         for (auto& kv : g_table) {
-            std::fprintf(f, "{\"precision\": \"%s\", \"N\": %d, \"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, \"ms\": %.6g}%s\n",
+            std::fprintf(f,
+                         "{\"precision\": \"%s\", \"N\": %d, \"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, "
+                         "\"ms\": %.6g, \"kernel\": \"%s\"}%s\n",
                          kv.first.first == AH_FP64 ? "fp64" : "fp32", kv.first.second, kv.second.cfg.tile_x,
-                         kv.second.cfg.tile_y, kv.second.cfg.zchunk, kv.second.ms, ++i < g_table.size() ? "," : "");
+                         kv.second.cfg.tile_y, kv.second.cfg.zchunk, kv.second.ms,
+                         kv.second.cfg.kernel == AH_KERNEL_TILE2 ? "tile2" : "tile", ++i < g_table.size() ? "," : "");
         }
         std::fprintf(f, "]}\n");
         std::fclose(f);
@@ -168,7 +180,9 @@ int ah_tune_load(const char* path)
                 continue;
             }
             const int pr = std::strcmp(prec, "fp64") == 0 ? AH_FP64 : (std::strcmp(prec, "fp32") == 0 ? AH_FP32 : -1);
-            const ah_step_config c{AH_KERNEL_TILE, tx, ty, zc};
+            // an entry without a kernel field is a single-step one
+            const int kern = std::strstr(line, "\"kernel\": \"tile2\"") ? AH_KERNEL_TILE2 : AH_KERNEL_TILE;
+            const ah_step_config c{kern, tx, ty, zc};
             if (!ah::valid_entry(pr, N, c)) {
                 bad = true;
                 continue;

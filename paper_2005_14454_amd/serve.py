@@ -8,6 +8,11 @@ per step (continuous batching: requests that arrive while others run join
 the next replay).  A request completes when its last diagnostics record is
 on the host; time-to-completion (TTC) runs from arrival to that moment.
 
+The loop never waits for the GPU to drain: each advance queues one replay
+(the pool keeps up to eight queued, waiting only for older ones), finished
+requests are found from counter copies that land behind the replays, and
+admissions and series downloads are queued or run beside them.
+
 `python -m paper_2005_14454_amd.serve --requests 500` runs the full stream;
 the function `run_stream` is what bench.py calls.
 """
@@ -69,7 +74,7 @@ def make_stream(n: int, rate: float, seed: int = 5, nmin: int = 64, nmax: int = 
     return reqs
 
 
-def saturated_throughput(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 2) -> float:
+def saturated_throughput(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 1) -> float:
     """Site-updates/s the pool sustains on this request mix when every
     request is there from the start (the serving capacity the arrival rate
     is set against).  The requests are copied; their records stay empty."""
@@ -78,7 +83,7 @@ def saturated_throughput(reqs, hbm_budget: int, max_slots: int = 256, chunk: int
     return run_stream(burst, hbm_budget, max_slots, chunk)["throughput_su_per_s"]
 
 
-def run_stream(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 2, log=None):
+def run_stream(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 1, log=None):
     """Serve the requests; returns a summary dict and fills the Request records."""
     pool = Pool(hbm_budget, max_slots)
     future = deque(sorted(reqs, key=lambda r: r.arrival))
@@ -106,7 +111,7 @@ def run_stream(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 2, log=
             waiting = still
             if by_pool:
                 pool.advance(chunk)
-                for pid in pool.poll():
+                for pid in pool.poll_async():
                     r = by_pool.pop(pid)
                     r.series = pool.results(pid)
                     r.done = time.perf_counter() - t0

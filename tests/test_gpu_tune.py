@@ -1,13 +1,15 @@
-"""The autotuner: it times the tiled step's tile shapes and z-chunks for a
-(precision, N), records the fastest, and lattices created afterwards with
-automatic configuration use it.  Every tile shape computes the same fields
-bit for bit, so a tuned lattice evolves exactly as an untuned one."""
+"""The autotuner: it times the tiled step's tile shapes and z-chunks, with one
+and with two steps per pass, for a (precision, N), records the fastest per
+step, and lattices created afterwards with automatic configuration use it.
+Every tile shape and kernel computes the same fields bit for bit, so a
+tuned lattice evolves exactly as an untuned one."""
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 SHAPES = {(64, 8), (64, 4), (32, 8), (128, 4), (64, 16), (128, 8)}
+SHAPES2 = {(32, 8), (64, 4), (64, 8)}  # two steps per pass
 
 
 @pytest.fixture
@@ -22,15 +24,16 @@ def ah():
 def test_autotune_records_and_is_used(ah, precision):
     p = ah.Params(N=48, precision=precision)
     best = ah.autotune(p, steps=2)
-    assert best["kernel"] == "tile" and best["ms"] > 0
-    assert tuple(best["tile"]) in SHAPES
+    assert best["kernel"] in ("tile", "tile2") and best["ms"] > 0
+    assert tuple(best["tile"]) in (SHAPES if best["kernel"] == "tile" else SHAPES2)
     if precision == "fp64":
         assert tuple(best["tile"]) not in {(64, 16), (128, 8)}
+        assert best["kernel"] == "tile" or tuple(best["tile"]) != (64, 8)
     assert 2 <= best["zchunk"] <= 48
     assert ah.tune_lookup(p)["tile"] == best["tile"]
     with ah.Lattice(p) as lat:
         cfg = lat.get_step_config()
-        assert (cfg["kernel"], cfg["tile"], cfg["zchunk"]) == ("tile", best["tile"], best["zchunk"])
+        assert (cfg["kernel"], cfg["tile"], cfg["zchunk"]) == (best["kernel"], best["tile"], best["zchunk"])
         lat.init(3)
         lat.step(4)
         tuned = lat.get_state()

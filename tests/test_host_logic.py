@@ -129,6 +129,17 @@ def test_tuning_table_roundtrip_and_validation(ah, tmp_path):
             with pytest.raises(ah.AHError):
                 ah.tune_set(*bad)
         assert ah.tune_lookup(p64)["tile"] == (32, 8)
+        # two steps per pass: its own shapes (FP64 without 64 x 8), kept through save and load
+        ah.tune_set(p32, (64, 8), 0, kernel="tile2")
+        assert ah.tune_lookup(p32) == {"kernel": "tile2", "tile": (64, 8), "zchunk": 0}
+        with pytest.raises(ah.AHError):
+            ah.tune_set(p64, (64, 8), 0, kernel="tile2")
+        with pytest.raises(ah.AHError):
+            ah.tune_set(p32, (128, 8), 0, kernel="tile2")
+        ah.tune_save(str(path))
+        ah.tune_clear()
+        ah.tune_load(str(path))
+        assert ah.tune_lookup(p32)["kernel"] == "tile2" and ah.tune_lookup(p64)["kernel"] == "tile"
         badfile = tmp_path / "bad.json"
         badfile.write_text('{"version": 1, "entries": [\n'
                            '{"precision": "fp32", "N": 64, "tile_x": 64, "tile_y": 8, "zchunk": 0, "ms": 1},\n'
