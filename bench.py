@@ -26,27 +26,44 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_512cubed_hbm_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2005_14454_amd", "csrc", "ah_step_tile.hip")
 
 
-def measured_traffic(precision, N, tile):
+STEP_SOURCES = {"tile": ("ah_step_tile.hip", "ah_stencil.h"), "tile2": ("ah_step2.hip", "ah_stencil.h")}
+
+
+def kernel_source_hash(kernel):
+    """sha256[:16] of the sources of the plain step kernel `kernel` ("tile": one
+    step per pass, "tile2": two), as the committed profiles record it."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in STEP_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2005_14454_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def step_kernel_name(precision, cfg):
+    real = "float" if precision == "fp32" else "double"
+    tx, ty = cfg["tile"]
+    if cfg["kernel"] == "tile2":
+        return f"k_step2_tile<{real}, {tx}, {ty}>"
+    return f"k_step_tile<{real}, {tx}, {ty}, false>"
+
+
+def measured_traffic(precision, N, cfg):
     """HBM bytes per plain-step launch at 512^3 from the committed rocprofv3
     PMC summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None
-    when the kernel source has changed since the counters were taken."""
-    import hashlib
+    when the kernel's sources have changed since the counters were taken."""
     if N != 512 or not os.path.exists(TRAFFIC_PROFILE):
         return None
     text = open(TRAFFIC_PROFILE).read()
-    cur = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
-    if f"sha256[:16] = {cur}" not in text:
+    if f"{cfg['kernel']} sources sha256[:16] = {kernel_source_hash(cfg['kernel'])}" not in text:
         return None
-    real = "float" if precision == "fp32" else "double"
-    name = f"k_step_tile<{real}, {tile[0]}, {tile[1]}, false>"
+    name = step_kernel_name(precision, cfg)
     # one row per launch geometry; the autotuner's candidates have few
     # dispatches, the benchmark's own configuration the most
     best = None
     for line in text.splitlines():
-        if line.startswith(name):
+        if line.startswith(name + " "):
             cols = line[len(name):].split()
             n, total_gb = int(cols[6]), float(cols[4])
             if best is None or n > best[0]:
@@ -74,11 +91,11 @@ def tiling(ah, p):
     return got
 
 
-def run_gpu(precision, N, steps, warmup, measure_every, seed):
+def run_gpu(precision, N, steps, warmup, measure_every, seed, m=1.0):
     import torch
     import paper_2005_14454_amd as ah
 
-    p = ah.Params(N=N, precision=precision, m=1.0)
+    p = ah.Params(N=N, precision=precision, m=m)
     tuned = tiling(ah, p)  # tile shape and z-chunk for this (precision, N)
     lat = ah.Lattice(p)
     cfg = lat.get_step_config()
@@ -101,19 +118,26 @@ def run_gpu(precision, N, steps, warmup, measure_every, seed):
     torch.cuda.empty_cache()
     sec = t1 - t0
     V = N ** 3
-    # the plain step kernel (launches that did not also form diagnostics)
+    # the plain step kernel (launches that did not also form diagnostics):
+    # the timing counts steps, so this is its time per step; a two-step
+    # launch covers two steps and moves the algorithmic bytes of two
+    per_launch = 2 if cfg["kernel"] == "tile2" else 1
     avg_kernel_s = (kern_ms - meas_ms) / 1e3 / max(launches - meas_launches, 1)
     avg_measured_s = meas_ms / 1e3 / max(meas_launches, 1)
-    achieved = BYTES_PER_SITE[precision] * V / avg_kernel_s / 1e9
+    algo = BYTES_PER_SITE[precision] * V * per_launch
+    launch_s = avg_kernel_s * per_launch
+    achieved = algo / launch_s / 1e9
     return {
         "value": V * steps / sec,
         "tuned": tuned,
+        "step_kernel": {"kernel": cfg["kernel"], "tile": list(cfg["tile"]), "zchunk": cfg["zchunk"],
+                        "steps_per_launch": per_launch, "launch_ms": 1e3 * launch_s},
         "ms_per_step": 1e3 * sec / steps,
         "kernel_ms": 1e3 * avg_kernel_s,
         "measured_step_ms": 1e3 * avg_measured_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(precision, N, cfg["tile"]),
-                     "traffic_unit": "bytes per launch", "algorithmic_bytes": BYTES_PER_SITE[precision] * V},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(precision, N, cfg),
+                     "traffic_unit": "bytes per launch", "algorithmic_bytes": algo},
         "last_measurement": {k: last[k] for k in ("step", "winding_sum_abs", "xi_W", "xi_L", "v2_phi", "v2_omega",
                                                   "energy", "gauss_rel", "nonfinite")},
     }
@@ -192,11 +216,16 @@ def batched_ensemble(sizes=(64, 96, 128, 192, 256), nlat=64, rng_seed=4, measure
         t0 = time.perf_counter()
         left = set(ids)
         steps = 1
-        while left:
-            pool.advance(chunk)
-            steps += chunk
-            for rid in pool.poll():
+        need = max(n for _, _, n in reqs) + 1  # replays until the longest lattice has finished
+        while steps < need:
+            k = min(chunk, need - steps)
+            pool.advance(k)
+            steps += k
+            for rid in pool.poll_async():
                 left.discard(rid)
+        for rid in pool.poll():  # waits for the last replays
+            left.discard(rid)
+        assert not left
         t1 = time.perf_counter()
         finals = [pool.results(rid)[-1] for rid in ids]
     # the same lattices one after another through the single-lattice path,
@@ -336,6 +365,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=40)
+    ap.add_argument("--no-config1", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the lattice path runs on one GPU (asked for --gpus {args.gpus}); "
@@ -353,6 +383,12 @@ def main():
         fp64 = run_gpu("fp64", args.N, args.steps, args.warmup, args.measure_every, seed)
         print(f"# fp64: {fp64['value']:.4e} su/s, {fp64['ms_per_step']:.3f} ms/step, kernel "
               f"{fp64['kernel_ms']:.3f} ms", file=sys.stderr, flush=True)
+    # the small single-lattice workload: 64^3 FP64 from the random-phase start
+    # of seed 0, 160 steps, diagnostics every 10 steps (snapshots 0 .. 150)
+    config1 = None if args.no_config1 else run_gpu("fp64", 64, 160, 0, 10, 0)
+    if config1:
+        print(f"# 64^3 fp64: {config1['value']:.4e} su/s, {config1['ms_per_step'] * 1e3:.1f} us/step, "
+              f"kernel {config1['kernel_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     batched = None if args.no_batched else batched_ensemble()
     if batched:
         print(f"# batched: {batched['value']:.4e} su/s over {batched['lattices']} lattices, "
@@ -400,7 +436,16 @@ def main():
         "batched_small": batched_small,
         "served": serv,
         "fp64": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
-                                           "roofline": fp64["roofline"], "dtype": "f64", "tuned": fp64["tuned"]},
+                                           "roofline": fp64["roofline"], "dtype": "f64", "tuned": fp64["tuned"],
+                                           "step_kernel": fp64["step_kernel"]},
+        "config1_64cubed_fp64": None if config1 is None else {
+            "workload": "single 64^3 periodic lattice, FP64, radiation era m=1, s=0, seed 0, 160 steps from the "
+                        "initial condition, diagnostics every 10 steps",
+            "value": config1["value"], "unit": "site-updates/s", "ms_per_step": config1["ms_per_step"],
+            "roofline": config1["roofline"], "measured_step_ms": config1["measured_step_ms"],
+            "step_kernel": config1["step_kernel"], "tuned": config1["tuned"],
+            "last_measurement": config1["last_measurement"]},
+        "step_kernel": fp32["step_kernel"],
         "tuned": fp32["tuned"],
         "kernel_ms": {"fp32": fp32["kernel_ms"], "fp64": None if fp64 is None else fp64["kernel_ms"]},
         "measured_step_ms": {"fp32": fp32["measured_step_ms"],
