@@ -306,11 +306,12 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
     if (c.zchunk == 0) {
         // enough workgroups to cover the chip: about 1024 of 512 threads, or
         // one resident round (256) of 1024-thread workgroups, whose z-chunks
-        // are then as long as possible
+        // are then as long as possible; small lattices go down to the
+        // shortest chunk they allow
         const int64_t per_chunk = (int64_t)((p.N + c.tile_x - 1) / c.tile_x) * ((p.N + c.tile_y - 1) / c.tile_y);
         const int64_t target = (c.kernel == AH_KERNEL_TILE && c.tile_x * c.tile_y >= 1024) ? 256 : 1024;
         int64_t zc = (int64_t)p.N * per_chunk / target;
-        if (zc < 8) zc = 8;
+        if (zc < min_zchunk(p.N)) zc = min_zchunk(p.N);
         if (zc > p.N) zc = p.N;
         c.zchunk = (int32_t)zc;
     }

@@ -980,10 +980,12 @@ hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int n
     return hipErrorInvalidValue;
 }
 
+// One site per thread up to 1024 workgroups of 256 (a grid-stride loop
+// beyond): small lattices get their Gauss pass in one short wave of blocks.
 int gauss_blocks(int N)
 {
     const int64_t V = (int64_t)N * N * N;
-    int64_t nb = (V + 2047) / 2048;
+    int64_t nb = (V + 255) / 256;
     if (nb > 1024) nb = 1024;
     return (int)(nb < 1 ? 1 : nb);
 }

@@ -49,7 +49,7 @@ def test_tuned_automatic_zchunk_is_resolved(ah):
     ah.tune_set(p, (64, 4), 0)
     with ah.Lattice(p) as lat:
         cfg = lat.get_step_config()
-        assert cfg["tile"] == (64, 4) and 8 <= cfg["zchunk"] <= 40
+        assert cfg["tile"] == (64, 4) and 2 <= cfg["zchunk"] <= 40
         lat.init(5)
         lat.step(3)
         m = lat.measure()
