@@ -49,9 +49,21 @@ struct StepCoef {
     double kappa;      // 2 e0^2 f
 };
 
+// Stored layout of every field of a lattice: site (x, y, z) at element
+// x + P (y + N z), with the row pitch P >= N a whole number of 128-byte cache
+// lines.  Every row then starts on a line, and a tile's rows are read as
+// whole lines whatever N is; the P - N elements that end a row are never
+// read or written.
+inline int row_pitch(int N, int precision)
+{
+    const int per_line = precision == AH_FP64 ? 16 : 32;
+    return (N + per_line - 1) / per_line * per_line;
+}
+
 // Lattice-wide constants.
 struct LatticeConst {
     int N;
+    int P;  // row pitch (row_pitch(N, precision))
     int compact;
     double dx, deta, sigma2;
 };
@@ -149,7 +161,7 @@ struct PoolLattice {
     int64_t series_cap;
     int N, tiles_x, tiles_y, zchunk;     // step tiling
     int meas_zchunk, meas_blocks, measure_every, precision;
-    int gauss_blocks, pad1;  // Gauss records follow the meas_blocks step records
+    int gauss_blocks, P;     // Gauss records follow the meas_blocks step records; P: row pitch
     int compact, pad0;
     double dx, deta, sigma2;
 };
@@ -169,9 +181,14 @@ constexpr size_t kScratchBytes = (size_t)kGatherMax * sizeof(int64_t) + (size_t)
 // call for that device, with it current).
 hipError_t scratch_ptr(int device, void** out);
 
+// Copies between a dense host array of N^3 values (x fastest) and a stored
+// field of row pitch P, element size rb, enqueued on s (ah_runtime.cpp).
+hipError_t field_upload(void* dev, const void* host, int N, int P, size_t rb, hipStream_t s);
+hipError_t field_download(void* host, const void* dev, int N, int P, size_t rb, hipStream_t s);
+
 // ---- launchers (ah_kernels.hip, ah_step_tile.hip) -------------------------
 template <typename R>
-hipError_t launch_init(const Fields<R>& f, int N, double sigma, uint64_t seed, hipStream_t s);
+hipError_t launch_init(const Fields<R>& f, int N, int P, double sigma, uint64_t seed, hipStream_t s);
 
 template <typename R>
 hipError_t launch_step(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2,
@@ -216,7 +233,7 @@ hipError_t launch_fold_batch(const PoolLattice* lat, int nlat, hipStream_t s);
 hipError_t launch_advance_batch(const PoolLattice* lat, int nlat, hipStream_t s);
 
 template <typename R>
-hipError_t launch_gather(const Fields<R>& f, const int64_t* sites, int64_t count, int64_t V, R* out, hipStream_t s);
+hipError_t launch_gather(const Fields<R>& f, const int64_t* sites, int64_t count, int N, int P, R* out, hipStream_t s);
 
 template <typename R>
 hipError_t launch_winding(const Fields<R>& f, const LatticeConst& L, int8_t* w, hipStream_t s);

@@ -82,8 +82,8 @@ Footprint footprint(const ah_params& p, const ah_step_config& cfg, int64_t nstep
         f.total = SIZE_MAX;
         return f;
     }
-    const size_t V = (size_t)p.N * p.N * p.N;
-    f.field = align_up(V * (p.precision == AH_FP64 ? 8 : 4));
+    const size_t stored = (size_t)p.N * p.N * row_pitch(p.N, p.precision);
+    f.field = align_up(stored * (p.precision == AH_FP64 ? 8 : 4));
     f.fields = 15 * f.field;
     f.meas_zc = cfg.zchunk;
     f.meas_blocks = step_tile_blocks(p.N, TileConfig{cfg.tile_x, cfg.tile_y, cfg.zchunk});
@@ -630,6 +630,7 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         d.nsteps = nsteps;
         d.series_cap = fp.series_cap;
         d.N = p->N;
+        d.P = row_pitch(p->N, p->precision);
         d.tiles_x = (p->N + cfg.tile_x - 1) / cfg.tile_x;
         d.tiles_y = (p->N + cfg.tile_y - 1) / cfg.tile_y;
         d.zchunk = cfg.zchunk;
@@ -655,12 +656,12 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
                 f64 = Fields<double>{(double*)d.pp[0][0], (double*)d.pp[0][1], (double*)d.mom[0], (double*)d.mom[1],
                                      (double*)d.pp[0][2], (double*)d.pp[0][3], (double*)d.pp[0][4], (double*)d.mom[2],
                                      (double*)d.mom[3], (double*)d.mom[4]};
-                e = launch_init<double>(f64, p->N, p->sigma, seed, P->stream);
+                e = launch_init<double>(f64, p->N, d.P, p->sigma, seed, P->stream);
             } else {
                 f32 = Fields<float>{(float*)d.pp[0][0], (float*)d.pp[0][1], (float*)d.mom[0], (float*)d.mom[1],
                                     (float*)d.pp[0][2], (float*)d.pp[0][3], (float*)d.pp[0][4], (float*)d.mom[2],
                                     (float*)d.mom[3], (float*)d.mom[4]};
-                e = launch_init<float>(f32, p->N, p->sigma, seed, P->stream);
+                e = launch_init<float>(f32, p->N, d.P, p->sigma, seed, P->stream);
             }
         }
         if (e != hipSuccess) {
@@ -813,7 +814,8 @@ int ah_pool_get_state(ah_pool* P, int64_t id, double* host_soa, int64_t* step)
         std::vector<float> tmp(rb == 4 ? V : 0);
         for (int cc = 0; cc < 10; ++cc) {
             double* dst = host_soa + cc * V;
-            e = hipMemcpy(rb == 8 ? (void*)dst : (void*)tmp.data(), comps[cc], V * rb, hipMemcpyDeviceToHost);
+            e = field_download(rb == 8 ? (void*)dst : (void*)tmp.data(), comps[cc], s->p.N, s->d.P, rb, P->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
             if (e != hipSuccess) return phip(P, e, "ah_pool_get_state copy");
             if (rb == 4)
                 for (size_t q = 0; q < V; ++q) dst[q] = (double)tmp[q];

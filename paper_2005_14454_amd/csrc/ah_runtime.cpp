@@ -22,7 +22,8 @@ struct ah_handle {
     bool owns_arena = false;
     void* arena = nullptr;
     size_t arena_bytes = 0;
-    int64_t V = 0;
+    int64_t V = 0;  // sites, N^3
+    int P = 0;      // row pitch of the stored fields (site (x, y, z) at x + P (y + N z))
     size_t real_bytes = 8;
     // ping-pong phi/A buffers [2][5] (phr, phi, a0, a1, a2) and Pi/E buffers
     // [2][5] (pir, pii, e0, e1, e2).  A single step drifts phi and A into the
@@ -177,8 +178,8 @@ int validate(const ah_params* p, std::string* why) { return validate_params(p, w
 
 size_t field_bytes(const ah_params& p)
 {
-    const size_t V = (size_t)p.N * p.N * p.N;
-    return align_up(V * (p.precision == AH_FP64 ? 8 : 4));
+    const size_t stored = (size_t)p.N * p.N * row_pitch(p.N, p.precision);
+    return align_up(stored * (p.precision == AH_FP64 ? 8 : 4));
 }
 
 
@@ -228,12 +229,34 @@ LatticeConst lconst(const ah_params& p)
 {
     LatticeConst L;
     L.N = p.N;
+    L.P = row_pitch(p.N, p.precision);
     L.compact = p.gauge_action == AH_COMPACT ? 1 : 0;
     L.dx = p.dx;
     L.deta = p.deta;
     L.sigma2 = p.sigma * p.sigma;
     return L;
 }
+
+}  // namespace
+
+namespace ah {
+
+hipError_t field_upload(void* dev, const void* host, int N, int P, size_t rb, hipStream_t s)
+{
+    if (P == N) return hipMemcpyAsync(dev, host, (size_t)N * N * N * rb, hipMemcpyHostToDevice, s);
+    return hipMemcpy2DAsync(dev, (size_t)P * rb, host, (size_t)N * rb, (size_t)N * rb, (size_t)N * N,
+                            hipMemcpyHostToDevice, s);
+}
+hipError_t field_download(void* host, const void* dev, int N, int P, size_t rb, hipStream_t s)
+{
+    if (P == N) return hipMemcpyAsync(host, dev, (size_t)N * N * N * rb, hipMemcpyDeviceToHost, s);
+    return hipMemcpy2DAsync(host, (size_t)N * rb, dev, (size_t)P * rb, (size_t)N * rb, (size_t)N * N,
+                            hipMemcpyDeviceToHost, s);
+}
+
+}  // namespace ah
+
+namespace {
 
 // component c of the state (order phi_re, phi_im, pi_re, pi_im, A0..2, E0..2)
 void* comp_ptr(ah_handle* h, int c)
@@ -632,6 +655,7 @@ int ah_create(const ah_params* p, void* dev_arena, size_t arena_bytes, void* hip
         h->p = *p;
         h->stream = (hipStream_t)hip_stream;
         h->V = (int64_t)p->N * p->N * p->N;
+        h->P = row_pitch(p->N, p->precision);
         h->real_bytes = p->precision == AH_FP64 ? 8 : 4;
         hipError_t e = hipGetDevice(&h->device);
         if (e != hipSuccess) {
@@ -727,8 +751,8 @@ int ah_init(ah_handle* h, uint64_t seed)
         h->curm = 0;
         h->step = 0;
         hipError_t e = h->p.precision == AH_FP64
-                           ? launch_init<double>(fields_of<double>(h, 0), h->p.N, h->p.sigma, seed, h->stream)
-                           : launch_init<float>(fields_of<float>(h, 0), h->p.N, h->p.sigma, seed, h->stream);
+                           ? launch_init<double>(fields_of<double>(h, 0), h->p.N, h->P, h->p.sigma, seed, h->stream)
+                           : launch_init<float>(fields_of<float>(h, 0), h->p.N, h->P, h->p.sigma, seed, h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "ah_init launch");
         h->ready = true;
         return AH_OK;
@@ -750,10 +774,10 @@ int ah_set_state(ah_handle* h, const double* host_soa, int64_t step)
         for (int c = 0; c < 10; ++c) {
             const double* src = host_soa + (size_t)c * V;
             if (h->real_bytes == 8) {
-                e = hipMemcpyAsync(comp_ptr(h, c), src, V * 8, hipMemcpyHostToDevice, h->stream);
+                e = field_upload(comp_ptr(h, c), src, h->p.N, h->P, 8, h->stream);
             } else {
                 for (size_t i = 0; i < V; ++i) tmp[i] = (float)src[i];
-                e = hipMemcpyAsync(comp_ptr(h, c), tmp.data(), V * 4, hipMemcpyHostToDevice, h->stream);
+                e = field_upload(comp_ptr(h, c), tmp.data(), h->p.N, h->P, 4, h->stream);
             }
             if (e != hipSuccess) return hip_fail(h, e, "ah_set_state copy");
             e = hipStreamSynchronize(h->stream);
@@ -778,9 +802,9 @@ int ah_get_state(ah_handle* h, double* host_soa, int64_t* step)
             double* dst = host_soa + (size_t)c * V;
             hipError_t e;
             if (h->real_bytes == 8) {
-                e = hipMemcpyAsync(dst, comp_ptr(h, c), V * 8, hipMemcpyDeviceToHost, h->stream);
+                e = field_download(dst, comp_ptr(h, c), h->p.N, h->P, 8, h->stream);
             } else {
-                e = hipMemcpyAsync(tmp.data(), comp_ptr(h, c), V * 4, hipMemcpyDeviceToHost, h->stream);
+                e = field_download(tmp.data(), comp_ptr(h, c), h->p.N, h->P, 4, h->stream);
             }
             if (e != hipSuccess) return hip_fail(h, e, "ah_get_state copy");
             e = hipStreamSynchronize(h->stream);
@@ -815,9 +839,9 @@ int ah_gather(ah_handle* h, const int64_t* sites, int64_t count, double* host_ou
         }
         e = hipMemcpyAsync(d_sites, sites, count * sizeof(int64_t), hipMemcpyHostToDevice, h->stream);
         if (e == hipSuccess)
-            e = rb == 8 ? launch_gather<double>(fields_of<double>(h, h->cur), (const int64_t*)d_sites, count, h->V,
+            e = rb == 8 ? launch_gather<double>(fields_of<double>(h, h->cur), (const int64_t*)d_sites, count, h->p.N, h->P,
                                                 (double*)d_out, h->stream)
-                        : launch_gather<float>(fields_of<float>(h, h->cur), (const int64_t*)d_sites, count, h->V,
+                        : launch_gather<float>(fields_of<float>(h, h->cur), (const int64_t*)d_sites, count, h->p.N, h->P,
                                                (float*)d_out, h->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(rb == 8 ? (void*)host_out : (void*)tmp.data(), d_out, count * 10 * rb,
@@ -854,9 +878,9 @@ int ah_gather_noalloc(ah_handle* h, const int64_t* sites, int64_t count, double*
         const size_t rb = h->real_bytes;
         e = hipMemcpyAsync(d_sites, sites, count * sizeof(int64_t), hipMemcpyHostToDevice, h->stream);
         if (e == hipSuccess)
-            e = rb == 8 ? launch_gather<double>(fields_of<double>(h, h->cur), d_sites, count, h->V, (double*)d_out,
+            e = rb == 8 ? launch_gather<double>(fields_of<double>(h, h->cur), d_sites, count, h->p.N, h->P, (double*)d_out,
                                                 h->stream)
-                        : launch_gather<float>(fields_of<float>(h, h->cur), d_sites, count, h->V, (float*)d_out,
+                        : launch_gather<float>(fields_of<float>(h, h->cur), d_sites, count, h->p.N, h->P, (float*)d_out,
                                                h->stream);
         // FP32 values land in the first half of host_out and are widened in
         // place, last first, so no host staging buffer is needed either

@@ -60,7 +60,7 @@ template <typename R>
 struct Step2Args {
     Fields<R> in;   // snapshot n
     Fields<R> out;  // snapshot n+2
-    int N;
+    int N, P;  // side, row pitch: site (x, y, z) at x + P (y + N z)
     SiteCoef<R> k0, k1;  // coefficients of steps n and n+1
     R dx;
 };
@@ -110,8 +110,8 @@ __global__ void __launch_bounds__((kStep2Threads<TX, TY>), (kStep2MinWaves<R, TX
     constexpr int W1 = G::W1, H1 = G::H1, W2 = G::W2, H2 = G::H2, NT = G::NT;
     __shared__ Shared2<R, TX, TY> sh;
 
-    const int N = a.N;
-    const int64_t NN = (int64_t)N * N;
+    const int N = a.N, P = a.P;
+    const int64_t NN = (int64_t)N * P;  // plane stride
     int t = xcd_tile(blockIdx.x, gridDim.x);
     const int x0 = (t % tiles_x) * TX;
     t /= tiles_x;
@@ -172,8 +172,8 @@ __global__ void __launch_bounds__((kStep2Threads<TX, TY>), (kStep2MinWaves<R, TX
     const int c1 = rx + W1 * ry;              // R1 index of the stage-1 site
     const int c2 = (rx + 1) + W2 * (ry + 1);  // its R2 index
     const int co = ox + W2 * oy;              // R2 index of the outer site
-    const int64_t xy1 = has1 ? (int64_t)wrapi(x0 - 1 + rx, N) + (int64_t)N * wrapi(y0 - 1 + ry, N) : 0;
-    const int64_t xyo = (int64_t)wrapi(x0 - 2 + ox, N) + (int64_t)N * wrapi(y0 - 2 + oy, N);
+    const int64_t xy1 = has1 ? (int64_t)wrapi(x0 - 1 + rx, N) + (int64_t)P * wrapi(y0 - 1 + ry, N) : 0;
+    const int64_t xyo = (int64_t)wrapi(x0 - 2 + ox, N) + (int64_t)P * wrapi(y0 - 2 + oy, N);
     const int gx = x0 + rx - 1, gy = y0 + ry - 1;
     const bool active = is_tile && gx < N && gy < N;
     const int64_t own_xy = xy1;
@@ -397,6 +397,7 @@ hipError_t launch_step2_tile(const Fields<R>& in, const Fields<R>& out, const La
     a.in = in;
     a.out = out;
     a.N = N;
+    a.P = L.P;
     a.dx = (R)L.dx;
     for (int j = 0; j < 2; ++j) {
         const StepCoef& c = j ? c1 : c0;

@@ -51,7 +51,7 @@ struct StepArgs {
     R* oa0;
     R* oa1;
     R* oa2;
-    int N;
+    int N, P;  // side, row pitch: site (x, y, z) at x + P (y + N z)
     R dx, sigma2, cP1, cP2, cE1, cE2, lamh, kappa, deta;
 };
 
@@ -231,15 +231,16 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
 
     const R inv_dx = R(1) / dx;
     const R inv_dx2 = inv_dx * inv_dx;
-    const int64_t NN = (int64_t)N * N;
+    const int P = a.P;
+    const int64_t NN = (int64_t)N * P;  // plane stride
 
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int gx = x0 + lx, gy = y0 + ly;
     const bool active = gx < N && gy < N;
     const int gxw = wrapi(gx, N), gyw = wrapi(gy, N);
-    const int64_t own_xy = (int64_t)gxw + (int64_t)N * gyw;
-    const uint32_t ob = (uint32_t)own_xy;  // 32-bit in-plane offset (N^2 < 2^32)
+    const int64_t own_xy = (int64_t)gxw + (int64_t)P * gyw;
+    const uint32_t ob = (uint32_t)own_xy;  // 32-bit in-plane offset (N P < 2^32)
     const int ro = (ly + 1) * RW + (lx + 1);  // own region slot
 
     // halo ring site of this thread (if any)
@@ -261,7 +262,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             hry = 1 + (tid - 2 * RW - TY);
         }
         rh = hry * RW + hrx;
-        halo_xy = (int64_t)wrapi(x0 - 1 + hrx, N) + (int64_t)N * wrapi(y0 - 1 + hry, N);
+        halo_xy = (int64_t)wrapi(x0 - 1 + hrx, N) + (int64_t)P * wrapi(y0 - 1 + hry, N);
     }
     const uint32_t hb = (uint32_t)halo_xy;
     // halo sites whose link phases the windings of the tile read
@@ -760,6 +761,7 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(con
     a.oa1 = (R*)L.pp[cur ^ 1][3];
     a.oa2 = (R*)L.pp[cur ^ 1][4];
     a.N = L.N;
+    a.P = L.P;
     a.dx = (R)L.dx;
     a.sigma2 = (R)L.sigma2;
     a.cP1 = (R)row[C_P1];
@@ -793,22 +795,27 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(con
 // - c Im[conj(phi^x) Pi^x] on the stored half-step fields, in FP64 from the
 // exactly widened stored values.  Each workgroup walks a fixed grid-stride
 // set of sites of the lattice and writes one record (Gauss slots only).
+// Sites are taken in dense order s = x + N (y + N z), each at its stored
+// offset x + P (y + N z).
 template <typename R>
-__device__ void gauss_block(const Fields<R>& f, int N, double inv_dx, double gc, int block, int nblocks,
+__device__ void gauss_block(const Fields<R>& f, int N, int P, double inv_dx, double gc, int block, int nblocks,
                             double* __restrict__ record, double* red)
 {
     const int64_t V = (int64_t)N * N * N;
-    const int64_t NN = (int64_t)N * N;
+    const int64_t NN = (int64_t)N * N, NP = (int64_t)N * P;
     double g2 = 0.0, d2 = 0.0, c2 = 0.0, gmax = 0.0;
     for (int64_t s = (int64_t)block * 256 + threadIdx.x; s < V; s += (int64_t)nblocks * 256) {
-        const int x = (int)(s % N), y = (int)((s / N) % N);
-        const int64_t sxm = s + (x == 0 ? N - 1 : -1);
-        const int64_t sym = s + (y == 0 ? NN - N : -(int64_t)N);
-        const int64_t szm = s >= NN ? s - NN : s + V - NN;
-        const double dv = (((double)f.e0[s] - (double)f.e0[sxm]) * inv_dx +
-                           ((double)f.e1[s] - (double)f.e1[sym]) * inv_dx) +
-                          ((double)f.e2[s] - (double)f.e2[szm]) * inv_dx;
-        const double crho = gc * ((double)f.phr[s] * (double)f.pii[s] - (double)f.phi[s] * (double)f.pir[s]);
+        const int64_t row = s / N;  // y + N z
+        const int x = (int)(s - row * N);
+        const int z = (int)(row / N), y = (int)(row - (int64_t)z * N);
+        const int64_t o = x + row * P;
+        const int64_t sxm = o + (x == 0 ? N - 1 : -1);
+        const int64_t sym = o + (y == 0 ? NP - P : -(int64_t)P);
+        const int64_t szm = z > 0 ? o - NP : o + (NN - N) * P;
+        const double dv = (((double)f.e0[o] - (double)f.e0[sxm]) * inv_dx +
+                           ((double)f.e1[o] - (double)f.e1[sym]) * inv_dx) +
+                          ((double)f.e2[o] - (double)f.e2[szm]) * inv_dx;
+        const double crho = gc * ((double)f.phr[o] * (double)f.pii[o] - (double)f.phi[o] * (double)f.pir[o]);
         const double G = dv - crho;
         g2 += G * G;
         d2 += dv * dv;
@@ -835,10 +842,11 @@ __device__ void gauss_block(const Fields<R>& f, int N, double inv_dx, double gc,
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_gauss(Fields<R> f, int N, double inv_dx, double gc, double* partials)
+__global__ void __launch_bounds__(256) k_gauss(Fields<R> f, int N, int P, double inv_dx, double gc,
+                                               double* partials)
 {
     __shared__ double red[16];
-    gauss_block<R>(f, N, inv_dx, gc, blockIdx.x, gridDim.x, partials + (int64_t)blockIdx.x * kMeasStride, red);
+    gauss_block<R>(f, N, P, inv_dx, gc, blockIdx.x, gridDim.x, partials + (int64_t)blockIdx.x * kMeasStride, red);
 }
 
 // Gauss residual of every pool lattice whose snapshot is due, before it is stepped.
@@ -856,7 +864,7 @@ __global__ void __launch_bounds__(256) k_gauss_batch(const PoolLattice* __restri
         const Fields<R> f{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[0], (R*)L.mom[1], (R*)L.pp[cur][2],
                           (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[2], (R*)L.mom[3], (R*)L.mom[4]};
         const double* row = L.coef + k * kCoefStride;
-        gauss_block<R>(f, L.N, 1.0 / L.dx, row[C_GAUSS], it.tile, L.gauss_blocks,
+        gauss_block<R>(f, L.N, L.P, 1.0 / L.dx, row[C_GAUSS], it.tile, L.gauss_blocks,
                        L.partials + (int64_t)(L.meas_blocks + it.tile) * kMeasStride, red);
     }
 }
@@ -904,6 +912,7 @@ hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa
     a.oa1 = oa1;
     a.oa2 = oa2;
     a.N = N;
+    a.P = L.P;
     a.dx = (R)L.dx;
     a.sigma2 = (R)L.sigma2;
     a.cP1 = (R)c.cP1;
@@ -993,7 +1002,7 @@ int gauss_blocks(int N)
 template <typename R>
 hipError_t launch_gauss(const Fields<R>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gauss<R>, dim3(gauss_blocks(L.N)), dim3(256), 0, s, f, L.N, 1.0 / L.dx, gc, partials);
+    hipLaunchKernelGGL(k_gauss<R>, dim3(gauss_blocks(L.N)), dim3(256), 0, s, f, L.N, L.P, 1.0 / L.dx, gc, partials);
     return hipGetLastError();
 }
 template hipError_t launch_gauss<double>(const Fields<double>&, const LatticeConst&, double, double*, hipStream_t);
