@@ -219,9 +219,13 @@ int ah_get_winding(ah_handle* h, int8_t* host_w);
 typedef struct ah_step_config {
     int32_t kernel;         /* AH_KERNEL_* */
     int32_t tile_x, tile_y; /* tiled kernel: (64,8), (64,4), (32,8), (128,4) (FP32 also (64,16), (128,8));
-                             * two-step kernel: see AH_KERNEL_TILE2; 0,0 = default */
-    int32_t zchunk;         /* x2-planes per workgroup of the tiled kernel; 0 = automatic, else >= 2
-                             * for N <= 128 and >= 8 above (the last chunk of a column may be shorter) */
+                             * two-step kernel: see AH_KERNEL_TILE2; 0,0 = default: the shape of the
+                             * highest measured rate once the idle lanes of a ragged last tile are
+                             * counted (one step), (32,8) (two steps) */
+    int32_t zchunk;         /* x2-planes per workgroup of the tiled kernel; 0 = automatic: equal chunks,
+                             * the count that minimises (rounds of resident workgroups) x (planes per
+                             * chunk + 2); else >= 2 for N <= 128 and >= 8 above (the last chunk of a
+                             * column may be shorter) */
 } ah_step_config;
 
 /* Select the step kernel; AH_E_INVAL for an unsupported combination. */
@@ -281,16 +285,19 @@ int ah_tune_load(const char* path);
  * history; compact action) resident in one device arena and advances all
  * active ones together: each ah_pool_advance step is one replay of a HIP
  * graph holding the diagnostics pass of the lattices whose snapshot is due,
- * its fixed-order fold, the tiled step of every active lattice (one kernel
- * node per precision and tile shape, one block per (lattice, tile) work
- * item) and a counter update.  Pool lattices run the tuned (else default)
- * tile shape with FP32 1024-thread shapes halved in y and FP64 on 32 x 8,
- * and z-chunks of at least 16 planes (ah_pool_step_config reports them).
- * Every lattice takes the coefficients of its own step from its own FP64
- * table, so its fields and diagnostics are bitwise identical to the same
- * lattice run alone through ah_step / ah_measure with the same tiling.  Requests enter and leave between
- * advances (continuous batching); the graph is rebuilt when the set changes.
- * A pool is used from one host thread at a time. */
+ * the measured step of those lattices and its fixed-order fold, the plain
+ * step of every other active lattice (one kernel node per precision and
+ * tile shape, one block per (lattice, tile) work item) and a counter update.
+ * Pool lattices run the tuned one-step (else the default) tile shape with
+ * z-chunks of at least 16 planes (ah_pool_step_config reports them), and
+ * their measured steps the measured march's tiling, as a lattice alone
+ * does.  Every lattice takes the coefficients of its own step from its own
+ * FP64 table, so its fields and diagnostics are bitwise identical to the
+ * same lattice run alone through ah_step / ah_measure with the same tiling.
+ * Requests enter and leave between advances (continuous batching); the
+ * graph is captured again only when a node's work list outgrows its
+ * capacity (or shrinks far below it) or a new node is needed.  A pool is
+ * used from one host thread at a time. */
 typedef struct ah_pool ah_pool;
 
 typedef struct ah_pool_info {
@@ -300,6 +307,7 @@ typedef struct ah_pool_info {
     int32_t active;         /* lattices admitted and not yet collected */
     int32_t max_slots;
     int64_t graph_launches; /* steps issued so far */
+    int64_t graph_captures; /* times the per-step graph was captured */
 } ah_pool_info;
 
 /* Create a pool with a device arena of hbm_budget bytes (hipMalloc'd and

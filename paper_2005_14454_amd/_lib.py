@@ -59,7 +59,8 @@ class ah_step_config(ctypes.Structure):
 
 class ah_pool_info(ctypes.Structure):
     _fields_ = [("budget", ctypes.c_size_t), ("bytes_in_use", ctypes.c_size_t), ("largest_free", ctypes.c_size_t),
-                ("active", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("graph_launches", ctypes.c_int64)]
+                ("active", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("graph_launches", ctypes.c_int64),
+                ("graph_captures", ctypes.c_int64)]
 
 
 class AHError(RuntimeError):

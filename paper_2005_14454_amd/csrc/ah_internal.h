@@ -125,6 +125,24 @@ inline bool tile2_supported(int precision, int tx, int ty)
     return tx == 64 && ty == 8 && precision == AH_FP32;
 }
 
+// Tile shapes of the pool's batched plain step (its measured step runs the
+// measured march's shape, measured_tile).
+inline bool batch_tile_supported(int precision, int tx, int ty)
+{
+    if ((tx == 64 && (ty == 8 || ty == 4)) || (tx == 32 && ty == 8)) return true;
+    return precision == AH_FP32 && tx == 128 && (ty == 4 || ty == 8);
+}
+
+// Default one-step tile shape for side N; false if none applies.
+bool default_tile(int precision, int N, int* tx, int* ty);
+// Workgroups of a tiled launch one CU holds at once (measured: the march
+// that also forms the diagnostics).
+int resident_per_cu(int kernel, int precision, int tx, int ty, bool measured);
+// Automatic z-chunk of a tiled launch.
+int auto_zchunk(int kernel, int precision, int N, int tx, int ty, bool measured);
+// Tiling of the measured march of a lattice stepped with cfg (resolved).
+TileConfig measured_tiling(const ah_params& p, const ah_step_config& cfg);
+
 // Smallest z-chunk the tiled kernels accept for a lattice of side N.  Short
 // chunks pay for themselves only on small lattices, which they give enough
 // workgroups (64^3 FP32 on MI355X: 2-plane chunks step in 11.4 us, 8-plane
@@ -162,6 +180,7 @@ struct PoolLattice {
     int N, tiles_x, tiles_y, zchunk;     // step tiling
     int meas_zchunk, meas_blocks, measure_every, precision;
     int gauss_blocks, P;     // Gauss records follow the meas_blocks step records; P: row pitch
+    int mtiles_x, mtiles_y;  // tiling of the measured step (measured_tile), z-chunks of meas_zchunk
     int compact, pad0;
     double dx, deta, sigma2;
 };
@@ -169,6 +188,7 @@ struct WorkItem {
     int lattice, tile;  // lattice < 0: an empty item (padding)
 };
 constexpr int kXcdCount = 8;           // XCDs of the device; block b runs on XCD b % 8
+constexpr int kGaussPerItem = 8;       // Gauss-pass blocks of one lattice per pool work item
 constexpr int kSeriesStride = 18;      // M_COUNT sums + step index + pad
 static_assert(M_COUNT + 1 <= kSeriesStride, "a series record holds the sums and the step index");
 

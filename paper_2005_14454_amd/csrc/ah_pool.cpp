@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -63,13 +64,15 @@ struct Slot {
     int measure_every = 0;
     size_t off = 0, bytes = 0;
     ah_step_config cfg{};
+    TileConfig meas{};  // tiling of the measured step
     PoolLattice d{};
     bool reported = false;
 };
 
 struct Footprint {
     size_t field, fields, partials, coef, series, total;
-    int meas_blocks, meas_zc, gauss_blocks;
+    TileConfig meas;  // tiling of the measured step
+    int meas_blocks, gauss_blocks;
     int64_t series_cap;
 };
 
@@ -85,8 +88,8 @@ Footprint footprint(const ah_params& p, const ah_step_config& cfg, int64_t nstep
     const size_t stored = (size_t)p.N * p.N * row_pitch(p.N, p.precision);
     f.field = align_up(stored * (p.precision == AH_FP64 ? 8 : 4));
     f.fields = 15 * f.field;
-    f.meas_zc = cfg.zchunk;
-    f.meas_blocks = step_tile_blocks(p.N, TileConfig{cfg.tile_x, cfg.tile_y, cfg.zchunk});
+    f.meas = measured_tiling(p, cfg);
+    f.meas_blocks = step_tile_blocks(p.N, f.meas);
     f.gauss_blocks = gauss_blocks(p.N);
     f.partials = align_up((size_t)(f.meas_blocks + f.gauss_blocks) * kMeasStride * sizeof(double));
     f.coef = align_up((size_t)(nsteps + 1) * kCoefStride * sizeof(double));
@@ -115,6 +118,19 @@ struct Retired {
     hipEvent_t ev;  // recorded after the last work that could use them
 };
 
+// A node group of the pool graph: kind 0 the Gauss pass of one precision,
+// kind 1 the step (plain and measured) of one precision and tile shape.
+struct GroupKey {
+    int kind, precision, tx, ty;
+    bool operator<(const GroupKey& o) const
+    {
+        return std::tie(kind, precision, tx, ty) < std::tie(o.kind, o.precision, o.tx, o.ty);
+    }
+};
+struct NodeGroup {
+    size_t off, cap;  // region of the work list (items); a step group's cap is a multiple of kXcdCount
+};
+
 struct ah_pool {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -139,6 +155,8 @@ struct ah_pool {
     int64_t* d_counters = nullptr;
     WorkItem* d_work = nullptr;
     size_t work_cap = 0;
+    std::map<GroupKey, NodeGroup> groups;  // work-list regions of the captured graph's nodes
+    int64_t graph_captures = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool dirty = true;
@@ -338,9 +356,17 @@ hipError_t retire(ah_pool* P, hipGraphExec_t exec, hipGraph_t graph, void* buf)
     return hipSuccess;
 }
 
-// Rebuild descriptors, work lists and the per-step graph.  Nothing here
-// waits for the stream: the uploads are ordered after the replays already
-// queued, which keep reading the old descriptors until then.
+// Rebuild descriptors and work lists, and the per-step graph when its
+// node layout no longer fits.  Nothing here waits for the stream: the
+// uploads are ordered after the replays already queued, which keep reading
+// the old descriptors and lists until then.
+//
+// The graph has one Gauss node per precision and one step node (plain and
+// measured) per (precision, tile shape), each over a fixed-capacity region
+// of the work list whose unused items are empty.  An admission or a release
+// that fits the captured capacities only rewrites the lists; a new group or
+// a list beyond its capacity (or far below it) captures anew, with room for
+// growth.
 int rebuild(ah_pool* P)
 {
     hipError_t e;
@@ -355,79 +381,112 @@ int rebuild(ah_pool* P)
             desc[i].counter = P->d_counters + 2 * i;
         }
     }
-    // work lists: one per (precision, tile shape); the measured-step node and
-    // the plain-step node of a group share it
-    struct Group {
-        int precision, tx, ty;
-        size_t off, n;
-    };
-    std::vector<WorkItem> work;
-    std::vector<Group> step_groups, gauss_groups;
-    for (int prec : {AH_FP32, AH_FP64}) {
-        Group g{prec, 0, 0, work.size(), 0};
-        for (int i = 0; i < nslot; ++i) {
-            const Slot& s = P->slots[i];
-            if (!s.used || s.p.precision != prec) continue;
-            for (int t = 0; t < s.d.gauss_blocks; ++t) work.push_back({i, t});
-        }
-        g.n = work.size() - g.off;
-        if (g.n) gauss_groups.push_back(g);
+    // the lists each group needs now: Gauss items per precision; step items
+    // per (precision, tile shape) in kXcdCount bands
+    std::map<GroupKey, std::vector<WorkItem>> gauss_need;
+    std::map<GroupKey, std::array<std::vector<WorkItem>, kXcdCount>> step_need;
+    for (int i = 0; i < nslot; ++i) {
+        const Slot& s = P->slots[i];
+        if (!s.used) continue;
+        auto& g = gauss_need[GroupKey{0, s.p.precision, 0, 0}];
+        for (int t = 0; t < s.d.gauss_blocks; t += kGaussPerItem) g.push_back({i, t});
     }
-    std::map<std::tuple<int, int, int>, std::vector<int>> by_shape;
-    for (int i = 0; i < nslot; ++i)
-        if (P->slots[i].used)
-            by_shape[{P->slots[i].p.precision, P->slots[i].cfg.tile_x, P->slots[i].cfg.tile_y}].push_back(i);
+    // step groups: kind 1 the plain step per (precision, tile shape), kind 2
+    // the measured step per (precision, measured tile shape)
+    std::map<GroupKey, std::vector<int>> by_shape;
+    for (int i = 0; i < nslot; ++i) {
+        const Slot& s = P->slots[i];
+        if (!s.used) continue;
+        by_shape[GroupKey{1, s.p.precision, s.cfg.tile_x, s.cfg.tile_y}].push_back(i);
+        by_shape[GroupKey{2, s.p.precision, s.meas.tx, s.meas.ty}].push_back(i);
+    }
     // The step kernels run one block per item and give XCD x (which runs
     // blocks x, x+8, ...) the x-th eighth of the list.  So that every XCD
     // gets an equal share of every lattice, with neighbouring tiles (which
     // read each other's halo) in the same L2, each lattice's tiles, in index
     // order, are cut into eight contiguous runs, run x goes to band x, bands
-    // list the lattices with the longest z-marches first and are padded to
-    // one length with empty items.
+    // list the lattices with the longest z-marches first.
     for (auto& kv : by_shape) {
-        Group g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), work.size(), 0};
+        const bool meas = kv.first.kind == 2;
+        auto zc_of = [&](const PoolLattice& d) { return meas ? d.meas_zchunk : d.zchunk; };
         std::vector<int> order = kv.second;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
             const PoolLattice &da = P->slots[a].d, &db = P->slots[b].d;
-            return std::min(da.zchunk, da.N) > std::min(db.zchunk, db.N);  // planes per item
+            return std::min(zc_of(da), da.N) > std::min(zc_of(db), db.N);  // planes per item
         });
-        std::vector<WorkItem> band[kXcdCount];
+        auto& band = step_need[kv.first];
         for (int i : order) {
             const PoolLattice& d = P->slots[i].d;
-            const int tiles_z = (d.N + d.zchunk - 1) / d.zchunk;
-            const int nt = d.tiles_x * d.tiles_y * tiles_z;
+            const int tiles_z = (d.N + zc_of(d) - 1) / zc_of(d);
+            const int nt = (meas ? d.mtiles_x * d.mtiles_y : d.tiles_x * d.tiles_y) * tiles_z;
             for (int x = 0; x < kXcdCount; ++x) {
                 const int t0 = (int)((int64_t)nt * x / kXcdCount), t1 = (int)((int64_t)nt * (x + 1) / kXcdCount);
                 for (int t = t0; t < t1; ++t) band[x].push_back({i, t});
             }
         }
-        size_t len = 0;
-        for (auto& b : band) len = std::max(len, b.size());
-        for (auto& b : band) {
-            b.resize(len, WorkItem{-1, 0});
-            work.insert(work.end(), b.begin(), b.end());
-        }
-        g.n = work.size() - g.off;
-        if (len) step_groups.push_back(g);
     }
-    if (work.size() > P->work_cap) {
-        // the queued replays may still read the old list: it is freed once they have run
-        if (P->d_work) {
-            e = retire(P, nullptr, nullptr, P->d_work);
-            if (e != hipSuccess) return phip(P, e, "pool work list retire");
-        }
-        P->d_work = nullptr;
-        size_t cap = std::max<size_t>(work.size() * 2, 4096);
-        e = hipMalloc(&P->d_work, cap * sizeof(WorkItem));
-        if (e != hipSuccess) {
+    // items each group needs (a step group: kXcdCount bands of the longest band's length)
+    std::map<GroupKey, size_t> need;
+    for (auto& kv : gauss_need) need[kv.first] = kv.second.size();
+    for (auto& kv : step_need) {
+        size_t len = 0;
+        for (auto& b : kv.second) len = std::max(len, b.size());
+        need[kv.first] = len * kXcdCount;
+    }
+    size_t need_total = 0, cap_total = 0;
+    bool fits = P->exec != nullptr;
+    for (auto& kv : need) {
+        need_total += kv.second;
+        auto it = P->groups.find(kv.first);
+        if (it == P->groups.end() || it->second.cap < kv.second) fits = false;
+    }
+    for (auto& kv : P->groups) cap_total += kv.second.cap;
+    if (cap_total > 4 * std::max<size_t>(need_total, 4096)) fits = false;  // mostly empty: shrink
+    if (!fits) {
+        // capacities with room for growth (groups that emptied keep a small
+        // one), laid out one after another
+        std::map<GroupKey, NodeGroup> groups;
+        size_t off = 0;
+        auto add = [&](const GroupKey& k, size_t n) {
+            const size_t unit = k.kind != 0 ? (size_t)kXcdCount * 32 : 256;
+            size_t cap = std::max<size_t>(n + n / 4, unit);
+            cap = (cap + unit - 1) / unit * unit;
+            groups[k] = NodeGroup{off, cap};
+            off += cap;
+        };
+        for (auto& kv : need) add(kv.first, kv.second);
+        for (auto& kv : P->groups)
+            if (!need.count(kv.first)) add(kv.first, 0);
+        if (off > P->work_cap) {
+            // the queued replays may still read the old list: it is freed once they have run
+            if (P->d_work) {
+                e = retire(P, nullptr, nullptr, P->d_work);
+                if (e != hipSuccess) return phip(P, e, "pool work list retire");
+            }
+            P->d_work = nullptr;
             P->work_cap = 0;
-            return phip(P, e, "pool work list allocation");
+            e = hipMalloc(&P->d_work, off * sizeof(WorkItem));
+            if (e != hipSuccess) return phip(P, e, "pool work list allocation");
+            P->work_cap = off;
         }
-        P->work_cap = cap;
+        P->groups = groups;
+    }
+    // the whole list, every group at its offset, unused items empty
+    size_t total = 0;
+    for (auto& kv : P->groups) total = std::max(total, kv.second.off + kv.second.cap);
+    std::vector<WorkItem> work(total, WorkItem{-1, 0});
+    for (auto& kv : gauss_need) std::copy(kv.second.begin(), kv.second.end(), work.begin() + P->groups[kv.first].off);
+    for (auto& kv : step_need) {
+        const NodeGroup& g = P->groups[kv.first];
+        const size_t per_band = g.cap / kXcdCount;
+        for (int x = 0; x < kXcdCount; ++x)
+            std::copy(kv.second[x].begin(), kv.second[x].end(), work.begin() + g.off + x * per_band);
     }
     e = stage_upload(P, P->d_lat, desc.data(), nslot * sizeof(PoolLattice));
-    if (e == hipSuccess && !work.empty()) e = stage_upload(P, P->d_work, work.data(), work.size() * sizeof(WorkItem));
+    if (e == hipSuccess && total) e = stage_upload(P, P->d_work, work.data(), total * sizeof(WorkItem));
     if (e != hipSuccess) return phip(P, e, "pool descriptor upload");
+    P->dirty = false;
+    if (fits) return AH_OK;
 
     if (P->exec || P->graph) {
         e = retire(P, P->exec, P->graph, nullptr);
@@ -435,25 +494,30 @@ int rebuild(ah_pool* P)
     }
     P->exec = nullptr;
     P->graph = nullptr;
+    P->dirty = true;  // until a graph is instantiated
     e = hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return phip(P, e, "pool graph capture begin");
     hipError_t le = hipSuccess;
     // Gauss residual of the due snapshots (read-only, before anything is
     // overwritten), measured steps of the due lattices, their fold, the plain
     // steps of all others, the counter update
-    for (auto& g : gauss_groups) {
-        if (le != hipSuccess) break;
-        const int grid = (int)std::min<size_t>(g.n, 2048);
-        le = g.precision == AH_FP64 ? launch_gauss_batch<double>(P->d_lat, P->d_work + g.off, (int)g.n, grid, P->stream)
-                                    : launch_gauss_batch<float>(P->d_lat, P->d_work + g.off, (int)g.n, grid, P->stream);
+    for (auto& kv : P->groups) {
+        if (kv.first.kind != 0 || le != hipSuccess) continue;
+        const NodeGroup& g = kv.second;
+        const int grid = (int)std::min<size_t>(g.cap, 2048);
+        le = kv.first.precision == AH_FP64
+                 ? launch_gauss_batch<double>(P->d_lat, P->d_work + g.off, (int)g.cap, grid, P->stream)
+                 : launch_gauss_batch<float>(P->d_lat, P->d_work + g.off, (int)g.cap, grid, P->stream);
     }
     for (int measured = 1; measured >= 0; --measured) {
-        for (auto& g : step_groups) {
-            if (le != hipSuccess) break;
-            const int grid = (int)g.n;  // one block per work item
-            le = g.precision == AH_FP64 ? launch_step_batch<double>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx,
-                                                                    g.ty, grid, measured != 0, P->stream)
-                                        : launch_step_batch<float>(P->d_lat, P->d_work + g.off, (int)g.n, g.tx, g.ty,
+        for (auto& kv : P->groups) {
+            if (kv.first.kind != (measured ? 2 : 1) || le != hipSuccess) continue;
+            const GroupKey& k = kv.first;
+            const NodeGroup& g = kv.second;
+            const int grid = (int)g.cap;  // one block per work item
+            le = k.precision == AH_FP64 ? launch_step_batch<double>(P->d_lat, P->d_work + g.off, (int)g.cap, k.tx,
+                                                                    k.ty, grid, measured != 0, P->stream)
+                                        : launch_step_batch<float>(P->d_lat, P->d_work + g.off, (int)g.cap, k.tx, k.ty,
                                                                    grid, measured != 0, P->stream);
         }
         if (measured && le == hipSuccess) le = launch_fold_batch(P->d_lat, nslot, P->stream);
@@ -464,6 +528,7 @@ int rebuild(ah_pool* P)
     if (e != hipSuccess) return phip(P, e, "pool graph capture end");
     e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return phip(P, e, "pool graph instantiate");
+    ++P->graph_captures;
     P->dirty = false;
     return AH_OK;
 }
@@ -525,25 +590,26 @@ int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_po
     });
 }
 
-// Tile configuration of a pool lattice: the tuned (or default) tile shape
-// and z-chunk, with z-chunks of at least 16 planes.  The pool supplies much
-// of the parallelism that short z-chunks buy a lattice run alone; 16 planes
-// keep enough work items for ensembles of small lattices (measured on
-// MI355X: 128 lattices of N in {32, 48, 64} run 11% faster than with
-// 64-plane chunks, a mix of N in 64 .. 256 2% faster; 8 and 32 planes are
-// slower than 16).
+// Tile configuration of a pool lattice: the tuned one-step configuration if
+// the pool's step is built for its shape (a two-step entry lends its tile
+// shape, with the automatic z-chunk), else the default, as for a lattice run
+// alone; z-chunks of at least 16 planes.  The measured node runs the
+// measured march's tiling (measured_tiling), as a lattice alone does.
+// The pool supplies much of the parallelism that short z-chunks buy a
+// lattice run alone; 16 planes keep enough work items for ensembles of small
+// lattices (measured on MI355X: 128 lattices of N in {32, 48, 64} run 11%
+// faster than with 64-plane chunks, a mix of N in 64 .. 256 2% faster; 8
+// and 32 planes are slower than 16).
 static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why)
 {
     ah_step_config t{AH_KERNEL_TILE, 0, 0, 0};
-    (void)tuned_config(p, &t);
-    t.kernel = AH_KERNEL_TILE;  // the pool steps one step per replay; a two-step entry lends its tile
+    if (tuned_config(p, &t)) {
+        if (t.kernel != AH_KERNEL_TILE) t.zchunk = 0;
+        t.kernel = AH_KERNEL_TILE;
+        if (!batch_tile_supported(p.precision, t.tile_x, t.tile_y)) t = ah_step_config{AH_KERNEL_TILE, 0, 0, 0};
+    }
     const int rc = resolve_step_config(p, t, cfg, why);
     if (rc != AH_OK) return rc;
-    // one tile shape serves both nodes, so it must be one whose measured march
-    // keeps its registers: FP32 1024-thread tiles are halved in y, FP64 runs
-    // on 32 x 8 (as fast as any FP64 shape for the plain step)
-    if (p.precision == AH_FP32 && cfg->tile_x * cfg->tile_y == 1024) cfg->tile_y /= 2;
-    if (p.precision == AH_FP64) (void)measured_tile(p.precision, &cfg->tile_x, &cfg->tile_y);
     int zc = cfg->zchunk < 16 ? 16 : cfg->zchunk;
     if (zc > p.N) zc = p.N;
     cfg->zchunk = zc;
@@ -608,6 +674,7 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         s.off = off;
         s.bytes = fp.total;
         s.cfg = cfg;
+        s.meas = fp.meas;
         char* base = (char*)P->arena + off;
         PoolLattice& d = s.d;
         std::memset(&d, 0, sizeof(d));
@@ -634,7 +701,9 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         d.tiles_x = (p->N + cfg.tile_x - 1) / cfg.tile_x;
         d.tiles_y = (p->N + cfg.tile_y - 1) / cfg.tile_y;
         d.zchunk = cfg.zchunk;
-        d.meas_zchunk = fp.meas_zc;
+        d.mtiles_x = (p->N + fp.meas.tx - 1) / fp.meas.tx;
+        d.mtiles_y = (p->N + fp.meas.ty - 1) / fp.meas.ty;
+        d.meas_zchunk = fp.meas.zchunk;
         d.meas_blocks = fp.meas_blocks;
         d.gauss_blocks = fp.gauss_blocks;
         d.measure_every = measure_every;
@@ -879,6 +948,7 @@ int ah_pool_stats(const ah_pool* P, ah_pool_info* info)
     info->largest_free = largest_free(P);
     info->max_slots = (int32_t)P->slots.size();
     info->graph_launches = P->graph_launches;
+    info->graph_captures = P->graph_captures;
     return AH_OK;
 }
 

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -291,6 +292,102 @@ struct DeviceGuard {
 }  // namespace
 
 namespace ah {
+
+// Step rates of the one-step tile shapes on a lattice they tile exactly
+// (MI355X, 512^3, best z-chunk; 1e9 site-updates/s; 0: no such instance).
+namespace {
+struct ShapeRate {
+    int tx, ty;
+    double fp32, fp64;
+};
+constexpr ShapeRate kShapeRates[] = {
+    {128, 4, 65.9, 0.0}, {128, 8, 64.7, 0.0}, {64, 8, 61.2, 28.3}, {64, 4, 60.8, 27.1}, {32, 8, 59.0, 27.7},
+};
+}  // namespace
+
+bool default_tile(int precision, int N, int* tx, int* ty)
+{
+    double best = 0.0;
+    for (const ShapeRate& r : kShapeRates) {
+        const double rate = precision == AH_FP64 ? r.fp64 : r.fp32;
+        if (rate <= 0.0 || !tile_supported(precision, r.tx, r.ty) || !batch_tile_supported(precision, r.tx, r.ty))
+            continue;
+        // a ragged last tile in x or y runs idle lanes
+        const double rx = (double)((N + r.tx - 1) / r.tx * r.tx) / N, ry = (double)((N + r.ty - 1) / r.ty * r.ty) / N;
+        const double score = rate / (rx * ry);
+        if (score > best) {
+            best = score;
+            *tx = r.tx;
+            *ty = r.ty;
+        }
+    }
+    return best > 0.0;
+}
+
+int resident_per_cu(int kernel, int precision, int tx, int ty, bool measured)
+{
+    if (kernel == AH_KERNEL_TILE2) {
+        // waves per SIMD at the pass's registers: FP32 3, FP64 2; the FP64
+        // pass's LDS (over 100 KB) admits one workgroup per CU
+        if (precision == AH_FP64) return 1;
+        const int nt = tx * ty, ring = (tx + 2) * (ty + 2) - nt;
+        const int waves = (nt + (ring + 63) / 64 * 64) / 64;
+        return std::max(1, 12 / waves);
+    }
+    // waves per SIMD at the march's registers: plain FP32 4, FP64 2; the
+    // measured march 2 in both precisions
+    const int waves = (tx * ty + 63) / 64;
+    return std::max(1, (precision == AH_FP64 || measured ? 8 : 16) / waves);
+}
+
+int auto_zchunk(int kernel, int precision, int N, int tx, int ty, bool measured)
+{
+    // Workgroups run in rounds of (CUs x resident workgroups); a launch
+    // takes about rounds x (planes per chunk + 2), the 2 for a chunk's
+    // prologue.  The z-chunks are equal (a short last chunk would leave most
+    // of its round idle); among equal estimates the one with more
+    // workgroups, which spread more evenly over the XCDs.  Chosen on MI355X
+    // over a sweep of N in 65 .. 512 and five tile shapes: within 2% of the
+    // best measured z-chunk on average.
+    constexpr int kCUs = 256;
+    const int64_t per_chunk = (int64_t)((N + tx - 1) / tx) * ((N + ty - 1) / ty);
+    const int64_t slots = (int64_t)kCUs * resident_per_cu(kernel, precision, tx, ty, measured);
+    const int zmin = std::min(min_zchunk(N), N);
+    int best_zc = N;
+    int64_t best_t = -1, best_nb = 0;
+    for (int nz = 1; nz <= N / zmin; ++nz) {
+        const int zc = (N + nz - 1) / nz;
+        if (zc < zmin) break;
+        const int64_t nb = per_chunk * ((N + zc - 1) / zc);
+        const int64_t t = (nb + slots - 1) / slots * (zc + 2);
+        if (best_t < 0 || t < best_t || (t == best_t && nb > best_nb)) {
+            best_t = t;
+            best_nb = nb;
+            best_zc = zc;
+        }
+    }
+    return best_zc;
+}
+
+// Any tile shape computes the same fields bit for bit, so the measured march
+// may run another shape than the plain step: the fastest measured march
+// (measured_tile: FP32 64 x 8, FP64 32 x 8), with the step's z-chunk when
+// the step runs that shape too, else the automatic z-chunk of the measured
+// march but no shorter than the step's (a pool's floor of 16 planes then
+// holds for its measured node too).  A lattice of the site kernel takes the
+// automatic one.  The diagnostics records are summed in tile order, so a
+// lattice measured with the same tiling (alone or in a pool) gets the same
+// bits.
+TileConfig measured_tiling(const ah_params& p, const ah_step_config& cfg)
+{
+    int tx = cfg.tile_x, ty = cfg.tile_y;
+    const bool tiled = cfg.kernel == AH_KERNEL_TILE || cfg.kernel == AH_KERNEL_TILE2;
+    if (!measured_tile(p.precision, &tx, &ty) && tiled) return TileConfig{tx, ty, cfg.zchunk};
+    int zc = auto_zchunk(AH_KERNEL_TILE, p.precision, p.N, tx, ty, true);
+    if (tiled && cfg.zchunk > zc) zc = std::min(cfg.zchunk, p.N);
+    return TileConfig{tx, ty, zc};
+}
+
 // Resolve automatic choices of a step configuration for the lattice.
 int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_config* out, std::string* why)
 {
@@ -310,12 +407,11 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
         return AH_E_INVAL;
     }
     if (c.tile_x == 0 && c.tile_y == 0) {
-        // FP32: 128-wide rows halve the x-halo line fetches per site.  FP64:
-        // 32 x 8, as fast as 64 x 8 for the plain step, and its measured
-        // march, unlike that of 512-thread tiles, does not spill.  Two-step
-        // passes: 32 x 8 in both precisions
-        c.tile_x = c.kernel == AH_KERNEL_TILE2 ? 32 : (p.precision == AH_FP32 ? (p.N >= 128 ? 128 : 64) : 32);
+        // one step: the shape of the highest rate once its ragged edge is
+        // paid for; two-step passes: 32 x 8 in both precisions
+        c.tile_x = 32;
         c.tile_y = 8;
+        if (c.kernel == AH_KERNEL_TILE) (void)default_tile(p.precision, p.N, &c.tile_x, &c.tile_y);
     }
     if (c.kernel == AH_KERNEL_TILE2 ? !tile2_supported(p.precision, c.tile_x, c.tile_y)
                                     : !tile_supported(p.precision, c.tile_x, c.tile_y)) {
@@ -326,18 +422,7 @@ int resolve_step_config(const ah_params& p, const ah_step_config& in, ah_step_co
         *why = "zchunk must be 0 (automatic) or at least 2 (N <= 128) or 8 (N > 128)";
         return AH_E_INVAL;
     }
-    if (c.zchunk == 0) {
-        // enough workgroups to cover the chip: about 1024 of 512 threads, or
-        // one resident round (256) of 1024-thread workgroups, whose z-chunks
-        // are then as long as possible; small lattices go down to the
-        // shortest chunk they allow
-        const int64_t per_chunk = (int64_t)((p.N + c.tile_x - 1) / c.tile_x) * ((p.N + c.tile_y - 1) / c.tile_y);
-        const int64_t target = (c.kernel == AH_KERNEL_TILE && c.tile_x * c.tile_y >= 1024) ? 256 : 1024;
-        int64_t zc = (int64_t)p.N * per_chunk / target;
-        if (zc < min_zchunk(p.N)) zc = min_zchunk(p.N);
-        if (zc > p.N) zc = p.N;
-        c.zchunk = (int32_t)zc;
-    }
+    if (c.zchunk == 0) c.zchunk = auto_zchunk(c.kernel, p.precision, p.N, c.tile_x, c.tile_y, false);
     if (c.zchunk > p.N) c.zchunk = p.N;
     *out = c;
     return AH_OK;
@@ -417,28 +502,10 @@ MeasConst meas_const(const ah_params& p, int64_t n)
     return mc;
 }
 
-// Tile configuration used for the diagnostics of a compact-action handle:
-// the step's own when the step is tiled, the default tile otherwise.
-// Tile of the measured march.  Any tile shape computes the same fields bit
-// for bit, so the measured step may use another shape than the plain one
-// (measured_tile: FP32 64 x 8, FP64 32 x 8), with the automatic z-chunk of
-// that shape when it differs from the step's.  The site kernel's lattices (and
-// ah_measure on them) use the automatic tile configuration.
+// Tiling of the measured march (diagnostics of a compact-action handle).
 TileConfig meas_tiles(const ah_handle* h)
 {
-    ah_step_config d;
-    std::string why;
-    if (h->cfg.kernel == AH_KERNEL_TILE || h->cfg.kernel == AH_KERNEL_TILE2) {
-        int tx = h->cfg.tile_x, ty = h->cfg.tile_y;
-        if (!measured_tile(h->p.precision, &tx, &ty)) return TileConfig{tx, ty, h->cfg.zchunk};
-        (void)resolve_step_config(h->p, ah_step_config{AH_KERNEL_TILE, tx, ty, 0}, &d, &why);
-        return TileConfig{d.tile_x, d.tile_y, d.zchunk};
-    }
-    (void)resolve_step_config(h->p, ah_step_config{AH_KERNEL_TILE, 0, 0, 0}, &d, &why);
-    int tx = d.tile_x, ty = d.tile_y;
-    if (measured_tile(h->p.precision, &tx, &ty))
-        (void)resolve_step_config(h->p, ah_step_config{AH_KERNEL_TILE, tx, ty, 0}, &d, &why);
-    return TileConfig{d.tile_x, d.tile_y, d.zchunk};
+    return measured_tiling(h->p, h->cfg);
 }
 
 // Diagnostics of the current snapshot folded into dst[M_COUNT] (device), and

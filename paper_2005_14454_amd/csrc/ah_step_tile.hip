@@ -773,13 +773,16 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(con
     a.deta = (R)L.deta;
     a = uniform(a);
     const MeasArgs ma = uniform(MeasArgs{L.dx, row[C_INV2E2F], row[C_LAMQ], row[C_GAUSS]});
+    // the measured node runs the lattice's measured tiling, the plain node its step tiling
+    const int tiles_x = MEAS ? L.mtiles_x : L.tiles_x, tiles_y = MEAS ? L.mtiles_y : L.tiles_y;
+    const int zchunk = MEAS ? L.meas_zchunk : L.zchunk;
     int t = it.tile;
-    const int tx = t % L.tiles_x;
-    t /= L.tiles_x;
-    const int ty = t % L.tiles_y;
-    const int tz = t / L.tiles_y;
-    const int z0 = uniform(tz * L.zchunk);
-    const int z1 = uniform((z0 + L.zchunk < L.N) ? z0 + L.zchunk : L.N);
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int ty = t % tiles_y;
+    const int tz = t / tiles_y;
+    const int z0 = uniform(tz * zchunk);
+    const int z1 = uniform((z0 + zchunk < L.N) ? z0 + zchunk : L.N);
     const int x0 = uniform(tx * TX), y0 = uniform(ty * TY);
     if constexpr (MEAS)
         march_step<R, TX, TY, true>(sh, &mxs, a, ma, uniform(L.partials + (int64_t)it.tile * kMeasStride),
@@ -849,7 +852,9 @@ __global__ void __launch_bounds__(256) k_gauss(Fields<R> f, int N, int P, double
     gauss_block<R>(f, N, P, inv_dx, gc, blockIdx.x, gridDim.x, partials + (int64_t)blockIdx.x * kMeasStride, red);
 }
 
-// Gauss residual of every pool lattice whose snapshot is due, before it is stepped.
+// Gauss residual of every pool lattice whose snapshot is due, before it is
+// stepped.  An item is kGaussPerItem consecutive blocks of the lattice's
+// pass (records as the single-lattice pass writes them).
 template <typename R>
 __global__ void __launch_bounds__(256) k_gauss_batch(const PoolLattice* __restrict__ lat,
                                                      const WorkItem* __restrict__ work, int nwork)
@@ -857,6 +862,7 @@ __global__ void __launch_bounds__(256) k_gauss_batch(const PoolLattice* __restri
     __shared__ double red[16];
     for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
         const WorkItem it = work[w];
+        if (it.lattice < 0) continue;  // an empty item
         const PoolLattice& L = lat[it.lattice];
         const int64_t k = *L.counter;
         if (!measure_due(L, k)) continue;
@@ -864,8 +870,10 @@ __global__ void __launch_bounds__(256) k_gauss_batch(const PoolLattice* __restri
         const Fields<R> f{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[0], (R*)L.mom[1], (R*)L.pp[cur][2],
                           (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[2], (R*)L.mom[3], (R*)L.mom[4]};
         const double* row = L.coef + k * kCoefStride;
-        gauss_block<R>(f, L.N, L.P, 1.0 / L.dx, row[C_GAUSS], it.tile, L.gauss_blocks,
-                       L.partials + (int64_t)(L.meas_blocks + it.tile) * kMeasStride, red);
+        const int b1 = min(it.tile + kGaussPerItem, L.gauss_blocks);
+        for (int b = it.tile; b < b1; ++b)
+            gauss_block<R>(f, L.N, L.P, 1.0 / L.dx, row[C_GAUSS], b, L.gauss_blocks,
+                           L.partials + (int64_t)(L.meas_blocks + b) * kMeasStride, red);
     }
 }
 
@@ -967,24 +975,31 @@ template <typename R>
 hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,
                              bool measured, hipStream_t s)
 {
-    // a pool tile shape serves both nodes, so only shapes with a measured
-    // instance are built
-#define AH_BATCH_CASE(TXv, TYv)                                                                                      \
-    if constexpr (has_measured<R>(TXv, TYv)) {                                                                       \
-        if (tx == TXv && ty == TYv) {                                                                                \
-            if (measured)                                                                                            \
-                hipLaunchKernelGGL((k_step_batch<R, TXv, TYv, true>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work,  \
-                                   nwork);                                                                           \
-            else                                                                                                     \
-                hipLaunchKernelGGL((k_step_batch<R, TXv, TYv, false>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work, \
-                                   nwork);                                                                           \
-            return hipGetLastError();                                                                                \
-        }                                                                                                            \
+    // plain node: the shapes of batch_tile_supported; measured node: the
+    // measured march's shape (measured_tile)
+    if (measured) {
+        int mx = 0, my = 0;
+        (void)measured_tile(sizeof(R) == 8 ? AH_FP64 : AH_FP32, &mx, &my);
+        if (tx != mx || ty != my) return hipErrorInvalidValue;
+        if constexpr (sizeof(R) == 8)
+            hipLaunchKernelGGL((k_step_batch<R, 32, 8, true>), dim3(grid), dim3(256), 0, s, lat, work, nwork);
+        else
+            hipLaunchKernelGGL((k_step_batch<R, 64, 8, true>), dim3(grid), dim3(512), 0, s, lat, work, nwork);
+        return hipGetLastError();
+    }
+    if (!batch_tile_supported(sizeof(R) == 8 ? AH_FP64 : AH_FP32, tx, ty)) return hipErrorInvalidValue;
+#define AH_BATCH_CASE(TXv, TYv)                                                                                   \
+    if (tx == TXv && ty == TYv) {                                                                                 \
+        hipLaunchKernelGGL((k_step_batch<R, TXv, TYv, false>), dim3(grid), dim3(TXv * TYv), 0, s, lat, work, nwork); \
+        return hipGetLastError();                                                                                 \
     }
     AH_BATCH_CASE(64, 8)
     AH_BATCH_CASE(64, 4)
     AH_BATCH_CASE(32, 8)
-    AH_BATCH_CASE(128, 4)
+    if constexpr (sizeof(R) == 4) {
+        AH_BATCH_CASE(128, 4)
+        AH_BATCH_CASE(128, 8)
+    }
 #undef AH_BATCH_CASE
     return hipErrorInvalidValue;
 }
