@@ -6,6 +6,7 @@
 #include "ah.h"
 #include "ah_internal.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -72,9 +73,12 @@ int ah_autotune(const ah_params* p, int32_t steps, ah_step_config* best, double*
             shapes.push_back({AH_KERNEL_TILE, 128, 8});
             shapes.push_back({AH_KERNEL_TILE2, 64, 8});
         }
-        std::vector<int> zcs = {0, p->N};
-        for (int div : {2, 4, 8, 16, 32})
-            if (p->N / div >= ah::min_zchunk(p->N)) zcs.push_back(p->N / div);
+        // the automatic z-chunk and equal chunks of 1 .. 32 per column
+        std::vector<int> zcs = {0};
+        for (int nz : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32}) {
+            const int zc = (p->N + nz - 1) / nz;
+            if (zc >= ah::min_zchunk(p->N) && std::find(zcs.begin(), zcs.end(), zc) == zcs.end()) zcs.push_back(zc);
+        }
         ah_step_config bcfg{};
         double bms = 1e300;
         for (auto& t : shapes) {

@@ -1,8 +1,9 @@
 """Summaries of rocprofv3 output for the profiles the repository keeps.
 
     python -m paper_2005_14454_amd.profile_summary trace DIR [--note TEXT]
-        per kernel (name and workgroup size): calls, mean, min and max duration
-        from the kernel trace (rocprofv3 --kernel-trace --output-format csv -d DIR)
+        per kernel and launch geometry (workgroup and grid size): calls, mean,
+        min and max duration from the kernel trace (rocprofv3 --kernel-trace
+        --output-format csv -d DIR)
 
     python -m paper_2005_14454_amd.profile_summary traffic FETCH_DIR WRITE_DIR [--N 512]
         HBM bytes per dispatch from two counter passes (--pmc FETCH_SIZE, then
@@ -78,6 +79,18 @@ def busy_fraction(intervals):
     return busy / span if span else 0.0, span / 1e9
 
 
+def idle_gaps(intervals, min_s):
+    """(start offset in s, length in s) of every stretch of at least min_s
+    seconds between kernels (no kernel running), in time order."""
+    iv = sorted(intervals)
+    out, end = [], iv[0][1] if iv else 0
+    for s, e in iv[1:]:
+        if s - end >= min_s * 1e9:
+            out.append(((end - iv[0][0]) / 1e9, (s - end) / 1e9))
+        end = max(end, e)
+    return out
+
+
 def trace(directory, note="", window=None):
     """Per-kernel statistics; window = a kernel name: the busy fraction is
     also given from its first to its last launch."""
@@ -86,14 +99,22 @@ def trace(directory, note="", window=None):
     for r in _rows(directory, "kernel_trace.csv"):
         name = short_name(_col(r, "Kernel_Name", "Kernel-Name"))
         wg = _col(r, "Workgroup_Size", "Workgroup_Size_X", "Workgroup-Size")
+        grid = _col(r, "Grid_Size", "Grid_Size_X", "Grid-Size")
         t0, t1 = int(_col(r, "Start_Timestamp")), int(_col(r, "End_Timestamp"))
-        per[(name, int(wg))].append((t1 - t0) / 1e6)
+        per[(name, int(wg), int(grid))].append((t1 - t0) / 1e6)
         spans.append((t0, t1, name))
     lines = [f"rocprofv3 kernel trace summary of {directory}"]
     if note:
         lines.append(note)
     frac, span_s = busy_fraction([(a, b) for a, b, _ in spans])
     lines.append(f"GPU busy (union of kernel intervals) {frac:.3f} of {span_s:.2f} s from the first kernel to the last")
+    long_gaps = idle_gaps([(a, b) for a, b, _ in spans], 0.1)
+    if long_gaps:
+        gap_s = sum(g for _, g in long_gaps)
+        lines.append(f"idle gaps of 0.1 s or more: {len(long_gaps)}, {gap_s:.2f} s in all (at "
+                     + ", ".join(f"{t:.2f} s: {g:.2f} s" for t, g in long_gaps[:8])
+                     + (", ..." if len(long_gaps) > 8 else "") + ")")
+        lines.append(f"GPU busy outside those gaps {frac * span_s / (span_s - gap_s):.3f} of {span_s - gap_s:.2f} s")
     if window:
         w = [(a, b) for a, b, n in spans if window in n]
         if w:
@@ -103,9 +124,10 @@ def trace(directory, note="", window=None):
     for k, h in source_hashes().items():
         lines.append(f"{k} sources sha256[:16] = {h}")
     lines.append("")
-    lines.append(f"{'kernel':<48} {'wg':>5} {'calls':>6} {'avg_ms':>9} {'min_ms':>9} {'max_ms':>9}")
-    for (name, wg), d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
-        lines.append(f"{name[:48]:<48} {wg:>5} {len(d):>6} {statistics.mean(d):>9.4f} {min(d):>9.4f} {max(d):>9.4f}")
+    lines.append(f"{'kernel':<48} {'wg':>5} {'threads':>10} {'calls':>6} {'avg_ms':>9} {'min_ms':>9} {'max_ms':>9}")
+    for (name, wg, grid), d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{name[:48]:<48} {wg:>5} {grid:>10} {len(d):>6} {statistics.mean(d):>9.4f} {min(d):>9.4f} "
+                     f"{max(d):>9.4f}")
     return "\n".join(lines)
 
 

@@ -91,6 +91,7 @@ def run_stream(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 1, log=
     by_pool = {}
     done = 0
     site_updates = 0
+    empty = 0.0  # seconds with no request resident or waiting (the next one has not arrived)
     t0 = time.perf_counter()
     try:
         while done < len(reqs):
@@ -120,7 +121,9 @@ def run_stream(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 1, log=
                     if log:
                         log(f"done {r.rid} N={r.params.N} {r.params.precision} ttc={r.done - r.arrival:.3f}s")
             elif future:
-                time.sleep(max(0.0, min(0.05, future[0].arrival - (time.perf_counter() - t0))))
+                ts = time.perf_counter()
+                time.sleep(max(0.0, min(0.05, future[0].arrival - (ts - t0))))
+                empty += time.perf_counter() - ts
             elif waiting:
                 raise RuntimeError("a waiting request can never be admitted (budget too small)")
         wall = time.perf_counter() - t0
@@ -144,6 +147,7 @@ def run_stream(reqs, hbm_budget: int, max_slots: int = 256, chunk: int = 1, log=
     return {
         "requests": len(reqs),
         "wall_s": wall,
+        "empty_s": empty,
         "site_updates": site_updates,
         "throughput_su_per_s": site_updates / wall,
         "ttc_p50_s": float(np.percentile(ttc, 50)),

@@ -17,19 +17,24 @@ def _write(path, header, rows):
 def test_trace_statistics_and_busy_fraction(tmp_path):
     d = tmp_path / "trace"
     rows = [
-        ('"void ah::(anonymous namespace)::k_step2_tile<float, 64, 8>(x)"', 704, 0, 4_000_000),
-        ('"void ah::(anonymous namespace)::k_step2_tile<float, 64, 8>(x)"', 704, 4_000_000, 8_000_000),
-        ('"k_gauss<float>(y)"', 256, 9_000_000, 10_000_000),
+        ('"void ah::(anonymous namespace)::k_step2_tile<float, 64, 8>(x)"', 704, 720896, 0, 4_000_000),
+        ('"void ah::(anonymous namespace)::k_step2_tile<float, 64, 8>(x)"', 704, 720896, 4_000_000, 8_000_000),
+        ('"void ah::(anonymous namespace)::k_step2_tile<float, 64, 8>(x)"', 704, 1408, 8_000_000, 8_500_000),
+        ('"k_gauss<float>(y)"', 256, 262144, 9_000_000, 10_000_000),
     ]
     _write(str(d / "host" / "123" / "run_kernel_trace.csv"),
-           ["Kernel_Name", "Workgroup_Size", "Start_Timestamp", "End_Timestamp"], rows)
+           ["Kernel_Name", "Workgroup_Size", "Grid_Size", "Start_Timestamp", "End_Timestamp"], rows)
     text = ps.trace(str(d), "note", window="k_step2_tile")
     assert "k_step2_tile<float, 64, 8>" in text and "k_gauss<float>" in text
-    line = [l for l in text.splitlines() if l.startswith("k_step2_tile")][0].split()
-    assert line[-4:] == ["2", "4.0000", "4.0000", "4.0000"]
-    assert "GPU busy (union of kernel intervals) 0.900 of 0.01 s" in text
+    # one row per launch geometry: the two large launches, then the small one
+    lines = [l.split() for l in text.splitlines() if l.startswith("k_step2_tile")]
+    assert lines[0][-5:] == ["720896", "2", "4.0000", "4.0000", "4.0000"]
+    assert lines[1][-5:] == ["1408", "1", "0.5000", "0.5000", "0.5000"]
+    assert "GPU busy (union of kernel intervals) 0.950 of 0.01 s" in text
     assert "GPU busy between the first and last k_step2_tile: 1.000" in text
     assert ps.busy_fraction([(0, 10), (5, 20), (30, 40)])[0] == 0.75
+    # stretches with no kernel: only those of at least the given length
+    assert ps.idle_gaps([(0, 10), (5, 20), (30, 40), (2_000_000_040, 2_000_000_050)], 1.0) == [(40e-9, 2.0)]
 
 
 def test_traffic_is_scaled_by_the_copy(tmp_path):
