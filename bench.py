@@ -103,16 +103,25 @@ def run_gpu(precision, N, steps, warmup, measure_every, seed, m=1.0):
     lat.step(warmup)
     lat.measure()
     torch.cuda.synchronize()
-    lat.set_timing(True)
+    # The timed job with an event pair around every launch (the kernel times
+    # come from them).  On a lattice of N <= 128, whose launches take tens of
+    # microseconds, the two event records per launch would add to the job's
+    # time: there the job is timed without them and the same number of steps
+    # is then run again with them, for the kernel times.
+    split = N <= 128
+    lat.set_timing(not split)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     meas = lat.step_measured(steps, measure_every)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    last = meas[-1] if meas else lat.measure()
+    if split:
+        lat.set_timing(True)
+        lat.step_measured(steps, measure_every)
     kern_ms, launches = lat.get_timing()
     meas_ms, meas_launches = lat.get_timing_split()
     lat.set_timing(False)
-    last = meas[-1] if meas else lat.measure()
     lat.close()
     del lat
     torch.cuda.empty_cache()

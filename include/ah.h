@@ -210,8 +210,9 @@ int ah_get_winding(ah_handle* h, int8_t* host_w);
                            * steps follow each other: the step n -> n+1 is formed on the tile plus a
                            * one-site ring and kept in LDS, the step n+1 -> n+2 on the tile from it, so
                            * the fields are read and written once per two steps.  Bitwise equal to two
-                           * single steps.  Tiles (32,8), (64,4), FP32 also (64,8); the single steps it
-                           * leaves (an odd count, diagnostics) run the tiled kernel on the same tile */
+                           * single steps.  Tiles (32,8), (64,4), FP32 also (64,8); a single plain step
+                           * it leaves (an odd count) runs the tiled kernel on its default tiling, the
+                           * measured steps on the measured march's tiling */
 
 /* Performance knobs of the step; they do not change the equations.  The
  * tiled kernel gives bitwise-identical results for every tile shape and

@@ -231,7 +231,17 @@ hipError_t launch_step2_tile(const Fields<R>& in, const Fields<R>& out, const La
 // workgroups (= diagnostics records) of one tiled launch
 int step_tile_blocks(int N, const TileConfig& tc);
 
-// Gauss-residual pass: gauss_blocks(N) records (Gauss slots only) into partials
+// Gauss-residual pass: 64 x 4 (x, y) tiles marching z-chunks of
+// gauss_zchunk(N) planes, one workgroup of 256 threads and one record (Gauss
+// slots only) per (tile, chunk): gauss_blocks(N) of them.  The chunks are as
+// long as 2048 workgroups allow, from 1 plane (small lattices, which then
+// still have enough workgroups) to 64.
+__host__ __device__ inline int gauss_zchunk(int N)
+{
+    const int64_t tiles = (int64_t)((N + 63) / 64) * ((N + 3) / 4);
+    int64_t zc = (int64_t)N * tiles / 2048;
+    return (int)(zc < 1 ? 1 : (zc > 64 ? 64 : zc));
+}
 int gauss_blocks(int N);
 template <typename R>
 hipError_t launch_gauss(const Fields<R>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s);

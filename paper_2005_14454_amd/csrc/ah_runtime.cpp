@@ -595,7 +595,13 @@ hipError_t do_step(ah_handle* h)
     hipError_t e = t.begin();
     if (e != hipSuccess) return e;
     if (h->cfg.kernel == AH_KERNEL_TILE || h->cfg.kernel == AH_KERNEL_TILE2) {
-        const TileConfig tc{h->cfg.tile_x, h->cfg.tile_y, h->cfg.zchunk};
+        TileConfig tc{h->cfg.tile_x, h->cfg.tile_y, h->cfg.zchunk};
+        if (h->cfg.kernel == AH_KERNEL_TILE2) {
+            // a single step between two-step passes runs the default one-step
+            // tiling (every tiling gives the same fields)
+            if (default_tile(h->p.precision, h->p.N, &tc.tx, &tc.ty))
+                tc.zchunk = auto_zchunk(AH_KERNEL_TILE, h->p.precision, h->p.N, tc.tx, tc.ty, false);
+        }
         e = launch_step_tile<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, tc, nullptr, nullptr,
                                 true, h->stream);
     } else {

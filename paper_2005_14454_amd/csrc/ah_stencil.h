@@ -18,6 +18,21 @@ namespace ah {
 namespace {
 
 __device__ inline float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// A block-uniform value moved into scalar registers.  What a kernel loads
+// from a descriptor or a coefficient row in memory, or converts from it, the
+// compiler keeps in vector registers (one copy per lane), which would cost a
+// march a wave per SIMD of occupancy.
+template <typename T>
+__device__ inline T uniform(T v)
+{
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+    for (unsigned k = 0; k < sizeof(T) / 4; ++k) w[k] = __builtin_amdgcn_readfirstlane(w[k]);
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
 __device__ inline double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Streaming accesses: Pi and E are read and written once per step at their

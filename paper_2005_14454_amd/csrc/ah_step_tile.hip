@@ -719,20 +719,6 @@ __device__ inline bool measure_due(const PoolLattice& L, int64_t k)
 // run its steps.  MEAS: only lattices whose snapshot k is due for diagnostics
 // (measured step, or measurement alone for the final snapshot); otherwise
 // only lattices that are not due.
-// A block-uniform value moved into scalar registers.  The pool kernel reads
-// its lattice descriptor from memory, and the compiler keeps what it loads
-// from there in vector registers (one copy per lane), which would cost the
-// plain march a wave per SIMD of occupancy.
-template <typename T>
-__device__ inline T uniform(T v)
-{
-    static_assert(sizeof(T) % 4 == 0, "32-bit words");
-    int w[sizeof(T) / 4];
-    __builtin_memcpy(w, &v, sizeof(T));
-    for (unsigned k = 0; k < sizeof(T) / 4; ++k) w[k] = __builtin_amdgcn_readfirstlane(w[k]);
-    __builtin_memcpy(&v, w, sizeof(T));
-    return v;
-}
 
 template <typename R, int TX, int TY, bool MEAS>
 __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(const PoolLattice* __restrict__ lat,
@@ -796,34 +782,45 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(con
 
 // Discrete Gauss law of the snapshot: G^x = sum_i (E_i^x - E_i^{x-i})/dx
 // - c Im[conj(phi^x) Pi^x] on the stored half-step fields, in FP64 from the
-// exactly widened stored values.  Each workgroup walks a fixed grid-stride
-// set of sites of the lattice and writes one record (Gauss slots only).
-// Sites are taken in dense order s = x + N (y + N z), each at its stored
-// offset x + P (y + N z).
+// exactly widened stored values.  A workgroup of 256 threads owns a
+// kGaussTX x kGaussTY (x, y) tile and marches a chunk of gauss_zchunk(N)
+// planes of it (block = tile + tiles * chunk), carrying E_z of the plane
+// below in a register, so every field is read from memory once; it writes
+// one record (Gauss slots only).
+constexpr int kGaussTX = 64, kGaussTY = 4;
+static_assert(kGaussTX * kGaussTY == 256, "one site of a plane per thread");
+
 template <typename R>
-__device__ void gauss_block(const Fields<R>& f, int N, int P, double inv_dx, double gc, int block, int nblocks,
+__device__ void gauss_block(const Fields<R>& f, int N, int P, double inv_dx, double gc, int block,
                             double* __restrict__ record, double* red)
 {
-    const int64_t V = (int64_t)N * N * N;
-    const int64_t NN = (int64_t)N * N, NP = (int64_t)N * P;
+    const int tiles_x = (N + kGaussTX - 1) / kGaussTX, tiles_y = (N + kGaussTY - 1) / kGaussTY;
+    const int zc = gauss_zchunk(N);
+    const int t = block % (tiles_x * tiles_y), c = block / (tiles_x * tiles_y);
+    const int x = (t % tiles_x) * kGaussTX + (int)(threadIdx.x % kGaussTX);
+    const int y = (t / tiles_x) * kGaussTY + (int)(threadIdx.x / kGaussTX);
+    const int z0 = c * zc, z1 = min(z0 + zc, N);
     double g2 = 0.0, d2 = 0.0, c2 = 0.0, gmax = 0.0;
-    for (int64_t s = (int64_t)block * 256 + threadIdx.x; s < V; s += (int64_t)nblocks * 256) {
-        const int64_t row = s / N;  // y + N z
-        const int x = (int)(s - row * N);
-        const int z = (int)(row / N), y = (int)(row - (int64_t)z * N);
-        const int64_t o = x + row * P;
-        const int64_t sxm = o + (x == 0 ? N - 1 : -1);
-        const int64_t sym = o + (y == 0 ? NP - P : -(int64_t)P);
-        const int64_t szm = z > 0 ? o - NP : o + (NN - N) * P;
-        const double dv = (((double)f.e0[o] - (double)f.e0[sxm]) * inv_dx +
-                           ((double)f.e1[o] - (double)f.e1[sym]) * inv_dx) +
-                          ((double)f.e2[o] - (double)f.e2[szm]) * inv_dx;
-        const double crho = gc * ((double)f.phr[o] * (double)f.pii[o] - (double)f.phi[o] * (double)f.pir[o]);
-        const double G = dv - crho;
-        g2 += G * G;
-        d2 += dv * dv;
-        c2 += crho * crho;
-        gmax = fmax(gmax, fabs(G));
+    if (x < N && y < N) {
+        const int64_t NP = (int64_t)N * P;
+        const int64_t xy = x + (int64_t)y * P;
+        const int64_t dxm = x == 0 ? N - 1 : -1;                      // to x - kx
+        const int64_t dym = y == 0 ? (int64_t)(N - 1) * P : -(int64_t)P;  // to x - ky
+        int64_t o = xy + (int64_t)z0 * NP;
+        double ezm = (double)f.e2[xy + (int64_t)(z0 == 0 ? N - 1 : z0 - 1) * NP];  // E_z below
+        for (int z = z0; z < z1; ++z, o += NP) {
+            const double ez = (double)f.e2[o];
+            const double dv = (((double)f.e0[o] - (double)f.e0[o + dxm]) * inv_dx +
+                               ((double)f.e1[o] - (double)f.e1[o + dym]) * inv_dx) +
+                              (ez - ezm) * inv_dx;
+            const double crho = gc * ((double)f.phr[o] * (double)f.pii[o] - (double)f.phi[o] * (double)f.pir[o]);
+            const double G = dv - crho;
+            g2 += G * G;
+            d2 += dv * dv;
+            c2 += crho * crho;
+            gmax = fmax(gmax, fabs(G));
+            ezm = ez;
+        }
     }
     // fixed-order block reduction
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -849,7 +846,7 @@ __global__ void __launch_bounds__(256) k_gauss(Fields<R> f, int N, int P, double
                                                double* partials)
 {
     __shared__ double red[16];
-    gauss_block<R>(f, N, P, inv_dx, gc, blockIdx.x, gridDim.x, partials + (int64_t)blockIdx.x * kMeasStride, red);
+    gauss_block<R>(f, N, P, inv_dx, gc, blockIdx.x, partials + (int64_t)blockIdx.x * kMeasStride, red);
 }
 
 // Gauss residual of every pool lattice whose snapshot is due, before it is
@@ -872,7 +869,7 @@ __global__ void __launch_bounds__(256) k_gauss_batch(const PoolLattice* __restri
         const double* row = L.coef + k * kCoefStride;
         const int b1 = min(it.tile + kGaussPerItem, L.gauss_blocks);
         for (int b = it.tile; b < b1; ++b)
-            gauss_block<R>(f, L.N, L.P, 1.0 / L.dx, row[C_GAUSS], b, L.gauss_blocks,
+            gauss_block<R>(f, L.N, L.P, 1.0 / L.dx, row[C_GAUSS], b,
                            L.partials + (int64_t)(L.meas_blocks + b) * kMeasStride, red);
     }
 }
@@ -1004,14 +1001,11 @@ hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int n
     return hipErrorInvalidValue;
 }
 
-// One site per thread up to 1024 workgroups of 256 (a grid-stride loop
-// beyond): small lattices get their Gauss pass in one short wave of blocks.
 int gauss_blocks(int N)
 {
-    const int64_t V = (int64_t)N * N * N;
-    int64_t nb = (V + 255) / 256;
-    if (nb > 1024) nb = 1024;
-    return (int)(nb < 1 ? 1 : nb);
+    const int64_t tiles = (int64_t)((N + 63) / 64) * ((N + 3) / 4);
+    const int zc = gauss_zchunk(N);
+    return (int)(tiles * ((N + zc - 1) / zc));
 }
 
 template <typename R>

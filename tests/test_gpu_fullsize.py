@@ -57,7 +57,7 @@ def test_fullsize_one_step_sampled(oracle_mod, bench_tiling, precision, tol):
     want = ah.tune_lookup(gp)
     with ah.Lattice(gp) as lat:
         cfg = lat.get_step_config()
-        assert (cfg["tile"], cfg["zchunk"]) == (want["tile"], want["zchunk"]), (cfg, want)
+        assert (cfg["kernel"], cfg["tile"], cfg["zchunk"]) == (want["kernel"], want["tile"], want["zchunk"]), (cfg, want)
         lat.init(1)
         lat.step(5)
         before = lat.get_state()
@@ -67,7 +67,6 @@ def test_fullsize_one_step_sampled(oracle_mod, bench_tiling, precision, tol):
         cfg = lat.get_step_config()
         w_sites = sample_sites(N, 3000, seed=17)
         w_gpu = lat.winding()[:, w_sites].T
-    assert cfg["kernel"] == "tile"
     sites = np.unique(np.concatenate([sample_sites(N, 4000, seed=5), _boundary_sites(N)]))
     ref = oracle_mod.step_sites(op, before, 5, sites)
     got = after[:, sites]
