@@ -288,11 +288,14 @@ int ah_tune_load(const char* path);
  * graph holding the diagnostics pass of the lattices whose snapshot is due,
  * the measured step of those lattices and its fixed-order fold, the plain
  * step of every other active lattice (one kernel node per precision and
- * tile shape, one block per (lattice, tile) work item) and a counter update.
- * Pool lattices run the tuned one-step (else the default) tile shape with
- * z-chunks of at least 16 planes (ah_pool_step_config reports them), and
- * their measured steps the measured march's tiling, as a lattice alone
- * does.  Every lattice takes the coefficients of its own step from its own
+ * tile shape, one block per (lattice, tile) work item) and a counter update;
+ * an FP32 lattice whose next two snapshots are both not due takes a
+ * two-step pass instead (AH_KERNEL_TILE2; 64 x 8 unless its tuning entry
+ * names another two-step shape), which advances it by two steps in that
+ * replay.  Pool lattices run the tuned one-step (else the default) tile
+ * shape with z-chunks of at least 16 planes (ah_pool_step_config reports
+ * them), and their measured steps the measured march's tiling, as a lattice
+ * alone does.  Every lattice takes the coefficients of its own step from its own
  * FP64 table, so its fields and diagnostics are bitwise identical to the
  * same lattice run alone through ah_step / ah_measure with the same tiling.
  * Requests enter and leave between advances (continuous batching); the
@@ -316,8 +319,10 @@ typedef struct ah_pool_info {
  * pool creates its own stream (graph capture needs a non-null stream). */
 int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_pool** out);
 
-/* Device bytes a request occupies in a pool: 15 N^3 reals of fields,
- * diagnostics records, the (nsteps+1)-row coefficient table, the series. */
+/* Device bytes a request occupies in a pool: fields (15 arrays of N^2 rows
+ * of the pitched length; 20 for FP32, whose Pi and E are double-buffered for
+ * its two-step passes), diagnostics records, the (nsteps+1)-row coefficient
+ * table, the series. */
 int ah_pool_footprint(const ah_params* p, int64_t nsteps, int32_t measure_every, size_t* bytes);
 
 /* Admit a lattice: random-phase IC from `seed` (as ah_init), `nsteps` steps,

@@ -169,10 +169,11 @@ enum CoefSlot { C_P1 = 0, C_P2, C_E1, C_E2, C_LAMH, C_KAPPA, C_INV2E2F, C_LAMQ, 
 
 // Device-resident descriptor of one pool lattice (plain data; uploaded by the host).
 struct PoolLattice {
-    void* pp[2][5];        // ping-pong phi_re, phi_im, A0, A1, A2; buffer (step & 1) is current
-    void* mom[5];          // Pi_re, Pi_im, E0, E1, E2 (updated in place)
+    void* pp[2][5];        // ping-pong phi_re, phi_im, A0, A1, A2; counter[2] names the current one
+    void* mom[2][5];       // Pi_re, Pi_im, E0, E1, E2; counter[3] names the current one (updated in place by a
+                           // single step; a two-step pass writes the other); mom[1] only with two-step passes
     const double* coef;    // (nsteps + 1) rows of kCoefStride doubles
-    int64_t* counter;      // counter[0]: local step k; counter[1]: measurements taken
+    int64_t* counter;      // kCounterWords words: local step k, measurements taken, phi/A buffer, Pi/E buffer
     double* partials;      // diagnostics records of this lattice
     double* series;        // measurement records: kSeriesStride doubles each
     int64_t nsteps;        // steps to run; the lattice is finished when counter[0] == nsteps + 1
@@ -181,13 +182,15 @@ struct PoolLattice {
     int meas_zchunk, meas_blocks, measure_every, precision;
     int gauss_blocks, P;     // Gauss records follow the meas_blocks step records; P: row pitch
     int mtiles_x, mtiles_y;  // tiling of the measured step (measured_tile), z-chunks of meas_zchunk
-    int compact, pad0;
+    int two_tiles_x, two_tiles_y, two_zchunk;  // tiling of the two-step pass; two_zchunk == 0: none
+    int compact;
     double dx, deta, sigma2;
 };
 struct WorkItem {
     int lattice, tile;  // lattice < 0: an empty item (padding)
 };
 constexpr int kXcdCount = 8;           // XCDs of the device; block b runs on XCD b % 8
+constexpr int kCounterWords = 4;       // int64 words of a pool lattice's counter
 constexpr int kGaussPerItem = 8;       // Gauss-pass blocks of one lattice per pool work item
 constexpr int kSeriesStride = 18;      // M_COUNT sums + step index + pad
 static_assert(M_COUNT + 1 <= kSeriesStride, "a series record holds the sums and the step index");
@@ -251,6 +254,10 @@ hipError_t launch_gauss_batch(const PoolLattice* lat, const WorkItem* work, int 
 template <typename R>
 hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,
                              bool measured, hipStream_t s);
+// the pool's two-step pass (ah_step2.hip): lattices whose step k takes one
+template <typename R>
+hipError_t launch_step2_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,
+                              hipStream_t s);
 
 template <typename R>
 hipError_t launch_measure(const Fields<R>& f, const LatticeConst& L, const StepCoef& c,

@@ -4,10 +4,11 @@
 //
 // Each lattice owns its fields, a per-step FP64 coefficient table, its
 // diagnostics records and its measurement series inside the arena, plus a
-// descriptor and a two-word counter (step, measurements taken) in pool
-// metadata.  The graph replayed per step is
-//     measure (lattices whose snapshot is due) -> fold -> step (one node per
-//     precision and tile shape) -> advance counters
+// descriptor and a counter (step, measurements taken, buffer parities) in
+// pool metadata.  The graph replayed per step is
+//     Gauss pass and measured step (lattices whose snapshot is due) -> fold
+//     -> single step and two-step pass (one node per precision and tile
+//     shape) -> advance counters
 // and every kernel reads the lattice's own counter, so the same graph serves
 // every step until the set of lattices changes.
 //
@@ -65,6 +66,7 @@ struct Slot {
     size_t off = 0, bytes = 0;
     ah_step_config cfg{};
     TileConfig meas{};  // tiling of the measured step
+    TileConfig two{};   // tiling of the two-step pass (zchunk 0: none)
     PoolLattice d{};
     bool reported = false;
 };
@@ -76,9 +78,11 @@ struct Footprint {
     int64_t series_cap;
 };
 
-// Bytes of one pool lattice; total = SIZE_MAX when nsteps is too large for
+// Bytes of one pool lattice (15 fields, 20 with two-step passes, whose Pi
+// and E are double-buffered); total = SIZE_MAX when nsteps is too large for
 // its coefficient table to be addressed at all.
-Footprint footprint(const ah_params& p, const ah_step_config& cfg, int64_t nsteps, int measure_every)
+Footprint footprint(const ah_params& p, const ah_step_config& cfg, const TileConfig& two, int64_t nsteps,
+                    int measure_every)
 {
     Footprint f{};
     if ((uint64_t)nsteps >= (SIZE_MAX / 4) / (kCoefStride * sizeof(double))) {
@@ -87,7 +91,7 @@ Footprint footprint(const ah_params& p, const ah_step_config& cfg, int64_t nstep
     }
     const size_t stored = (size_t)p.N * p.N * row_pitch(p.N, p.precision);
     f.field = align_up(stored * (p.precision == AH_FP64 ? 8 : 4));
-    f.fields = 15 * f.field;
+    f.fields = (two.zchunk > 0 ? 20 : 15) * f.field;
     f.meas = measured_tiling(p, cfg);
     f.meas_blocks = step_tile_blocks(p.N, f.meas);
     f.gauss_blocks = gauss_blocks(p.N);
@@ -119,7 +123,8 @@ struct Retired {
 };
 
 // A node group of the pool graph: kind 0 the Gauss pass of one precision,
-// kind 1 the step (plain and measured) of one precision and tile shape.
+// kind 1 the plain single step, kind 2 the measured step and kind 3 the
+// two-step pass of one precision and tile shape.
 struct GroupKey {
     int kind, precision, tx, ty;
     bool operator<(const GroupKey& o) const
@@ -297,8 +302,8 @@ hipError_t read_snapshots(ah_pool* P, bool wait)
         if (e != hipSuccess) return e;
         for (size_t i = 0; i < P->slots.size(); ++i)
             if (P->slots[i].used && P->slots[i].seq <= sn.seq) {
-                P->host_counters[2 * i] = sn.h[2 * i];
-                P->host_counters[2 * i + 1] = sn.h[2 * i + 1];
+                for (int w = 0; w < kCounterWords; ++w)
+                    P->host_counters[kCounterWords * i + w] = sn.h[kCounterWords * i + w];
             }
         P->launches_done = std::max(P->launches_done, sn.launches);
         P->snap_order.pop_front();
@@ -335,7 +340,7 @@ hipError_t queue_snapshot(ah_pool* P)
         if (!busy) break;
     }
     Snapshot& sn = P->snaps[j];
-    hipError_t e = hipMemcpyAsync(sn.h, P->d_counters, 2 * P->slots.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+    hipError_t e = hipMemcpyAsync(sn.h, P->d_counters, kCounterWords * P->slots.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
                                   P->stream);
     if (e == hipSuccess) e = hipEventRecord(sn.ev, P->stream);
     if (e != hipSuccess) return e;
@@ -378,7 +383,7 @@ int rebuild(ah_pool* P)
         } else {
             std::memset(&desc[i], 0, sizeof(PoolLattice));
             desc[i].nsteps = -1;
-            desc[i].counter = P->d_counters + 2 * i;
+            desc[i].counter = P->d_counters + kCounterWords * i;
         }
     }
     // the lists each group needs now: Gauss items per precision; step items
@@ -392,13 +397,15 @@ int rebuild(ah_pool* P)
         for (int t = 0; t < s.d.gauss_blocks; t += kGaussPerItem) g.push_back({i, t});
     }
     // step groups: kind 1 the plain step per (precision, tile shape), kind 2
-    // the measured step per (precision, measured tile shape)
+    // the measured step per (precision, measured tile shape), kind 3 the
+    // two-step pass per (precision, tile shape)
     std::map<GroupKey, std::vector<int>> by_shape;
     for (int i = 0; i < nslot; ++i) {
         const Slot& s = P->slots[i];
         if (!s.used) continue;
         by_shape[GroupKey{1, s.p.precision, s.cfg.tile_x, s.cfg.tile_y}].push_back(i);
         by_shape[GroupKey{2, s.p.precision, s.meas.tx, s.meas.ty}].push_back(i);
+        if (s.two.zchunk > 0) by_shape[GroupKey{3, s.p.precision, s.two.tx, s.two.ty}].push_back(i);
     }
     // The step kernels run one block per item and give XCD x (which runs
     // blocks x, x+8, ...) the x-th eighth of the list.  So that every XCD
@@ -407,8 +414,13 @@ int rebuild(ah_pool* P)
     // order, are cut into eight contiguous runs, run x goes to band x, bands
     // list the lattices with the longest z-marches first.
     for (auto& kv : by_shape) {
-        const bool meas = kv.first.kind == 2;
-        auto zc_of = [&](const PoolLattice& d) { return meas ? d.meas_zchunk : d.zchunk; };
+        const int kind = kv.first.kind;
+        auto zc_of = [&](const PoolLattice& d) {
+            return kind == 2 ? d.meas_zchunk : (kind == 3 ? d.two_zchunk : d.zchunk);
+        };
+        auto tiles_of = [&](const PoolLattice& d) {
+            return kind == 2 ? d.mtiles_x * d.mtiles_y : (kind == 3 ? d.two_tiles_x * d.two_tiles_y : d.tiles_x * d.tiles_y);
+        };
         std::vector<int> order = kv.second;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
             const PoolLattice &da = P->slots[a].d, &db = P->slots[b].d;
@@ -418,7 +430,7 @@ int rebuild(ah_pool* P)
         for (int i : order) {
             const PoolLattice& d = P->slots[i].d;
             const int tiles_z = (d.N + zc_of(d) - 1) / zc_of(d);
-            const int nt = (meas ? d.mtiles_x * d.mtiles_y : d.tiles_x * d.tiles_y) * tiles_z;
+            const int nt = tiles_of(d) * tiles_z;
             for (int x = 0; x < kXcdCount; ++x) {
                 const int t0 = (int)((int64_t)nt * x / kXcdCount), t1 = (int)((int64_t)nt * (x + 1) / kXcdCount);
                 for (int t = t0; t < t1; ++t) band[x].push_back({i, t});
@@ -522,6 +534,14 @@ int rebuild(ah_pool* P)
         }
         if (measured && le == hipSuccess) le = launch_fold_batch(P->d_lat, nslot, P->stream);
     }
+    for (auto& kv : P->groups) {
+        if (kv.first.kind != 3 || le != hipSuccess) continue;
+        const GroupKey& k = kv.first;
+        const NodeGroup& g = kv.second;
+        le = k.precision == AH_FP64
+                 ? launch_step2_batch<double>(P->d_lat, P->d_work + g.off, (int)g.cap, k.tx, k.ty, (int)g.cap, P->stream)
+                 : launch_step2_batch<float>(P->d_lat, P->d_work + g.off, (int)g.cap, k.tx, k.ty, (int)g.cap, P->stream);
+    }
     if (le == hipSuccess) le = launch_advance_batch(P->d_lat, nslot, P->stream);
     e = hipStreamEndCapture(P->stream, &P->graph);
     if (le != hipSuccess) return phip(P, le, "pool graph capture launch");
@@ -570,13 +590,13 @@ int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_po
         P->free_list.push_back({0, P->budget});
         P->slots.resize(max_slots);
         e = hipMalloc(&P->d_lat, max_slots * sizeof(PoolLattice));
-        if (e == hipSuccess) e = hipMalloc(&P->d_counters, 2 * max_slots * sizeof(int64_t));
-        if (e == hipSuccess) e = hipMemset(P->d_counters, 0, 2 * max_slots * sizeof(int64_t));
+        if (e == hipSuccess) e = hipMalloc(&P->d_counters, kCounterWords * max_slots * sizeof(int64_t));
+        if (e == hipSuccess) e = hipMemset(P->d_counters, 0, kCounterWords * max_slots * sizeof(int64_t));
         if (e == hipSuccess) e = hipHostMalloc((void**)&P->stage, kStageBytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking);
         P->snaps.resize(kSnapshots);
         for (int j = 0; j < kSnapshots && e == hipSuccess; ++j) {
-            e = hipHostMalloc((void**)&P->snaps[j].h, 2 * max_slots * sizeof(int64_t), hipHostMallocDefault);
+            e = hipHostMalloc((void**)&P->snaps[j].h, kCounterWords * max_slots * sizeof(int64_t), hipHostMallocDefault);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&P->snaps[j].ev, hipEventDisableTiming);
         }
         if (e != hipSuccess) {
@@ -584,7 +604,7 @@ int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_po
             (void)ah_pool_destroy(P);
             return AH_E_NOMEM;
         }
-        P->host_counters.assign(2 * (size_t)max_slots, 0);
+        P->host_counters.assign(kCounterWords * (size_t)max_slots, 0);
         *out = P;
         return AH_OK;
     });
@@ -594,25 +614,37 @@ int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_po
 // the pool's step is built for its shape (a two-step entry lends its tile
 // shape, with the automatic z-chunk), else the default, as for a lattice run
 // alone; z-chunks of at least 16 planes.  The measured node runs the
-// measured march's tiling (measured_tiling), as a lattice alone does.
+// measured march's tiling (measured_tiling), as a lattice alone does.  FP32
+// lattices also take two-step passes wherever neither of two snapshots is
+// due (two): on the tuned two-step tile shape, else 64 x 8, with the
+// automatic z-chunk of at least 16 planes; on MI355X the pass beats the
+// single step at every FP32 size measured (65 .. 512) and loses at every
+// FP64 size.
 // The pool supplies much of the parallelism that short z-chunks buy a
 // lattice run alone; 16 planes keep enough work items for ensembles of small
 // lattices (measured on MI355X: 128 lattices of N in {32, 48, 64} run 11%
 // faster than with 64-plane chunks, a mix of N in 64 .. 256 2% faster; 8
 // and 32 planes are slower than 16).
-static int pool_config(const ah_params& p, ah_step_config* cfg, std::string* why)
+static int pool_config(const ah_params& p, ah_step_config* cfg, TileConfig* two, std::string* why)
 {
     ah_step_config t{AH_KERNEL_TILE, 0, 0, 0};
+    int two_tx = 64, two_ty = 8;
     if (tuned_config(p, &t)) {
-        if (t.kernel != AH_KERNEL_TILE) t.zchunk = 0;
+        if (t.kernel == AH_KERNEL_TILE2) {
+            two_tx = t.tile_x;
+            two_ty = t.tile_y;
+            t.zchunk = 0;
+        }
         t.kernel = AH_KERNEL_TILE;
         if (!batch_tile_supported(p.precision, t.tile_x, t.tile_y)) t = ah_step_config{AH_KERNEL_TILE, 0, 0, 0};
     }
     const int rc = resolve_step_config(p, t, cfg, why);
     if (rc != AH_OK) return rc;
-    int zc = cfg->zchunk < 16 ? 16 : cfg->zchunk;
-    if (zc > p.N) zc = p.N;
-    cfg->zchunk = zc;
+    auto floor16 = [&](int zc) { return std::min(std::max(zc, 16), p.N); };
+    cfg->zchunk = floor16(cfg->zchunk);
+    *two = TileConfig{0, 0, 0};
+    if (p.precision == AH_FP32 && tile2_supported(p.precision, two_tx, two_ty))
+        *two = TileConfig{two_tx, two_ty, floor16(auto_zchunk(AH_KERNEL_TILE2, p.precision, p.N, two_tx, two_ty, false))};
     return AH_OK;
 }
 
@@ -623,8 +655,9 @@ int ah_pool_footprint(const ah_params* p, int64_t nsteps, int32_t measure_every,
         if (validate_params(p, &why) != AH_OK || nsteps < 0 || measure_every < 0 || !bytes) return AH_E_INVAL;
         if (p->gauge_action != AH_COMPACT) return AH_E_INVAL;
         ah_step_config cfg;
-        if (pool_config(*p, &cfg, &why) != AH_OK) return AH_E_INVAL;
-        const size_t total = footprint(*p, cfg, nsteps, measure_every).total;
+        TileConfig two;
+        if (pool_config(*p, &cfg, &two, &why) != AH_OK) return AH_E_INVAL;
+        const size_t total = footprint(*p, cfg, two, nsteps, measure_every).total;
         if (total == SIZE_MAX) return AH_E_INVAL;
         *bytes = total;
         return AH_OK;
@@ -641,9 +674,10 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
         ah_step_config cfg{AH_KERNEL_TILE, 0, 0, 0};
         if (p->gauge_action != AH_COMPACT) return pfail(P, AH_E_INVAL, "ah_pool_submit: the pool runs the compact action");
-        rc = pool_config(*p, &cfg, &why);
+        TileConfig two;
+        rc = pool_config(*p, &cfg, &two, &why);
         if (rc != AH_OK) return pfail(P, rc, "ah_pool_submit: " + why);
-        const Footprint fp = footprint(*p, cfg, nsteps, measure_every);
+        const Footprint fp = footprint(*p, cfg, two, nsteps, measure_every);
         if (fp.total > P->budget) return pfail(P, AH_E_NOMEM, "ah_pool_submit: request larger than the pool budget");
         int slot = -1;
         for (int i = 0; i < (int)P->slots.size(); ++i)
@@ -666,8 +700,7 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         s.used = true;
         s.id = P->next_id++;
         s.seq = ++P->seq;
-        P->host_counters[2 * slot] = 0;
-        P->host_counters[2 * slot + 1] = 0;
+        for (int w = 0; w < kCounterWords; ++w) P->host_counters[kCounterWords * slot + w] = 0;
         s.p = *p;
         s.nsteps = nsteps;
         s.measure_every = measure_every;
@@ -675,6 +708,7 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         s.bytes = fp.total;
         s.cfg = cfg;
         s.meas = fp.meas;
+        s.two = two;
         char* base = (char*)P->arena + off;
         PoolLattice& d = s.d;
         std::memset(&d, 0, sizeof(d));
@@ -683,17 +717,18 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
                 d.pp[b][c] = base;
                 base += fp.field;
             }
-        for (int c = 0; c < 5; ++c) {
-            d.mom[c] = base;
-            base += fp.field;
-        }
+        for (int b = 0; b < (two.zchunk > 0 ? 2 : 1); ++b)
+            for (int c = 0; c < 5; ++c) {
+                d.mom[b][c] = base;
+                base += fp.field;
+            }
         d.partials = (double*)base;
         base += fp.partials;
         double* coef = (double*)base;
         d.coef = coef;
         base += fp.coef;
         d.series = (double*)base;
-        d.counter = P->d_counters + 2 * slot;
+        d.counter = P->d_counters + kCounterWords * slot;
         d.nsteps = nsteps;
         d.series_cap = fp.series_cap;
         d.N = p->N;
@@ -705,6 +740,11 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         d.mtiles_y = (p->N + fp.meas.ty - 1) / fp.meas.ty;
         d.meas_zchunk = fp.meas.zchunk;
         d.meas_blocks = fp.meas_blocks;
+        if (two.zchunk > 0) {
+            d.two_tiles_x = (p->N + two.tx - 1) / two.tx;
+            d.two_tiles_y = (p->N + two.ty - 1) / two.ty;
+            d.two_zchunk = two.zchunk;
+        }
         d.gauss_blocks = fp.gauss_blocks;
         d.measure_every = measure_every;
         d.precision = p->precision;
@@ -717,19 +757,20 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
         // (the slot's previous lattice, if any, has finished, so they leave
         // its memory and counter alone); nothing waits for them
         hipError_t e = stage_upload(P, coef, rows.data(), rows.size() * sizeof(double));
-        if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 2 * sizeof(int64_t), P->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, kCounterWords * sizeof(int64_t), P->stream);
         if (e == hipSuccess) {
             Fields<double> f64;
             Fields<float> f32;
             if (p->precision == AH_FP64) {
-                f64 = Fields<double>{(double*)d.pp[0][0], (double*)d.pp[0][1], (double*)d.mom[0], (double*)d.mom[1],
-                                     (double*)d.pp[0][2], (double*)d.pp[0][3], (double*)d.pp[0][4], (double*)d.mom[2],
-                                     (double*)d.mom[3], (double*)d.mom[4]};
+                f64 = Fields<double>{(double*)d.pp[0][0], (double*)d.pp[0][1], (double*)d.mom[0][0],
+                                     (double*)d.mom[0][1], (double*)d.pp[0][2], (double*)d.pp[0][3],
+                                     (double*)d.pp[0][4], (double*)d.mom[0][2], (double*)d.mom[0][3],
+                                     (double*)d.mom[0][4]};
                 e = launch_init<double>(f64, p->N, d.P, p->sigma, seed, P->stream);
             } else {
-                f32 = Fields<float>{(float*)d.pp[0][0], (float*)d.pp[0][1], (float*)d.mom[0], (float*)d.mom[1],
-                                    (float*)d.pp[0][2], (float*)d.pp[0][3], (float*)d.pp[0][4], (float*)d.mom[2],
-                                    (float*)d.mom[3], (float*)d.mom[4]};
+                f32 = Fields<float>{(float*)d.pp[0][0], (float*)d.pp[0][1], (float*)d.mom[0][0], (float*)d.mom[0][1],
+                                    (float*)d.pp[0][2], (float*)d.pp[0][3], (float*)d.pp[0][4], (float*)d.mom[0][2],
+                                    (float*)d.mom[0][3], (float*)d.mom[0][4]};
                 e = launch_init<float>(f32, p->N, d.P, p->sigma, seed, P->stream);
             }
         }
@@ -787,7 +828,7 @@ static int report_done(ah_pool* P, int64_t* done_ids, int32_t cap, int32_t* n)
     for (size_t i = 0; i < P->slots.size(); ++i) {
         Slot& s = P->slots[i];
         if (!s.used || s.reported) continue;
-        if (P->host_counters[2 * i] == s.nsteps + 1) {
+        if (P->host_counters[kCounterWords * i] == s.nsteps + 1) {
             if (k < cap) {
                 done_ids[k] = s.id;
                 s.reported = true;
@@ -852,8 +893,8 @@ int ah_pool_progress(ah_pool* P, int64_t id, int64_t* step, int64_t* nsteps)
         Slot* s = find_slot(P, id, &i);
         if (!s) return pfail(P, AH_E_INVAL, "ah_pool_progress: unknown id");
         Guard g(P->device);
-        int64_t c[2];
-        hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+        int64_t c[kCounterWords];
+        hipError_t e = hipMemcpyAsync(c, P->d_counters + kCounterWords * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
         if (e != hipSuccess) return phip(P, e, "ah_pool_progress");
         *step = std::min(c[0], s->nsteps);
@@ -870,16 +911,17 @@ int ah_pool_get_state(ah_pool* P, int64_t id, double* host_soa, int64_t* step)
         Slot* s = find_slot(P, id, &i);
         if (!s) return pfail(P, AH_E_INVAL, "ah_pool_get_state: unknown id");
         Guard g(P->device);
-        int64_t c[2];
-        hipError_t e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+        int64_t c[kCounterWords];
+        hipError_t e = hipMemcpyAsync(c, P->d_counters + kCounterWords * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
         if (e != hipSuccess) return phip(P, e, "ah_pool_get_state");
         const int64_t k = std::min(c[0], s->nsteps);
-        const int cur = (int)(k & 1);
+        const int cur = (int)c[2], curm = (int)c[3];  // the buffers of snapshot k
         const size_t V = (size_t)s->p.N * s->p.N * s->p.N;
         const size_t rb = s->p.precision == AH_FP64 ? 8 : 4;
-        void* comps[10] = {s->d.pp[cur][0], s->d.pp[cur][1], s->d.mom[0], s->d.mom[1], s->d.pp[cur][2],
-                           s->d.pp[cur][3], s->d.pp[cur][4], s->d.mom[2], s->d.mom[3], s->d.mom[4]};
+        void* const* m = s->d.mom[curm];
+        void* comps[10] = {s->d.pp[cur][0], s->d.pp[cur][1], m[0], m[1], s->d.pp[cur][2],
+                           s->d.pp[cur][3], s->d.pp[cur][4], m[2], m[3], m[4]};
         std::vector<float> tmp(rb == 4 ? V : 0);
         for (int cc = 0; cc < 10; ++cc) {
             double* dst = host_soa + cc * V;
@@ -903,10 +945,11 @@ int ah_pool_results(ah_pool* P, int64_t id, ah_measurement* series, int32_t cap,
         if (!s) return pfail(P, AH_E_INVAL, "ah_pool_results: unknown id");
         Guard g(P->device);
         hipError_t e;
-        int64_t c[2] = {P->host_counters[2 * i], P->host_counters[2 * i + 1]};
+        int64_t c[kCounterWords];
+        for (int w = 0; w < kCounterWords; ++w) c[w] = P->host_counters[kCounterWords * i + w];
         if (c[0] != s->nsteps + 1) {
             // not seen finished yet: read the counters after the queued work
-            e = hipMemcpyAsync(c, P->d_counters + 2 * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
+            e = hipMemcpyAsync(c, P->d_counters + kCounterWords * i, sizeof(c), hipMemcpyDeviceToHost, P->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
             if (e != hipSuccess) return phip(P, e, "ah_pool_results");
             if (c[0] != s->nsteps + 1) return pfail(P, AH_E_AGAIN, "ah_pool_results: the lattice has not finished");

@@ -144,6 +144,20 @@ __device__ inline int wrapi(int v, int N)
     return v < N ? v : v % N;
 }
 
+// Whether pool lattice L forms the diagnostics of its snapshot k (every
+// measure_every-th and the last), and whether its step k is a two-step pass:
+// it has a two-step tiling, neither k nor k+1 is due and both steps remain.
+__device__ inline bool measure_due(const PoolLattice& L, int64_t k)
+{
+    if (k > L.nsteps) return false;
+    if (k == L.nsteps) return true;
+    return L.measure_every > 0 && (k % L.measure_every) == 0;
+}
+__device__ inline bool two_step_due(const PoolLattice& L, int64_t k)
+{
+    return L.two_zchunk > 0 && k + 1 < L.nsteps && !measure_due(L, k) && !measure_due(L, k + 1);
+}
+
 // Place tiles so that the blocks the hardware sends to one XCD (block b goes
 // to XCD b % 8) cover a contiguous range of tile indices.
 __device__ inline int xcd_tile(int b, int nb)

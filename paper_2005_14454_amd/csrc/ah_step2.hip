@@ -101,23 +101,16 @@ constexpr int kStep2Threads = Geom2<TX, TY>::NTH;
 template <typename R, int TX, int TY>
 constexpr int kStep2MinWaves = sizeof(R) == 8 ? 2 : 3;
 
-// One workgroup: tile t = xcd_tile(b) (tx fastest, then ty, then z-chunk).
+// Two steps of planes [z0, z1) of the tile whose lower corner is (x0, y0).
+// All threads of the workgroup call this with the same arguments.
 template <typename R, int TX, int TY>
-__global__ void __launch_bounds__((kStep2Threads<TX, TY>), (kStep2MinWaves<R, TX, TY>))
-    k_step2_tile(Step2Args<R> a, int zchunk, int tiles_x, int tiles_y)
+__device__ __forceinline__ void march2(Shared2<R, TX, TY>& sh, const Step2Args<R>& a, int x0, int y0, int z0, int z1)
 {
     using G = Geom2<TX, TY>;
     constexpr int W1 = G::W1, H1 = G::H1, W2 = G::W2, H2 = G::H2, NT = G::NT;
-    __shared__ Shared2<R, TX, TY> sh;
 
     const int N = a.N, P = a.P;
     const int64_t NN = (int64_t)N * P;  // plane stride
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int x0 = (t % tiles_x) * TX;
-    t /= tiles_x;
-    const int y0 = (t % tiles_y) * TY;
-    const int z0 = (t / tiles_y) * zchunk;
-    const int z1 = (z0 + zchunk < N) ? z0 + zchunk : N;
     const R dx = a.dx;
     const Fields<R>& f = a.in;
     // 1/dx and 1/dx^2 formed on the device as the single-step march forms them
@@ -386,6 +379,69 @@ __global__ void __launch_bounds__((kStep2Threads<TX, TY>), (kStep2MinWaves<R, TX
     }
 }
 
+// One lattice: tile t = xcd_tile(b) (tx fastest, then ty, then z-chunk).
+template <typename R, int TX, int TY>
+__global__ void __launch_bounds__((kStep2Threads<TX, TY>), (kStep2MinWaves<R, TX, TY>))
+    k_step2_tile(Step2Args<R> a, int zchunk, int tiles_x, int tiles_y)
+{
+    __shared__ Shared2<R, TX, TY> sh;
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (t % tiles_x) * TX;
+    t /= tiles_x;
+    const int y0 = (t % tiles_y) * TY;
+    const int z0 = (t / tiles_y) * zchunk;
+    const int z1 = (z0 + zchunk < a.N) ? z0 + zchunk : a.N;
+    march2<R, TX, TY>(sh, a, x0, y0, z0, z1);
+}
+
+// Pool lattices that take a two-step pass at their step k (two_step_due):
+// one block per (lattice, tile) work item, XCD x the x-th eighth of the list
+// as in the single-step batch kernel; snapshot k of the current buffers to
+// snapshot k+2 in the other ones, with the coefficients of rows k and k+1 of
+// the lattice's table.
+template <typename R, int TX, int TY>
+__global__ void __launch_bounds__((kStep2Threads<TX, TY>), (kStep2MinWaves<R, TX, TY>))
+    k_step2_batch(const PoolLattice* __restrict__ lat, const WorkItem* __restrict__ work, int nwork)
+{
+    __shared__ Shared2<R, TX, TY> sh;
+    const WorkItem it = work[xcd_tile(blockIdx.x, nwork)];
+    if (it.lattice < 0) return;
+    const PoolLattice& L = lat[it.lattice];
+    const int64_t k = L.counter[0];
+    if (!two_step_due(L, k)) return;  // uniform across the block
+    const int cur = (int)L.counter[2], curm = (int)L.counter[3];
+    Step2Args<R> a;
+    a.in = Fields<R>{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[curm][0], (R*)L.mom[curm][1], (R*)L.pp[cur][2],
+                     (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[curm][2], (R*)L.mom[curm][3], (R*)L.mom[curm][4]};
+    const int o = cur ^ 1, om = curm ^ 1;
+    a.out = Fields<R>{(R*)L.pp[o][0], (R*)L.pp[o][1], (R*)L.mom[om][0], (R*)L.mom[om][1], (R*)L.pp[o][2],
+                      (R*)L.pp[o][3], (R*)L.pp[o][4], (R*)L.mom[om][2], (R*)L.mom[om][3], (R*)L.mom[om][4]};
+    a.N = L.N;
+    a.P = L.P;
+    a.dx = (R)L.dx;
+    const double* row = L.coef + k * kCoefStride;
+    for (int j = 0; j < 2; ++j, row += kCoefStride) {
+        SiteCoef<R>& c = j ? a.k1 : a.k0;
+        c.inv_dx = c.inv_dx2 = R(0);  // formed in the march
+        c.sigma2 = (R)L.sigma2;
+        c.cP1 = (R)row[C_P1];
+        c.cP2 = (R)row[C_P2];
+        c.cE1 = (R)row[C_E1];
+        c.cE2 = (R)row[C_E2];
+        c.lamh = (R)row[C_LAMH];
+        c.kappa = (R)row[C_KAPPA];
+        c.deta = (R)L.deta;
+    }
+    a = uniform(a);
+    int t = it.tile;
+    const int x0 = uniform((t % L.two_tiles_x) * TX);
+    t /= L.two_tiles_x;
+    const int y0 = uniform((t % L.two_tiles_y) * TY);
+    const int z0 = uniform((t / L.two_tiles_y) * L.two_zchunk);
+    const int z1 = uniform((z0 + L.two_zchunk < L.N) ? z0 + L.two_zchunk : L.N);
+    march2<R, TX, TY>(sh, a, x0, y0, z0, z1);
+}
+
 }  // namespace
 
 template <typename R>
@@ -429,6 +485,28 @@ hipError_t launch_step2_tile(const Fields<R>& in, const Fields<R>& out, const La
 #undef AH_STEP2_CASE
     return hipErrorInvalidValue;
 }
+
+template <typename R>
+hipError_t launch_step2_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,
+                              hipStream_t s)
+{
+    if (!tile2_supported(sizeof(R) == 8 ? AH_FP64 : AH_FP32, tx, ty)) return hipErrorInvalidValue;
+#define AH_STEP2_BATCH_CASE(TXv, TYv)                                                                             \
+    if (tx == TXv && ty == TYv) {                                                                                 \
+        hipLaunchKernelGGL((k_step2_batch<R, TXv, TYv>), dim3(grid), dim3(Geom2<TXv, TYv>::NTH), 0, s, lat, work, \
+                           nwork);                                                                                \
+        return hipGetLastError();                                                                                 \
+    }
+    AH_STEP2_BATCH_CASE(32, 8)
+    AH_STEP2_BATCH_CASE(64, 4)
+    if constexpr (sizeof(R) == 4) {
+        AH_STEP2_BATCH_CASE(64, 8)
+    }
+#undef AH_STEP2_BATCH_CASE
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_step2_batch<double>(const PoolLattice*, const WorkItem*, int, int, int, int, hipStream_t);
+template hipError_t launch_step2_batch<float>(const PoolLattice*, const WorkItem*, int, int, int, int, hipStream_t);
 
 template hipError_t launch_step2_tile<double>(const Fields<double>&, const Fields<double>&, const LatticeConst&,
                                               const StepCoef&, const StepCoef&, const TileConfig&, hipStream_t);

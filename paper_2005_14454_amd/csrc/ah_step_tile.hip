@@ -706,12 +706,6 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_tile(Step
         march_step<R, TX, TY, false>(sh, nullptr, a, ma, nullptr, true, tx * TX, ty * TY, z0, z1);
 }
 
-__device__ inline bool measure_due(const PoolLattice& L, int64_t k)
-{
-    if (k > L.nsteps) return false;
-    if (k == L.nsteps) return true;
-    return L.measure_every > 0 && (k % L.measure_every) == 0;
-}
 
 // Many lattices in one launch: blocks stride over a work list of
 // (lattice, tile) items; each lattice reads its own step counter k, takes the
@@ -732,15 +726,15 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(con
     const WorkItem it = work[w];
     if (it.lattice < 0) return;
     const PoolLattice& L = lat[it.lattice];
-    const int64_t k = *L.counter;
+    const int64_t k = L.counter[0];
     const bool due = measure_due(L, k);
     if (MEAS != due) return;                     // uniform across the block
-    if (!MEAS && k >= L.nsteps) return;
+    if (!MEAS && (k >= L.nsteps || two_step_due(L, k))) return;
     const double* row = L.coef + k * kCoefStride;
-    const int cur = (int)(k & 1);
+    const int cur = (int)L.counter[2], curm = (int)L.counter[3];
     StepArgs<R> a;
-    a.f = Fields<R>{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[0], (R*)L.mom[1], (R*)L.pp[cur][2],
-                    (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[2], (R*)L.mom[3], (R*)L.mom[4]};
+    a.f = Fields<R>{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[curm][0], (R*)L.mom[curm][1], (R*)L.pp[cur][2],
+                    (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[curm][2], (R*)L.mom[curm][3], (R*)L.mom[curm][4]};
     a.ophr = (R*)L.pp[cur ^ 1][0];
     a.ophi = (R*)L.pp[cur ^ 1][1];
     a.oa0 = (R*)L.pp[cur ^ 1][2];
@@ -861,11 +855,12 @@ __global__ void __launch_bounds__(256) k_gauss_batch(const PoolLattice* __restri
         const WorkItem it = work[w];
         if (it.lattice < 0) continue;  // an empty item
         const PoolLattice& L = lat[it.lattice];
-        const int64_t k = *L.counter;
+        const int64_t k = L.counter[0];
         if (!measure_due(L, k)) continue;
-        const int cur = (int)(k & 1);
-        const Fields<R> f{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[0], (R*)L.mom[1], (R*)L.pp[cur][2],
-                          (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[2], (R*)L.mom[3], (R*)L.mom[4]};
+        const int cur = (int)L.counter[2], curm = (int)L.counter[3];
+        const Fields<R> f{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[curm][0], (R*)L.mom[curm][1],
+                          (R*)L.pp[cur][2], (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[curm][2],
+                          (R*)L.mom[curm][3], (R*)L.mom[curm][4]};
         const double* row = L.coef + k * kCoefStride;
         const int b1 = min(it.tile + kGaussPerItem, L.gauss_blocks);
         for (int b = it.tile; b < b1; ++b)
@@ -892,13 +887,28 @@ __global__ void __launch_bounds__(256) k_fold_batch(const PoolLattice* __restric
     }
 }
 
-// Advance the step counter of every pool lattice that is not finished.
+// Advance the counter of every pool lattice that is not finished by what
+// this replay did to it: a measured or single step (or the final
+// measurement) one step and the phi/A buffer, a two-step pass two steps and
+// both buffers.
 __global__ void k_advance_batch(const PoolLattice* __restrict__ lat, int nlat)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nlat) return;
-    const int64_t k = lat[i].counter[0];
-    if (k <= lat[i].nsteps) lat[i].counter[0] = k + 1;
+    const PoolLattice& L = lat[i];
+    int64_t* c = L.counter;
+    const int64_t k = c[0];
+    if (k > L.nsteps) return;
+    if (k == L.nsteps) {
+        c[0] = k + 1;  // the final measurement: finished
+    } else if (two_step_due(L, k)) {
+        c[0] = k + 2;
+        c[2] ^= 1;
+        c[3] ^= 1;
+    } else {
+        c[0] = k + 1;
+        c[2] ^= 1;
+    }
 }
 
 }  // namespace
