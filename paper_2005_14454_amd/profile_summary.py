@@ -11,6 +11,10 @@
         device copy in the same run (a copy of known size: it reads and writes
         its byte count), next to the algorithmic bytes of the step kernels
 
+    python -m paper_2005_14454_amd.profile_summary counters DIR [--N 512]
+        mean of every counter per kernel from one --pmc pass, and for the
+        step kernels the wave64 VALU instructions per site-update
+
 Every figure printed is computed from the named raw output, so a kept
 summary can be recomputed from the run it names.
 """
@@ -204,6 +208,41 @@ def traffic(fetch_dir, write_dir, N=512, note="", copy_bytes=8 << 30):
     return "\n".join(lines)
 
 
+SITE_UPDATES_PER_SITE = {"k_step_tile": 1, "k_step2_tile": 2}
+
+
+def counters(directory, N=512, note=""):
+    """Mean of every counter per kernel (one --pmc pass); SQ_INSTS_VALU per
+    site-update for the step kernels at N^3 (a rough figure where a kernel
+    name covers several lattice sizes)."""
+    vals = defaultdict(lambda: defaultdict(float))
+    names = {}
+    for r in _rows(directory, "counter_collection.csv"):
+        d = int(_col(r, "Dispatch_Id", "Dispatch-Id", "Correlation_Id"))
+        vals[d][_col(r, "Counter_Name", "Counter-Name")] += float(_col(r, "Counter_Value", "Counter-Value"))
+        names[d] = short_name(_col(r, "Kernel_Name", "Kernel-Name"))
+    per = defaultdict(list)
+    for d, v in vals.items():
+        per[names[d]].append(v)
+    cols = sorted({c for v in vals.values() for c in v})
+    lines = [f"rocprofv3 counters per dispatch (mean over dispatches) of {directory}"]
+    if note:
+        lines.append(note)
+    for k, h in source_hashes().items():
+        lines.append(f"{k} sources sha256[:16] = {h}")
+    lines.append("")
+    lines.append(f"{'kernel':<44} {'n':>4} " + " ".join(f"{c[:22]:>22}" for c in cols) + f" {'VALU/site-update':>16}")
+    for name, vs in sorted(per.items()):
+        means = [statistics.mean(v.get(c, 0.0) for v in vs) for c in cols]
+        base = re.match(r"(\w+)<", name)
+        upd = SITE_UPDATES_PER_SITE.get(base.group(1) if base else "", 0)
+        vpu = "-"
+        if upd and "SQ_INSTS_VALU" in cols:
+            vpu = f"{means[cols.index('SQ_INSTS_VALU')] * 64 / (upd * N ** 3):.1f}"
+        lines.append(f"{name[:44]:<44} {len(vs):>4} " + " ".join(f"{m:>22.4g}" for m in means) + f" {vpu:>16}")
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -217,9 +256,15 @@ def main(argv=None):
     c.add_argument("--N", type=int, default=512)
     c.add_argument("--note", default="")
     c.add_argument("--copy-bytes", type=int, default=8 << 30)
+    q = sub.add_parser("counters")
+    q.add_argument("dir")
+    q.add_argument("--N", type=int, default=512)
+    q.add_argument("--note", default="")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace(a.dir, a.note, a.window))
+    elif a.cmd == "counters":
+        print(counters(a.dir, a.N, a.note))
     else:
         print(traffic(a.fetch_dir, a.write_dir, a.N, a.note, a.copy_bytes))
 

@@ -54,3 +54,18 @@ def test_traffic_is_scaled_by_the_copy(tmp_path):
     # read 2 x 1000 KiB, write 3000 KiB; algorithmic 40 B per site for 8^3 sites
     assert row[-5:] == [f"{2000 * 1024 / 1e9:.3f}", f"{3000 * 1024 / 1e9:.3f}", f"{5000 * 1024 / 1e9:.3f}",
                         f"{40 * 4 * 512 / 1e9:.3f}", "1"]
+
+
+def test_counters_mean_and_valu_per_site_update(tmp_path):
+    d = tmp_path / "c"
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    # two dispatches of a two-step launch on a 4^3 lattice: 128 site-updates each
+    _write(str(d / "a" / "run_counter_collection.csv"), hdr,
+           [(1, '"k_step2_tile<float, 64, 8>(x)"', "SQ_INSTS_VALU", 100.0),
+            (1, '"k_step2_tile<float, 64, 8>(x)"', "SQ_WAVES", 4.0),
+            (2, '"k_step2_tile<float, 64, 8>(x)"', "SQ_INSTS_VALU", 300.0),
+            (2, '"k_step2_tile<float, 64, 8>(x)"', "SQ_WAVES", 4.0)])
+    text = ps.counters(str(d), N=4)
+    row = [l for l in text.splitlines() if l.startswith("k_step2_tile")][0].split()
+    # mean 200 wave instructions x 64 lanes / 128 site-updates
+    assert row[-4:] == ["2", "200", "4", f"{200 * 64 / 128:.1f}"]
