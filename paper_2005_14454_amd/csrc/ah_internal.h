@@ -171,7 +171,8 @@ enum CoefSlot { C_P1 = 0, C_P2, C_E1, C_E2, C_LAMH, C_KAPPA, C_INV2E2F, C_LAMQ, 
 struct PoolLattice {
     void* pp[2][5];        // ping-pong phi_re, phi_im, A0, A1, A2; counter[2] names the current one
     void* mom[2][5];       // Pi_re, Pi_im, E0, E1, E2; counter[3] names the current one (updated in place by a
-                           // single step; a two-step pass writes the other); mom[1] only with two-step passes
+                           // plain single step; a two-step pass and an FP32 measured step write the other);
+                           // mom[1] only for FP32 lattices and with two-step passes
     const double* coef;    // (nsteps + 1) rows of kCoefStride doubles
     int64_t* counter;      // kCounterWords words: local step k, measurements taken, phi/A buffer, Pi/E buffer
     double* partials;      // diagnostics records of this lattice
@@ -180,7 +181,8 @@ struct PoolLattice {
     int64_t series_cap;
     int N, tiles_x, tiles_y, zchunk;     // step tiling
     int meas_zchunk, meas_blocks, measure_every, precision;
-    int gauss_blocks, P;     // Gauss records follow the meas_blocks step records; P: row pitch
+    int gauss_blocks, P;     // Gauss records follow the meas_blocks step records (0: the Gauss residual is in
+                             // the measured march's records); P: row pitch
     int mtiles_x, mtiles_y;  // tiling of the measured step (measured_tile), z-chunks of meas_zchunk
     int two_tiles_x, two_tiles_y, two_zchunk;  // tiling of the two-step pass; two_zchunk == 0: none
     int compact;
@@ -217,13 +219,20 @@ template <typename R>
 hipError_t launch_step(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2,
                        const LatticeConst& L, const StepCoef& c, hipStream_t s);
 
-// Tiled step; with mc != nullptr also the diagnostics of the snapshot read
-// (one record per workgroup into partials, in tile order); write = false
-// leaves the fields untouched (diagnostics only).
+// Tiled step from `in` to `out`: phi and A into out's (other) buffers, Pi
+// and E into out's, which may be in's (an update in place).  With mc !=
+// nullptr also the diagnostics of the snapshot read (one record per workgroup
+// into partials, in tile order); for FP32 they include the Gauss residual,
+// and a measured FP32 step then needs Pi and E out of place (else
+// hipErrorInvalidValue).  write = false leaves the fields untouched
+// (diagnostics only).
 template <typename R>
-hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2, const LatticeConst& L,
-                            const StepCoef& c, const TileConfig& tc, const MeasConst* mc, double* partials,
-                            bool write, hipStream_t s);
+hipError_t launch_step_tile(const Fields<R>& in, const Fields<R>& out, const LatticeConst& L, const StepCoef& c,
+                            const TileConfig& tc, const MeasConst* mc, double* partials, bool write, hipStream_t s);
+
+// Whether the measured march of a lattice of this precision forms the Gauss
+// residual itself (FP32) or leaves it to the Gauss pass (FP64).
+__host__ __device__ inline bool gauss_in_march(int precision) { return precision == AH_FP32; }
 
 // Two steps in one pass: snapshot n of `in` to snapshot n+2 of `out` (all
 // ten fields in other buffers), with the coefficients of steps n and n+1.

@@ -6,7 +6,8 @@
 // diagnostics records and its measurement series inside the arena, plus a
 // descriptor and a counter (step, measurements taken, buffer parities) in
 // pool metadata.  The graph replayed per step is
-//     Gauss pass and measured step (lattices whose snapshot is due) -> fold
+//     Gauss pass (FP64 lattices whose snapshot is due; the FP32 measured
+//     step forms it itself) and measured step -> fold
 //     -> single step and two-step pass (one node per precision and tile
 //     shape) -> advance counters
 // and every kernel reads the lattice's own counter, so the same graph serves
@@ -74,13 +75,15 @@ struct Slot {
 struct Footprint {
     size_t field, fields, partials, coef, series, total;
     TileConfig meas;  // tiling of the measured step
+    int mom_buffers;  // Pi/E buffers: 2 for FP32 lattices and with two-step passes
     int meas_blocks, gauss_blocks;
     int64_t series_cap;
 };
 
-// Bytes of one pool lattice (15 fields, 20 with two-step passes, whose Pi
-// and E are double-buffered); total = SIZE_MAX when nsteps is too large for
-// its coefficient table to be addressed at all.
+// Bytes of one pool lattice (15 fields, 20 where Pi and E are
+// double-buffered: with two-step passes and for FP32 lattices, whose measured
+// step writes them out of place); total = SIZE_MAX when nsteps is too large
+// for its coefficient table to be addressed at all.
 Footprint footprint(const ah_params& p, const ah_step_config& cfg, const TileConfig& two, int64_t nsteps,
                     int measure_every)
 {
@@ -91,10 +94,11 @@ Footprint footprint(const ah_params& p, const ah_step_config& cfg, const TileCon
     }
     const size_t stored = (size_t)p.N * p.N * row_pitch(p.N, p.precision);
     f.field = align_up(stored * (p.precision == AH_FP64 ? 8 : 4));
-    f.fields = (two.zchunk > 0 ? 20 : 15) * f.field;
+    f.mom_buffers = (two.zchunk > 0 || gauss_in_march(p.precision)) ? 2 : 1;
+    f.fields = (size_t)(10 + 5 * f.mom_buffers) * f.field;
     f.meas = measured_tiling(p, cfg);
     f.meas_blocks = step_tile_blocks(p.N, f.meas);
-    f.gauss_blocks = gauss_blocks(p.N);
+    f.gauss_blocks = gauss_in_march(p.precision) ? 0 : gauss_blocks(p.N);
     f.partials = align_up((size_t)(f.meas_blocks + f.gauss_blocks) * kMeasStride * sizeof(double));
     f.coef = align_up((size_t)(nsteps + 1) * kCoefStride * sizeof(double));
     f.series_cap = (measure_every > 0 ? nsteps / measure_every + 1 : 0) + 1;
@@ -366,7 +370,7 @@ hipError_t retire(ah_pool* P, hipGraphExec_t exec, hipGraph_t graph, void* buf)
 // uploads are ordered after the replays already queued, which keep reading
 // the old descriptors and lists until then.
 //
-// The graph has one Gauss node per precision and one step node (plain and
+// The graph has a Gauss node for FP64 lattices and one step node (plain and
 // measured) per (precision, tile shape), each over a fixed-capacity region
 // of the work list whose unused items are empty.  An admission or a release
 // that fits the captured capacities only rewrites the lists; a new group or
@@ -386,13 +390,14 @@ int rebuild(ah_pool* P)
             desc[i].counter = P->d_counters + kCounterWords * i;
         }
     }
-    // the lists each group needs now: Gauss items per precision; step items
+    // the lists each group needs now: Gauss items of FP64 lattices; step items
     // per (precision, tile shape) in kXcdCount bands
     std::map<GroupKey, std::vector<WorkItem>> gauss_need;
     std::map<GroupKey, std::array<std::vector<WorkItem>, kXcdCount>> step_need;
     for (int i = 0; i < nslot; ++i) {
         const Slot& s = P->slots[i];
         if (!s.used) continue;
+        if (s.d.gauss_blocks == 0) continue;  // the measured march forms the residual
         auto& g = gauss_need[GroupKey{0, s.p.precision, 0, 0}];
         for (int t = 0; t < s.d.gauss_blocks; t += kGaussPerItem) g.push_back({i, t});
     }
@@ -510,7 +515,7 @@ int rebuild(ah_pool* P)
     e = hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return phip(P, e, "pool graph capture begin");
     hipError_t le = hipSuccess;
-    // Gauss residual of the due snapshots (read-only, before anything is
+    // Gauss residual of the due FP64 snapshots (read-only, before anything is
     // overwritten), measured steps of the due lattices, their fold, the plain
     // steps of all others, the counter update
     for (auto& kv : P->groups) {
@@ -717,7 +722,7 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
                 d.pp[b][c] = base;
                 base += fp.field;
             }
-        for (int b = 0; b < (two.zchunk > 0 ? 2 : 1); ++b)
+        for (int b = 0; b < fp.mom_buffers; ++b)
             for (int c = 0; c < 5; ++c) {
                 d.mom[b][c] = base;
                 base += fp.field;

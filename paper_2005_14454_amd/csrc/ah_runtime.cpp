@@ -509,7 +509,10 @@ TileConfig meas_tiles(const ah_handle* h)
 }
 
 // Diagnostics of the current snapshot folded into dst[M_COUNT] (device), and
-// with `advance` the step of that snapshot in the same pass.
+// with `advance` the step of that snapshot in the same pass.  FP32: the march
+// forms the Gauss residual too, and the step writes Pi and E into the other
+// buffer; FP64: a read-only Gauss pass runs first and the step updates Pi and
+// E in place.
 template <typename R>
 hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
 {
@@ -517,8 +520,17 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
     const StepCoef c = coef_at(p, h->step);
     const MeasConst mc = meas_const(p, h->step);
     const TileConfig tc = meas_tiles(h);
+    const bool fused = gauss_in_march(p.precision);
     const Fields<R> in = fields_of<R>(h, h->cur);
-    const Fields<R> out = fields_of<R>(h, h->cur ^ 1);
+    Fields<R> out = fields_of<R>(h, h->cur ^ 1);
+    if (fused) {
+        const int om = h->curm ^ 1;
+        out.pir = (R*)h->mom[om][0];
+        out.pii = (R*)h->mom[om][1];
+        out.e0 = (R*)h->mom[om][2];
+        out.e1 = (R*)h->mom[om][3];
+        out.e2 = (R*)h->mom[om][4];
+    }
     hipError_t e;
     if (advance && h->timing) {
         if (h->ev_used + 2 > h->ev.size()) {
@@ -532,12 +544,14 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
         e = hipEventRecord(h->ev[h->ev_used], h->stream);
         if (e != hipSuccess) return e;
     }
-    // the Gauss residual reads the snapshot before the step overwrites E
+    // the Gauss pass reads the snapshot before the step overwrites E
     const int nb = step_tile_blocks(p.N, tc);
-    e = launch_gauss<R>(in, lconst(p), mc.gauss_c, h->partials + (size_t)nb * kMeasStride, h->stream);
-    if (e != hipSuccess) return e;
-    e = launch_step_tile<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(p), c, tc, &mc, h->partials, advance,
-                            h->stream);
+    const int ngb = fused ? 0 : gauss_blocks(p.N);
+    if (!fused) {
+        e = launch_gauss<R>(in, lconst(p), mc.gauss_c, h->partials + (size_t)nb * kMeasStride, h->stream);
+        if (e != hipSuccess) return e;
+    }
+    e = launch_step_tile<R>(in, out, lconst(p), c, tc, &mc, h->partials, advance, h->stream);
     if (e != hipSuccess) return e;
     if (advance && h->timing) {
         e = hipEventRecord(h->ev[h->ev_used + 1], h->stream);
@@ -547,10 +561,11 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
         h->ev_measured.push_back(1);
         h->ev_steps.push_back(1);
     }
-    e = launch_measure_final(h->partials, nb + gauss_blocks(p.N), dst, h->stream);
+    e = launch_measure_final(h->partials, nb + ngb, dst, h->stream);
     if (e != hipSuccess) return e;
     if (advance) {
         h->cur ^= 1;
+        if (fused) h->curm ^= 1;
         h->step += 1;
     }
     return hipSuccess;
@@ -602,8 +617,7 @@ hipError_t do_step(ah_handle* h)
             if (default_tile(h->p.precision, h->p.N, &tc.tx, &tc.ty))
                 tc.zchunk = auto_zchunk(AH_KERNEL_TILE, h->p.precision, h->p.N, tc.tx, tc.ty, false);
         }
-        e = launch_step_tile<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, tc, nullptr, nullptr,
-                                true, h->stream);
+        e = launch_step_tile<R>(in, out, lconst(h->p), c, tc, nullptr, nullptr, true, h->stream);
     } else {
         e = launch_step<R>(in, out.phr, out.phi, out.a0, out.a1, out.a2, lconst(h->p), c, h->stream);
     }

@@ -51,6 +51,13 @@ struct StepArgs {
     R* oa0;
     R* oa1;
     R* oa2;
+    // Pi and E outputs: f's own arrays for an update in place (the FP32
+    // measured march needs other ones)
+    R* opr;
+    R* opi;
+    R* oe0;
+    R* oe1;
+    R* oe2;
     int N, P;  // side, row pitch: site (x, y, z) at x + P (y + N z)
     R dx, sigma2, cP1, cP2, cE1, cE2, lamh, kappa, deta;
 };
@@ -75,6 +82,9 @@ struct MeasShared {
     static constexpr int RS = (TX + 2) * (TY + 2);
     R A[2][3][RS];                      // stored A of the link planes held in the U ring
     float Y[2][3][RS];                  // link phases of planes z (ring of two)
+    // FP32 lattices: E_x, E_y of plane z (own sites, and the -x / -y halo)
+    // for the Gauss residual
+    R E[2][sizeof(R) == 4 ? RS : 1];
     // FP64 lattices: each thread's running diagnostics sums (kept here rather
     // than in registers, which the FP64 measured march runs out of)
     double acc[kMarchSums][sizeof(R) == 8 ? TX * TY : 1];
@@ -204,9 +214,13 @@ __device__ inline double wave_max(double v)
 // drift every own site (if `write`), and with MEAS also form the diagnostics of
 // the snapshot being read (section 2 estimators, energy split, windings),
 // writing the workgroup's fixed-order sums to `record`.  The Gauss residual
-// reads E at the -x and -y neighbours, which neighbouring workgroups of the
-// same pass overwrite in place, so it has a read-only pass of its own
-// (k_gauss) that runs first.
+// reads E at the -x and -y neighbours, which a neighbouring workgroup of a
+// pass that updates E in place may already have overwritten.  The FP32
+// measured march therefore writes Pi and E out of place (a.opr .. a.oe2) and
+// forms the residual itself, passing E_x and E_y of each plane through LDS and
+// carrying E_z of the plane below in a register.  The FP64 one updates them in
+// place (its LDS holds two workgroups per CU only without that exchange) and
+// leaves the residual to a read-only pass (k_gauss) that runs first.
 // All threads of the workgroup call this with the same arguments; it
 // synchronises the workgroup internally.
 template <typename R, int TX, int TY, bool MEAS>
@@ -228,6 +242,12 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     const int N = a.N;
     const R dx = a.dx, sigma2 = a.sigma2, cP1 = a.cP1, cP2 = a.cP2, cE1 = a.cE1, cE2 = a.cE2;
     const R lamh = a.lamh, kappa = a.kappa, deta = a.deta;
+    constexpr bool GAUSS = MEAS && sizeof(R) == 4;  // Gauss residual in this march
+    R* wpr = a.opr;
+    R* wpi = a.opi;
+    R* we0 = a.oe0;
+    R* we1 = a.oe1;
+    R* we2 = a.oe2;
 
     const R inv_dx = R(1) / dx;
     const R inv_dx2 = inv_dx * inv_dx;
@@ -268,6 +288,13 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     // halo sites whose link phases the windings of the tile read
     const bool halo_top = has_halo && hry == TY + 1 && hrx >= 1 && hrx <= TX;    // Y_x, Y_z
     const bool halo_right = has_halo && hrx == TX + 1 && hry >= 1 && hry <= TY;  // Y_y, Y_z
+    // halo sites whose E the Gauss residual of the tile reads: E_x on the -x
+    // column, E_y on the -y row
+    const bool halo_ex = has_halo && hrx == 0 && hry >= 1 && hry <= TY;
+    const bool halo_ey = has_halo && hry == 0 && hrx >= 1 && hrx <= TX;
+    const bool halo_e = GAUSS && (halo_ex || halo_ey);
+    const R* hE = halo_ex ? f.e0 : f.e1;
+    const int hEc = halo_ex ? 0 : 1;
 
     // neighbour slots in the region
     const int rxm = ro - 1, rxp = ro + 1, rym = ro - RW, ryp = ro + RW;
@@ -306,6 +333,11 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     int wabs = 0, nonfin = 0;
     if constexpr (MEAS)
         for (int k = 0; k < kMarchSums; ++k) acc(k) = 0.0;
+    // Gauss residual (GAUSS): sums of G^2, (div E)^2, (c rho)^2, max |G|, and
+    // E_z of the own site one plane below
+    double g2 = 0.0, d2 = 0.0, c2 = 0.0, gmax = 0.0;
+    R ezm = R(0);
+    const double inv_dx64 = 1.0 / ma.dx;
     {
         const int64_t pm = plane_of(z0 - 1), p0 = plane_of(z0);
         const R* A[3] = {f.a0, f.a1, f.a2};
@@ -330,6 +362,12 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         phi_c = {at(f.phr, p0, ob), at(f.phi, p0, ob)};
         sPhi[ro] = phi_c;
         if (has_halo) sPhi[rh] = Cx<R>{at(f.phr, p0, hb), at(f.phi, p0, hb)};
+        if constexpr (GAUSS) {
+            ezm = at(f.e2, pm, ob);
+            mx->E[0][ro] = at(f.e0, p0, ob);
+            mx->E[1][ro] = at(f.e1, p0, ob);
+            if (halo_e) mx->E[hEc][rh] = at(hE, p0, hb);
+        }
         uz_m = um[2];
         __syncthreads();
         // F_xz, F_yz of the own column at plane z0-1
@@ -374,6 +412,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         R a[3], ha[3];
         Cx<R> hphi, phi2;
         R pr, pi, e[3];
+        R he;  // GAUSS: the halo E of plane t+1
     };
     auto prefetch = [&](int t, Pre& q) {
         const int64_t p2 = plane_of(t + 2), p1 = plane_of(t + 1);
@@ -386,6 +425,8 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             q.ha[2] = at(f.a2, p2, hb);
             q.hphi = {at(f.phr, p1, hb), at(f.phi, p1, hb)};
         }
+        if constexpr (GAUSS)
+            if (halo_e) q.he = at(hE, p1, hb);
         q.phi2 = {at(f.phr, p2, ob), at(f.phi, p2, ob)};
         q.pr = ld_stream(f.pir + p1 + ob);
         q.pi = ld_stream(f.pii + p1 + ob);
@@ -514,11 +555,11 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             const R ne2 = fm(cE1, e_c[2], cE2 * fm(kappa, jz, -cz));
             if (write && active) {
                 const int64_t o = (int64_t)z * NN;  // plane offset (uniform); + ob: the site
-                st_stream(f.pir + o + ob, npr);
-                st_stream(f.pii + o + ob, npi);
-                st_stream(f.e0 + o + ob, ne0);
-                st_stream(f.e1 + o + ob, ne1);
-                st_stream(f.e2 + o + ob, ne2);
+                st_stream(wpr + o + ob, npr);
+                st_stream(wpi + o + ob, npi);
+                st_stream(we0 + o + ob, ne0);
+                st_stream(we1 + o + ob, ne1);
+                st_stream(we2 + o + ob, ne2);
                 st_stream(ophr + o + ob, fm(deta, npr, phi_c.r));
                 st_stream(ophi + o + ob, fm(deta, npi, phi_c.i));
                 st_stream(oa0 + o + ob, fm(deta, ne0, Ac[0]));
@@ -559,6 +600,20 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                     const double rho = ((kin + grad) + pot_e) + (el + mag);
                     acc(M_PL) += pres * L;
                     acc(M_RHOL) += rho * L;
+                    if constexpr (GAUSS) {
+                        // G = sum_i (E_i^x - E_i^{x-i}) / dx - c Im[conj(phi) Pi] of the
+                        // snapshot, in FP64 from the exactly widened stored values
+                        const double dv = (((double)e_c[0] - (double)mx->E[0][rxm]) * inv_dx64 +
+                                           ((double)e_c[1] - (double)mx->E[1][rym]) * inv_dx64) +
+                                          ((double)e_c[2] - (double)ezm) * inv_dx64;
+                        const double crho = ma.gauss_c * ((double)phi_c.r * (double)pi_c -
+                                                          (double)phi_c.i * (double)pr_c);
+                        const double G = dv - crho;
+                        g2 += G * G;
+                        d2 += dv * dv;
+                        c2 += crho * crho;
+                        gmax = fmax(gmax, fabs(G));
+                    }
                 }
             }
             fxz_m = fxz;
@@ -595,6 +650,11 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                 sPhi[rh] = hphi;
             }
             sPhi[ro] = rphi;
+            if constexpr (GAUSS) {
+                mx->E[0][ro] = q1.e[0];
+                mx->E[1][ro] = q1.e[1];
+                if (halo_e) mx->E[hEc][rh] = q1.he;
+            }
         } else if constexpr (MEAS) {
             if (has_halo) sPhi[rh] = hphi;
             sPhi[ro] = rphi;
@@ -619,6 +679,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
 
         // ---- 5. rotate the own-column registers
         uz_m = Uc[2];
+        if constexpr (GAUSS) ezm = e_c[2];
         for (int d = 0; d < 3; ++d) {
             Uc[d] = Up[d];
             Up[d] = Upp[d];
@@ -649,12 +710,22 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             red[wv][M_WABS] = rw;
             red[wv][M_NONFIN] = rn;
         }
+        if constexpr (GAUSS) {
+            const double v[4] = {wave_sum(g2), wave_sum(d2), wave_sum(c2), wave_max(gmax)};
+            if (lane == 0) {
+                red[wv][M_G2] = v[0];
+                red[wv][M_DIV2] = v[1];
+                red[wv][M_CRHO2] = v[2];
+                red[wv][M_GMAX] = v[3];
+            }
+        }
         __syncthreads();
         if (tid < kMeasStride) {
+            const bool gslot = tid == M_G2 || tid == M_DIV2 || tid == M_CRHO2 || tid == M_GMAX;
             double r = 0.0;
-            if (tid < kMarchSums || tid == M_WABS || tid == M_NONFIN) {
+            if (tid < kMarchSums || tid == M_WABS || tid == M_NONFIN || (GAUSS && gslot)) {
                 r = red[0][tid];
-                for (int w = 1; w < NT / 64; ++w) r += red[w][tid];
+                for (int w = 1; w < NT / 64; ++w) r = tid == M_GMAX ? fmax(r, red[w][tid]) : r + red[w][tid];
             }
             record[tid] = r;
         }
@@ -740,6 +811,13 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(con
     a.oa0 = (R*)L.pp[cur ^ 1][2];
     a.oa1 = (R*)L.pp[cur ^ 1][3];
     a.oa2 = (R*)L.pp[cur ^ 1][4];
+    // Pi and E in place, but out of place for the FP32 measured march
+    const int om = (MEAS && sizeof(R) == 4) ? curm ^ 1 : curm;
+    a.opr = (R*)L.mom[om][0];
+    a.opi = (R*)L.mom[om][1];
+    a.oe0 = (R*)L.mom[om][2];
+    a.oe1 = (R*)L.mom[om][3];
+    a.oe2 = (R*)L.mom[om][4];
     a.N = L.N;
     a.P = L.P;
     a.dx = (R)L.dx;
@@ -888,9 +966,9 @@ __global__ void __launch_bounds__(256) k_fold_batch(const PoolLattice* __restric
 }
 
 // Advance the counter of every pool lattice that is not finished by what
-// this replay did to it: a measured or single step (or the final
-// measurement) one step and the phi/A buffer, a two-step pass two steps and
-// both buffers.
+// this replay did to it: the final measurement one step; a single step one
+// step and the phi/A buffer, and the Pi/E buffer too if it was an FP32
+// measured step; a two-step pass two steps and both buffers.
 __global__ void k_advance_batch(const PoolLattice* __restrict__ lat, int nlat)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -908,24 +986,34 @@ __global__ void k_advance_batch(const PoolLattice* __restrict__ lat, int nlat)
     } else {
         c[0] = k + 1;
         c[2] ^= 1;
+        if (gauss_in_march(L.precision) && measure_due(L, k)) c[3] ^= 1;
     }
 }
 
 }  // namespace
 
 template <typename R>
-hipError_t launch_step_tile(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R* oa2, const LatticeConst& L,
-                            const StepCoef& c, const TileConfig& tc, const MeasConst* mc, double* partials,
-                            bool write, hipStream_t s)
+hipError_t launch_step_tile(const Fields<R>& in, const Fields<R>& out, const LatticeConst& L, const StepCoef& c,
+                            const TileConfig& tc, const MeasConst* mc, double* partials, bool write, hipStream_t s)
 {
     const int N = L.N;
+    // an FP32 measured step reads E of neighbours that other workgroups
+    // update: its Pi and E go to other buffers
+    if (sizeof(R) == 4 && mc && write && (out.pir == in.pir || out.pii == in.pii || out.e0 == in.e0 ||
+                                          out.e1 == in.e1 || out.e2 == in.e2))
+        return hipErrorInvalidValue;
     StepArgs<R> a;
     a.f = in;
-    a.ophr = ophr;
-    a.ophi = ophi;
-    a.oa0 = oa0;
-    a.oa1 = oa1;
-    a.oa2 = oa2;
+    a.ophr = out.phr;
+    a.ophi = out.phi;
+    a.oa0 = out.a0;
+    a.oa1 = out.a1;
+    a.oa2 = out.a2;
+    a.opr = out.pir;
+    a.opi = out.pii;
+    a.oe0 = out.e0;
+    a.oe1 = out.e1;
+    a.oe2 = out.e2;
     a.N = N;
     a.P = L.P;
     a.dx = (R)L.dx;
@@ -1053,11 +1141,11 @@ template hipError_t launch_step_batch<double>(const PoolLattice*, const WorkItem
 template hipError_t launch_step_batch<float>(const PoolLattice*, const WorkItem*, int, int, int, int, bool,
                                              hipStream_t);
 
-template hipError_t launch_step_tile<double>(const Fields<double>&, double*, double*, double*, double*, double*,
-                                             const LatticeConst&, const StepCoef&, const TileConfig&, const MeasConst*,
-                                             double*, bool, hipStream_t);
-template hipError_t launch_step_tile<float>(const Fields<float>&, float*, float*, float*, float*, float*,
-                                            const LatticeConst&, const StepCoef&, const TileConfig&, const MeasConst*,
-                                            double*, bool, hipStream_t);
+template hipError_t launch_step_tile<double>(const Fields<double>&, const Fields<double>&, const LatticeConst&,
+                                             const StepCoef&, const TileConfig&, const MeasConst*, double*, bool,
+                                             hipStream_t);
+template hipError_t launch_step_tile<float>(const Fields<float>&, const Fields<float>&, const LatticeConst&,
+                                            const StepCoef&, const TileConfig&, const MeasConst*, double*, bool,
+                                            hipStream_t);
 
 }  // namespace ah

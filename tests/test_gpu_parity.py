@@ -475,3 +475,44 @@ def test_fused_diagnostics_equal_separate_pass(ah, precision):
         # the tail: 3 more steps from step 25 measure snapshot 25 only
         more = a.step_measured(3, 5)
         assert [m["step"] for m in more] == [25]
+
+
+@pytest.mark.parametrize("kernel,zchunk", [("tile", 0), ("tile", 3), ("tile", 37), ("tile2", 5)])
+def test_fp32_gauss_in_measured_march(oracle_mod, ah, kernel, zchunk):
+    """FP32 lattices form the Gauss residual in the measured march: E_x, E_y of
+    the -x / -y neighbours pass through LDS (the -x column and -y row of the
+    halo included), E_z of the plane below is carried in a register and
+    loaded afresh at each z-chunk's first plane, and a measured step then
+    writes Pi and E into the other buffer.  N = 37 gives ragged x and y tiles;
+    the norms on a Gauss-violating random snapshot against the oracle, the
+    series of measured steps (every step, then every other) against the
+    oracle's norms of its own snapshots, and the fields after them (with a
+    two-step pass between the measured steps 9 and 12 for kernel tile2)."""
+    N = 37
+    op, gp = both_params(oracle_mod, N, "fp32", m=2.0)
+    st = random_state(N, seed=91).astype(np.float32).astype(np.float64)
+    with ah.Lattice(gp) as lat:
+        lat.set_step_config(kernel, (64, 8), zchunk)
+        lat.set_state(st, 5)
+        gm = lat.measure()
+        series = lat.step_measured(3, 1) + lat.step_measured(6, 3)
+        got = lat.get_state()
+    om = oracle_mod.measure(op, st, 5)
+    assert om["gauss_rel"] > 0.1  # a random snapshot violates the constraint
+    for k in ("gauss_rms", "gauss_max", "gauss_rel"):
+        assert abs(gm[k] - om[k]) <= 1e-11 * abs(om[k]), (k, gm[k], om[k])
+    assert [m["step"] for m in series] == [5, 6, 7, 9, 12]
+    assert all(series[0][k] == gm[k] for k in ("gauss_rms", "gauss_max", "gauss_rel", "energy"))
+    ref = st
+    for m in series:
+        n = m["step"]
+        if n > 5:
+            ref = oracle_mod.step(op, ref, prev, n - prev)
+        prev = n
+        on = oracle_mod.measure(op, ref, n)
+        # the snapshot itself differs from the oracle's by FP32 rounding
+        # (relative ~1e-6 after these few steps); the norms follow it
+        for k in ("gauss_rms", "gauss_rel"):
+            assert abs(m[k] - on[k]) <= 1e-4 * abs(on[k]), (n, k, m[k], on[k])
+    ref = oracle_mod.step(op, ref, prev, 14 - prev)
+    assert max(field_scaled_error(got, ref).values()) <= 1e-4
