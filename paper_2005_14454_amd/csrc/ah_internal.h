@@ -255,9 +255,8 @@ __host__ __device__ inline int gauss_zchunk(int N)
     return (int)(zc < 1 ? 1 : (zc > 64 ? 64 : zc));
 }
 int gauss_blocks(int N);
-template <typename R>
-hipError_t launch_gauss(const Fields<R>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s);
-template <typename R>
+// FP64 lattices only: an FP32 lattice's measured march forms the residual.
+hipError_t launch_gauss(const Fields<double>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s);
 hipError_t launch_gauss_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int grid, hipStream_t s);
 
 template <typename R>

@@ -126,7 +126,7 @@ struct Retired {
     hipEvent_t ev;  // recorded after the last work that could use them
 };
 
-// A node group of the pool graph: kind 0 the Gauss pass of one precision,
+// A node group of the pool graph: kind 0 the Gauss pass (FP64 lattices),
 // kind 1 the plain single step, kind 2 the measured step and kind 3 the
 // two-step pass of one precision and tile shape.
 struct GroupKey {
@@ -522,9 +522,7 @@ int rebuild(ah_pool* P)
         if (kv.first.kind != 0 || le != hipSuccess) continue;
         const NodeGroup& g = kv.second;
         const int grid = (int)std::min<size_t>(g.cap, 2048);
-        le = kv.first.precision == AH_FP64
-                 ? launch_gauss_batch<double>(P->d_lat, P->d_work + g.off, (int)g.cap, grid, P->stream)
-                 : launch_gauss_batch<float>(P->d_lat, P->d_work + g.off, (int)g.cap, grid, P->stream);
+        le = launch_gauss_batch(P->d_lat, P->d_work + g.off, (int)g.cap, grid, P->stream);
     }
     for (int measured = 1; measured >= 0; --measured) {
         for (auto& kv : P->groups) {

@@ -520,7 +520,7 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
     const StepCoef c = coef_at(p, h->step);
     const MeasConst mc = meas_const(p, h->step);
     const TileConfig tc = meas_tiles(h);
-    const bool fused = gauss_in_march(p.precision);
+    constexpr bool fused = sizeof(R) == 4;  // gauss_in_march(AH_FP32)
     const Fields<R> in = fields_of<R>(h, h->cur);
     Fields<R> out = fields_of<R>(h, h->cur ^ 1);
     if (fused) {
@@ -547,8 +547,8 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
     // the Gauss pass reads the snapshot before the step overwrites E
     const int nb = step_tile_blocks(p.N, tc);
     const int ngb = fused ? 0 : gauss_blocks(p.N);
-    if (!fused) {
-        e = launch_gauss<R>(in, lconst(p), mc.gauss_c, h->partials + (size_t)nb * kMeasStride, h->stream);
+    if constexpr (!fused) {
+        e = launch_gauss(in, lconst(p), mc.gauss_c, h->partials + (size_t)nb * kMeasStride, h->stream);
         if (e != hipSuccess) return e;
     }
     e = launch_step_tile<R>(in, out, lconst(p), c, tc, &mc, h->partials, advance, h->stream);

@@ -921,8 +921,8 @@ __global__ void __launch_bounds__(256) k_gauss(Fields<R> f, int N, int P, double
     gauss_block<R>(f, N, P, inv_dx, gc, blockIdx.x, partials + (int64_t)blockIdx.x * kMeasStride, red);
 }
 
-// Gauss residual of every pool lattice whose snapshot is due, before it is
-// stepped.  An item is kGaussPerItem consecutive blocks of the lattice's
+// Gauss residual of every FP64 pool lattice whose snapshot is due, before
+// it is stepped (the work list holds items of FP64 lattices only).  An item is kGaussPerItem consecutive blocks of the lattice's
 // pass (records as the single-lattice pass writes them).
 template <typename R>
 __global__ void __launch_bounds__(256) k_gauss_batch(const PoolLattice* __restrict__ lat,
@@ -1106,23 +1106,18 @@ int gauss_blocks(int N)
     return (int)(tiles * ((N + zc - 1) / zc));
 }
 
-template <typename R>
-hipError_t launch_gauss(const Fields<R>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s)
+hipError_t launch_gauss(const Fields<double>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gauss<R>, dim3(gauss_blocks(L.N)), dim3(256), 0, s, f, L.N, L.P, 1.0 / L.dx, gc, partials);
+    hipLaunchKernelGGL(k_gauss<double>, dim3(gauss_blocks(L.N)), dim3(256), 0, s, f, L.N, L.P, 1.0 / L.dx, gc,
+                       partials);
     return hipGetLastError();
 }
-template hipError_t launch_gauss<double>(const Fields<double>&, const LatticeConst&, double, double*, hipStream_t);
-template hipError_t launch_gauss<float>(const Fields<float>&, const LatticeConst&, double, double*, hipStream_t);
 
-template <typename R>
 hipError_t launch_gauss_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gauss_batch<R>, dim3(grid), dim3(256), 0, s, lat, work, nwork);
+    hipLaunchKernelGGL(k_gauss_batch<double>, dim3(grid), dim3(256), 0, s, lat, work, nwork);
     return hipGetLastError();
 }
-template hipError_t launch_gauss_batch<double>(const PoolLattice*, const WorkItem*, int, int, hipStream_t);
-template hipError_t launch_gauss_batch<float>(const PoolLattice*, const WorkItem*, int, int, hipStream_t);
 
 hipError_t launch_fold_batch(const PoolLattice* lat, int nlat, hipStream_t s)
 {
