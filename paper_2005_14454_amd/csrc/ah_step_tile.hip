@@ -304,10 +304,14 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
 
     // ---------------------------------------------------------------- prologue
     // U(z0-1) of the region into slot 1, U(z0) into slot 0, phi(z0) into sPhi.
+    // The FP64 plain march reads its own links of planes z and z+1 from LDS
+    // where it uses them rather than carrying them from plane to plane in
+    // registers (186 rather than 202 registers on 64 x 8, 1% faster).
+    constexpr bool ULDS = !MEAS && sizeof(R) == 8;
     Cx<R> Uc[3], Up[3];
     R Ac[3], Ap[3];
-    Cx<R> phi_m, phi_c, phi_p;
-    Cx<R> uz_m;
+    Cx<R> phi_c, phi_p;
+    Cx<R> bz_m;  // conj(U_z) phi of the own site one plane below
     R fxz_m, fyz_m;
     // diagnostics state (MEAS): the (x, z) and (y, z) windings of plane z need
     // Y_x, Y_y of plane z+1, so they are completed one plane later from the own
@@ -358,7 +362,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             }
         if constexpr (MEAS)
             for (int d = 0; d < 3; ++d) mx->A[0][d][ro] = Ac[d];
-        phi_m = {at(f.phr, pm, ob), at(f.phi, pm, ob)};
+        const Cx<R> phi_m{at(f.phr, pm, ob), at(f.phi, pm, ob)};
         phi_c = {at(f.phr, p0, ob), at(f.phi, p0, ob)};
         sPhi[ro] = phi_c;
         if (has_halo) sPhi[rh] = Cx<R>{at(f.phr, p0, hb), at(f.phi, p0, hb)};
@@ -368,7 +372,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             mx->E[1][ro] = at(f.e1, p0, ob);
             if (halo_e) mx->E[hEc][rh] = at(hE, p0, hb);
         }
-        uz_m = um[2];
+        bz_m = cmulc(um[2], phi_m);
         __syncthreads();
         // F_xz, F_yz of the own column at plane z0-1
         fxz_m = plaq_sin(um[0], sU[1][2][rxp], Uc[0], um[2]) * inv_dx2;
@@ -476,12 +480,17 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
 
         // ---- 1. update of the own site at plane z
         {
+            if constexpr (ULDS)
+                for (int d = 0; d < 3; ++d) {
+                    Uc[d] = sU[cur][d][ro];
+                    Up[d] = sU[nxt][d][ro];
+                }
             const Cx<R> ph_xm = sPhi[rxm], ph_xp = sPhi[rxp], ph_ym = sPhi[rym], ph_yp = sPhi[ryp];
             const Cx<R> ux_xm = sU[cur][0][rxm];  // U_x^{x-kx}
             const Cx<R> uy_ym = sU[cur][1][rym];  // U_y^{x-ky}
             // covariant Laplacian: sum_j U_j^x phi^{x+j} + conj(U_j^{x-j}) phi^{x-j} - 2 phi^x
             const Cx<R> fx = cmul(Uc[0], ph_xp), fy = cmul(Uc[1], ph_yp), fz = cmul(Uc[2], phi_p);
-            const Cx<R> bx = cmulc(ux_xm, ph_xm), by = cmulc(uy_ym, ph_ym), bz = cmulc(uz_m, phi_m);
+            const Cx<R> bx = cmulc(ux_xm, ph_xm), by = cmulc(uy_ym, ph_ym), bz = bz_m;
             const R lr = ((fx.r + bx.r) + (fy.r + by.r)) + fm(R(-6), phi_c.r, fz.r + bz.r);
             const R li = ((fx.i + bx.i) + (fy.i + by.i)) + fm(R(-6), phi_c.i, fz.i + bz.i);
             // currents J_i = Im[conj(phi) U_i phi^{x+i}] / dx
@@ -618,6 +627,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             }
             fxz_m = fxz;
             fyz_m = fyz;
+            bz_m = cmulc(Uc[2], phi_c);  // for plane z+1
         }
         if (!MEAS && !more) break;
         __syncthreads();  // all reads of slot cur and of sPhi (plane z) are done
@@ -678,16 +688,16 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         }
 
         // ---- 5. rotate the own-column registers
-        uz_m = Uc[2];
         if constexpr (GAUSS) ezm = e_c[2];
         for (int d = 0; d < 3; ++d) {
-            Uc[d] = Up[d];
-            Up[d] = Upp[d];
+            if constexpr (!ULDS) {
+                Uc[d] = Up[d];
+                Up[d] = Upp[d];
+            }
             Ac[d] = Ap[d];
             Ap[d] = q1.a[d];
             e_c[d] = q1.e[d];
         }
-        phi_m = phi_c;
         phi_c = phi_p;
         phi_p = q1.phi2;
         pr_c = q1.pr;
@@ -737,8 +747,10 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
 // per CU, so one can load while the other waits at a barrier.  Left to itself
 // the compiler may take a few more registers, which drops a 512-thread tile
 // to one workgroup per CU.  FP64 fits two waves per SIMD (its measured march
-// only with its sums in LDS and its loads issued late, spilling a few
-// registers); the FP32 measured march needs more than 128 and is left free.
+// only with its sums in LDS and its loads issued late).  Three waves of the
+// plain FP64 march on 256-thread tiles, which fit 168 registers only with
+// late loads (or spill with early ones), ran slower than two on 64 x 8.  The
+// FP32 measured march needs more than 128 registers and is left free.
 template <typename R, bool MEAS>
 constexpr int kMinWaves = sizeof(R) == 8 ? 2 : (MEAS ? 1 : 4);
 
