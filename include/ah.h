@@ -124,8 +124,8 @@ int ah_stability_margin(const ah_params* p, int64_t step, double* mu);
 
 /* Device bytes one lattice needs: 20 field arrays (the 10 state fields twice:
  * a single step drifts phi and A into the other buffer, a two-step pass and
- * an FP32 measured step write all ten) of N^3 reals each, plus reduction
- * scratch.  AH_E_INVAL on bad params. */
+ * a measured step write all ten) of N^3 reals each, plus reduction scratch.
+ * AH_E_INVAL on bad params. */
 int ah_required_bytes(const ah_params* p, size_t* bytes);
 
 /* Create a handle on the current HIP device.
@@ -285,10 +285,9 @@ int ah_tune_load(const char* path);
 /* A pool keeps many independent lattices (any N, precision, expansion
  * history; compact action) resident in one device arena and advances all
  * active ones together: each ah_pool_advance step is one replay of a HIP
- * graph holding the Gauss-residual pass of the FP64 lattices whose snapshot
- * is due, the measured step of the due lattices (for FP32 it forms the Gauss
- * residual itself) and its fixed-order fold, the plain
- * step of every other active lattice (one kernel node per precision and
+ * graph holding the measured step of the lattices whose snapshot is due (it
+ * forms every diagnostic, the Gauss residual included) and its fixed-order
+ * fold, the plain step of every other active lattice (one kernel node per precision and
  * tile shape, one block per (lattice, tile) work item) and a counter update;
  * an FP32 lattice whose next two snapshots are both not due takes a
  * two-step pass instead (AH_KERNEL_TILE2; 64 x 8 unless its tuning entry
@@ -320,10 +319,9 @@ typedef struct ah_pool_info {
  * pool creates its own stream (graph capture needs a non-null stream). */
 int ah_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, ah_pool** out);
 
-/* Device bytes a request occupies in a pool: fields (15 arrays of N^2 rows
- * of the pitched length; 20 for FP32, whose Pi and E are double-buffered for
- * its two-step passes and measured steps), diagnostics records, the
- * (nsteps+1)-row coefficient table, the series. */
+/* Device bytes a request occupies in a pool: fields (20 arrays of N^2 rows
+ * of the pitched length: phi, A, Pi and E each double-buffered), diagnostics
+ * records, the (nsteps+1)-row coefficient table, the series. */
 int ah_pool_footprint(const ah_params* p, int64_t nsteps, int32_t measure_every, size_t* bytes);
 
 /* Admit a lattice: random-phase IC from `seed` (as ah_init), `nsteps` steps,

@@ -171,8 +171,7 @@ enum CoefSlot { C_P1 = 0, C_P2, C_E1, C_E2, C_LAMH, C_KAPPA, C_INV2E2F, C_LAMQ, 
 struct PoolLattice {
     void* pp[2][5];        // ping-pong phi_re, phi_im, A0, A1, A2; counter[2] names the current one
     void* mom[2][5];       // Pi_re, Pi_im, E0, E1, E2; counter[3] names the current one (updated in place by a
-                           // plain single step; a two-step pass and an FP32 measured step write the other);
-                           // mom[1] only for FP32 lattices and with two-step passes
+                           // plain single step; a two-step pass and a measured step write the other)
     const double* coef;    // (nsteps + 1) rows of kCoefStride doubles
     int64_t* counter;      // kCounterWords words: local step k, measurements taken, phi/A buffer, Pi/E buffer
     double* partials;      // diagnostics records of this lattice
@@ -181,8 +180,7 @@ struct PoolLattice {
     int64_t series_cap;
     int N, tiles_x, tiles_y, zchunk;     // step tiling
     int meas_zchunk, meas_blocks, measure_every, precision;
-    int gauss_blocks, P;     // Gauss records follow the meas_blocks step records (0: the Gauss residual is in
-                             // the measured march's records); P: row pitch
+    int P;                   // row pitch
     int mtiles_x, mtiles_y;  // tiling of the measured step (measured_tile), z-chunks of meas_zchunk
     int two_tiles_x, two_tiles_y, two_zchunk;  // tiling of the two-step pass; two_zchunk == 0: none
     int compact;
@@ -193,7 +191,6 @@ struct WorkItem {
 };
 constexpr int kXcdCount = 8;           // XCDs of the device; block b runs on XCD b % 8
 constexpr int kCounterWords = 4;       // int64 words of a pool lattice's counter
-constexpr int kGaussPerItem = 8;       // Gauss-pass blocks of one lattice per pool work item
 constexpr int kSeriesStride = 18;      // M_COUNT sums + step index + pad
 static_assert(M_COUNT + 1 <= kSeriesStride, "a series record holds the sums and the step index");
 
@@ -221,18 +218,13 @@ hipError_t launch_step(const Fields<R>& in, R* ophr, R* ophi, R* oa0, R* oa1, R*
 
 // Tiled step from `in` to `out`: phi and A into out's (other) buffers, Pi
 // and E into out's, which may be in's (an update in place).  With mc !=
-// nullptr also the diagnostics of the snapshot read (one record per workgroup
-// into partials, in tile order); for FP32 they include the Gauss residual,
-// and a measured FP32 step then needs Pi and E out of place (else
-// hipErrorInvalidValue).  write = false leaves the fields untouched
-// (diagnostics only).
+// nullptr also the diagnostics of the snapshot read, Gauss residual included
+// (one record per workgroup into partials, in tile order); a measured step
+// then needs Pi and E out of place (else hipErrorInvalidValue).  write =
+// false leaves the fields untouched (diagnostics only).
 template <typename R>
 hipError_t launch_step_tile(const Fields<R>& in, const Fields<R>& out, const LatticeConst& L, const StepCoef& c,
                             const TileConfig& tc, const MeasConst* mc, double* partials, bool write, hipStream_t s);
-
-// Whether the measured march of a lattice of this precision forms the Gauss
-// residual itself (FP32) or leaves it to the Gauss pass (FP64).
-__host__ __device__ inline bool gauss_in_march(int precision) { return precision == AH_FP32; }
 
 // Two steps in one pass: snapshot n of `in` to snapshot n+2 of `out` (all
 // ten fields in other buffers), with the coefficients of steps n and n+1.
@@ -243,21 +235,6 @@ hipError_t launch_step2_tile(const Fields<R>& in, const Fields<R>& out, const La
 // workgroups (= diagnostics records) of one tiled launch
 int step_tile_blocks(int N, const TileConfig& tc);
 
-// Gauss-residual pass: 64 x 4 (x, y) tiles marching z-chunks of
-// gauss_zchunk(N) planes, one workgroup of 256 threads and one record (Gauss
-// slots only) per (tile, chunk): gauss_blocks(N) of them.  The chunks are as
-// long as 2048 workgroups allow, from 1 plane (small lattices, which then
-// still have enough workgroups) to 64.
-__host__ __device__ inline int gauss_zchunk(int N)
-{
-    const int64_t tiles = (int64_t)((N + 63) / 64) * ((N + 3) / 4);
-    int64_t zc = (int64_t)N * tiles / 2048;
-    return (int)(zc < 1 ? 1 : (zc > 64 ? 64 : zc));
-}
-int gauss_blocks(int N);
-// FP64 lattices only: an FP32 lattice's measured march forms the residual.
-hipError_t launch_gauss(const Fields<double>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s);
-hipError_t launch_gauss_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int grid, hipStream_t s);
 
 template <typename R>
 hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int tx, int ty, int grid,

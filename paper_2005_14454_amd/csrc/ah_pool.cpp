@@ -6,8 +6,7 @@
 // diagnostics records and its measurement series inside the arena, plus a
 // descriptor and a counter (step, measurements taken, buffer parities) in
 // pool metadata.  The graph replayed per step is
-//     Gauss pass (FP64 lattices whose snapshot is due; the FP32 measured
-//     step forms it itself) and measured step -> fold
+//     measured step (lattices whose snapshot is due) -> fold
 //     -> single step and two-step pass (one node per precision and tile
 //     shape) -> advance counters
 // and every kernel reads the lattice's own counter, so the same graph serves
@@ -75,15 +74,14 @@ struct Slot {
 struct Footprint {
     size_t field, fields, partials, coef, series, total;
     TileConfig meas;  // tiling of the measured step
-    int mom_buffers;  // Pi/E buffers: 2 for FP32 lattices and with two-step passes
-    int meas_blocks, gauss_blocks;
+    int meas_blocks;
     int64_t series_cap;
 };
 
-// Bytes of one pool lattice (15 fields, 20 where Pi and E are
-// double-buffered: with two-step passes and for FP32 lattices, whose measured
-// step writes them out of place); total = SIZE_MAX when nsteps is too large
-// for its coefficient table to be addressed at all.
+// Bytes of one pool lattice (20 fields: phi and A ping-pong, and so do Pi
+// and E, which a two-step pass and a measured step write out of place);
+// total = SIZE_MAX when nsteps is too large for its coefficient table to be
+// addressed at all.
 Footprint footprint(const ah_params& p, const ah_step_config& cfg, const TileConfig& two, int64_t nsteps,
                     int measure_every)
 {
@@ -94,12 +92,10 @@ Footprint footprint(const ah_params& p, const ah_step_config& cfg, const TileCon
     }
     const size_t stored = (size_t)p.N * p.N * row_pitch(p.N, p.precision);
     f.field = align_up(stored * (p.precision == AH_FP64 ? 8 : 4));
-    f.mom_buffers = (two.zchunk > 0 || gauss_in_march(p.precision)) ? 2 : 1;
-    f.fields = (size_t)(10 + 5 * f.mom_buffers) * f.field;
+    f.fields = 20 * f.field;
     f.meas = measured_tiling(p, cfg);
     f.meas_blocks = step_tile_blocks(p.N, f.meas);
-    f.gauss_blocks = gauss_in_march(p.precision) ? 0 : gauss_blocks(p.N);
-    f.partials = align_up((size_t)(f.meas_blocks + f.gauss_blocks) * kMeasStride * sizeof(double));
+    f.partials = align_up((size_t)f.meas_blocks * kMeasStride * sizeof(double));
     f.coef = align_up((size_t)(nsteps + 1) * kCoefStride * sizeof(double));
     f.series_cap = (measure_every > 0 ? nsteps / measure_every + 1 : 0) + 1;
     f.series = align_up((size_t)f.series_cap * kSeriesStride * sizeof(double));
@@ -126,9 +122,9 @@ struct Retired {
     hipEvent_t ev;  // recorded after the last work that could use them
 };
 
-// A node group of the pool graph: kind 0 the Gauss pass (FP64 lattices),
-// kind 1 the plain single step, kind 2 the measured step and kind 3 the
-// two-step pass of one precision and tile shape.
+// A node group of the pool graph: kind 1 the plain single step, kind 2 the
+// measured step and kind 3 the two-step pass of one precision and tile
+// shape.
 struct GroupKey {
     int kind, precision, tx, ty;
     bool operator<(const GroupKey& o) const
@@ -370,8 +366,8 @@ hipError_t retire(ah_pool* P, hipGraphExec_t exec, hipGraph_t graph, void* buf)
 // uploads are ordered after the replays already queued, which keep reading
 // the old descriptors and lists until then.
 //
-// The graph has a Gauss node for FP64 lattices and one step node (plain and
-// measured) per (precision, tile shape), each over a fixed-capacity region
+// The graph has one step node (plain, measured, two-step) per (precision,
+// tile shape), each over a fixed-capacity region
 // of the work list whose unused items are empty.  An admission or a release
 // that fits the captured capacities only rewrites the lists; a new group or
 // a list beyond its capacity (or far below it) captures anew, with room for
@@ -390,17 +386,9 @@ int rebuild(ah_pool* P)
             desc[i].counter = P->d_counters + kCounterWords * i;
         }
     }
-    // the lists each group needs now: Gauss items of FP64 lattices; step items
-    // per (precision, tile shape) in kXcdCount bands
-    std::map<GroupKey, std::vector<WorkItem>> gauss_need;
+    // the lists each group needs now: step items per (precision, tile shape)
+    // in kXcdCount bands
     std::map<GroupKey, std::array<std::vector<WorkItem>, kXcdCount>> step_need;
-    for (int i = 0; i < nslot; ++i) {
-        const Slot& s = P->slots[i];
-        if (!s.used) continue;
-        if (s.d.gauss_blocks == 0) continue;  // the measured march forms the residual
-        auto& g = gauss_need[GroupKey{0, s.p.precision, 0, 0}];
-        for (int t = 0; t < s.d.gauss_blocks; t += kGaussPerItem) g.push_back({i, t});
-    }
     // step groups: kind 1 the plain step per (precision, tile shape), kind 2
     // the measured step per (precision, measured tile shape), kind 3 the
     // two-step pass per (precision, tile shape)
@@ -444,7 +432,6 @@ int rebuild(ah_pool* P)
     }
     // items each group needs (a step group: kXcdCount bands of the longest band's length)
     std::map<GroupKey, size_t> need;
-    for (auto& kv : gauss_need) need[kv.first] = kv.second.size();
     for (auto& kv : step_need) {
         size_t len = 0;
         for (auto& b : kv.second) len = std::max(len, b.size());
@@ -465,7 +452,7 @@ int rebuild(ah_pool* P)
         std::map<GroupKey, NodeGroup> groups;
         size_t off = 0;
         auto add = [&](const GroupKey& k, size_t n) {
-            const size_t unit = k.kind != 0 ? (size_t)kXcdCount * 32 : 256;
+            const size_t unit = (size_t)kXcdCount * 32;
             size_t cap = std::max<size_t>(n + n / 4, unit);
             cap = (cap + unit - 1) / unit * unit;
             groups[k] = NodeGroup{off, cap};
@@ -492,7 +479,6 @@ int rebuild(ah_pool* P)
     size_t total = 0;
     for (auto& kv : P->groups) total = std::max(total, kv.second.off + kv.second.cap);
     std::vector<WorkItem> work(total, WorkItem{-1, 0});
-    for (auto& kv : gauss_need) std::copy(kv.second.begin(), kv.second.end(), work.begin() + P->groups[kv.first].off);
     for (auto& kv : step_need) {
         const NodeGroup& g = P->groups[kv.first];
         const size_t per_band = g.cap / kXcdCount;
@@ -515,15 +501,8 @@ int rebuild(ah_pool* P)
     e = hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return phip(P, e, "pool graph capture begin");
     hipError_t le = hipSuccess;
-    // Gauss residual of the due FP64 snapshots (read-only, before anything is
-    // overwritten), measured steps of the due lattices, their fold, the plain
-    // steps of all others, the counter update
-    for (auto& kv : P->groups) {
-        if (kv.first.kind != 0 || le != hipSuccess) continue;
-        const NodeGroup& g = kv.second;
-        const int grid = (int)std::min<size_t>(g.cap, 2048);
-        le = launch_gauss_batch(P->d_lat, P->d_work + g.off, (int)g.cap, grid, P->stream);
-    }
+    // measured steps of the due lattices, their fold, the plain steps of all
+    // others, the counter update
     for (int measured = 1; measured >= 0; --measured) {
         for (auto& kv : P->groups) {
             if (kv.first.kind != (measured ? 2 : 1) || le != hipSuccess) continue;
@@ -720,7 +699,7 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
                 d.pp[b][c] = base;
                 base += fp.field;
             }
-        for (int b = 0; b < fp.mom_buffers; ++b)
+        for (int b = 0; b < 2; ++b)
             for (int c = 0; c < 5; ++c) {
                 d.mom[b][c] = base;
                 base += fp.field;
@@ -748,7 +727,6 @@ int ah_pool_submit(ah_pool* P, const ah_params* p, uint64_t seed, int64_t nsteps
             d.two_tiles_y = (p->N + two.ty - 1) / two.ty;
             d.two_zchunk = two.zchunk;
         }
-        d.gauss_blocks = fp.gauss_blocks;
         d.measure_every = measure_every;
         d.precision = p->precision;
         d.compact = 1;

@@ -197,7 +197,6 @@ size_t partial_records(const ah_params& p)
         const int64_t t = (int64_t)((N + s[0] - 1) / s[0]) * ((N + s[1] - 1) / s[1]) * tz;
         if (t > best) best = t;
     }
-    best += gauss_blocks(N);
     return (size_t)(best > kMeasBlocks ? best : kMeasBlocks);
 }
 
@@ -509,10 +508,8 @@ TileConfig meas_tiles(const ah_handle* h)
 }
 
 // Diagnostics of the current snapshot folded into dst[M_COUNT] (device), and
-// with `advance` the step of that snapshot in the same pass.  FP32: the march
-// forms the Gauss residual too, and the step writes Pi and E into the other
-// buffer; FP64: a read-only Gauss pass runs first and the step updates Pi and
-// E in place.
+// with `advance` the step of that snapshot in the same pass, which writes Pi
+// and E into the other buffer (the Gauss residual reads E of neighbours).
 template <typename R>
 hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
 {
@@ -520,17 +517,14 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
     const StepCoef c = coef_at(p, h->step);
     const MeasConst mc = meas_const(p, h->step);
     const TileConfig tc = meas_tiles(h);
-    constexpr bool fused = sizeof(R) == 4;  // gauss_in_march(AH_FP32)
     const Fields<R> in = fields_of<R>(h, h->cur);
     Fields<R> out = fields_of<R>(h, h->cur ^ 1);
-    if (fused) {
-        const int om = h->curm ^ 1;
-        out.pir = (R*)h->mom[om][0];
-        out.pii = (R*)h->mom[om][1];
-        out.e0 = (R*)h->mom[om][2];
-        out.e1 = (R*)h->mom[om][3];
-        out.e2 = (R*)h->mom[om][4];
-    }
+    const int om = h->curm ^ 1;
+    out.pir = (R*)h->mom[om][0];
+    out.pii = (R*)h->mom[om][1];
+    out.e0 = (R*)h->mom[om][2];
+    out.e1 = (R*)h->mom[om][3];
+    out.e2 = (R*)h->mom[om][4];
     hipError_t e;
     if (advance && h->timing) {
         if (h->ev_used + 2 > h->ev.size()) {
@@ -544,13 +538,7 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
         e = hipEventRecord(h->ev[h->ev_used], h->stream);
         if (e != hipSuccess) return e;
     }
-    // the Gauss pass reads the snapshot before the step overwrites E
     const int nb = step_tile_blocks(p.N, tc);
-    const int ngb = fused ? 0 : gauss_blocks(p.N);
-    if constexpr (!fused) {
-        e = launch_gauss(in, lconst(p), mc.gauss_c, h->partials + (size_t)nb * kMeasStride, h->stream);
-        if (e != hipSuccess) return e;
-    }
     e = launch_step_tile<R>(in, out, lconst(p), c, tc, &mc, h->partials, advance, h->stream);
     if (e != hipSuccess) return e;
     if (advance && h->timing) {
@@ -561,11 +549,11 @@ hipError_t measured_pass(ah_handle* h, double* dst, bool advance)
         h->ev_measured.push_back(1);
         h->ev_steps.push_back(1);
     }
-    e = launch_measure_final(h->partials, nb + ngb, dst, h->stream);
+    e = launch_measure_final(h->partials, nb, dst, h->stream);
     if (e != hipSuccess) return e;
     if (advance) {
         h->cur ^= 1;
-        if (fused) h->curm ^= 1;
+        h->curm ^= 1;
         h->step += 1;
     }
     return hipSuccess;

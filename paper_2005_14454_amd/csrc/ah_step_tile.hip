@@ -51,8 +51,8 @@ struct StepArgs {
     R* oa0;
     R* oa1;
     R* oa2;
-    // Pi and E outputs: f's own arrays for an update in place (the FP32
-    // measured march needs other ones)
+    // Pi and E outputs: f's own arrays for an update in place (the measured
+    // march needs other ones)
     R* opr;
     R* opi;
     R* oe0;
@@ -85,6 +85,8 @@ struct MeasShared {
     // FP32 lattices: E_x, E_y of plane z (own sites, and the -x / -y halo)
     // for the Gauss residual
     R E[2][sizeof(R) == 4 ? RS : 1];
+    // FP64 lattices: each wave's Gauss sums, added plane by plane
+    double gacc[sizeof(R) == 8 ? TX * TY / 64 : 1][4];
     // FP64 lattices: each thread's running diagnostics sums (kept here rather
     // than in registers, which the FP64 measured march runs out of)
     double acc[kMarchSums][sizeof(R) == 8 ? TX * TY : 1];
@@ -215,12 +217,12 @@ __device__ inline double wave_max(double v)
 // the snapshot being read (section 2 estimators, energy split, windings),
 // writing the workgroup's fixed-order sums to `record`.  The Gauss residual
 // reads E at the -x and -y neighbours, which a neighbouring workgroup of a
-// pass that updates E in place may already have overwritten.  The FP32
-// measured march therefore writes Pi and E out of place (a.opr .. a.oe2) and
-// forms the residual itself, passing E_x and E_y of each plane through LDS and
-// carrying E_z of the plane below in a register.  The FP64 one updates them in
-// place (its LDS holds two workgroups per CU only without that exchange) and
-// leaves the residual to a read-only pass (k_gauss) that runs first.
+// pass that updated E in place could already have overwritten, so a measured
+// march that steps writes Pi and E out of place (a.opr .. a.oe2).  E_z of the
+// plane below is carried in a register; FP32 passes E_x and E_y of each plane
+// through LDS, FP64 (whose LDS holds two workgroups per CU only without that
+// exchange) loads the two neighbours with the plane's Pi and E and adds each
+// wave's sums of a plane into an LDS slot of the wave.
 // All threads of the workgroup call this with the same arguments; it
 // synchronises the workgroup internally.
 template <typename R, int TX, int TY, bool MEAS>
@@ -242,7 +244,8 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     const int N = a.N;
     const R dx = a.dx, sigma2 = a.sigma2, cP1 = a.cP1, cP2 = a.cP2, cE1 = a.cE1, cE2 = a.cE2;
     const R lamh = a.lamh, kappa = a.kappa, deta = a.deta;
-    constexpr bool GAUSS = MEAS && sizeof(R) == 4;  // Gauss residual in this march
+    constexpr bool GAUSS = MEAS;                  // Gauss residual in this march
+    constexpr bool GLDS = GAUSS && sizeof(R) == 4;  // its -x / -y E through LDS (FP64: loads)
     R* wpr = a.opr;
     R* wpi = a.opi;
     R* we0 = a.oe0;
@@ -292,7 +295,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     // column, E_y on the -y row
     const bool halo_ex = has_halo && hrx == 0 && hry >= 1 && hry <= TY;
     const bool halo_ey = has_halo && hry == 0 && hrx >= 1 && hrx <= TX;
-    const bool halo_e = GAUSS && (halo_ex || halo_ey);
+    const bool halo_e = GLDS && (halo_ex || halo_ey);
     const R* hE = halo_ex ? f.e0 : f.e1;
     const int hEc = halo_ex ? 0 : 1;
 
@@ -307,7 +310,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     // The FP64 plain march reads its own links of planes z and z+1 from LDS
     // where it uses them rather than carrying them from plane to plane in
     // registers (186 rather than 202 registers on 64 x 8, 1% faster).
-    constexpr bool ULDS = !MEAS && sizeof(R) == 8;
+    constexpr bool ULDS = sizeof(R) == 8;
     Cx<R> Uc[3], Up[3];
     R Ac[3], Ap[3];
     Cx<R> phi_c, phi_p;
@@ -326,7 +329,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             return link_phase_f(cmulc(ph, cmul(U, pn)), ph, pn, av, ma.dx);
     };
     // sums of the march: M_KIN .. M_RHOL (kMarchSums slots, FP64) and the
-    // exact counts M_WABS, M_NONFIN (integers); the Gauss slots belong to k_gauss
+    // exact counts M_WABS, M_NONFIN (integers); the Gauss sums follow
     double acc_reg[kMarchSums];
     auto acc = [&](int k) -> double& {
         if constexpr (sizeof(R) == 8)
@@ -341,6 +344,11 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     // E_z of the own site one plane below
     double g2 = 0.0, d2 = 0.0, c2 = 0.0, gmax = 0.0;
     R ezm = R(0);
+    // FP64: E_x at x - kx and E_y at x - ky of plane z, loaded with the plane's
+    // Pi and E (Pi and E go to other buffers, so these are the snapshot's)
+    R ex_xm = R(0), ey_ym = R(0);
+    const uint32_t ob_xm = gxw == 0 ? ob + (uint32_t)(N - 1) : ob - 1u;
+    const uint32_t ob_ym = gyw == 0 ? ob + (uint32_t)(N - 1) * (uint32_t)P : ob - (uint32_t)P;
     const double inv_dx64 = 1.0 / ma.dx;
     {
         const int64_t pm = plane_of(z0 - 1), p0 = plane_of(z0);
@@ -366,12 +374,15 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         phi_c = {at(f.phr, p0, ob), at(f.phi, p0, ob)};
         sPhi[ro] = phi_c;
         if (has_halo) sPhi[rh] = Cx<R>{at(f.phr, p0, hb), at(f.phi, p0, hb)};
-        if constexpr (GAUSS) {
-            ezm = at(f.e2, pm, ob);
+        if constexpr (GAUSS) ezm = at(f.e2, pm, ob);
+        if constexpr (GLDS) {
             mx->E[0][ro] = at(f.e0, p0, ob);
             mx->E[1][ro] = at(f.e1, p0, ob);
             if (halo_e) mx->E[hEc][rh] = at(hE, p0, hb);
         }
+        if constexpr (GAUSS && !GLDS)
+            if ((tid & 63) == 0)
+                for (int k = 0; k < 4; ++k) mx->gacc[tid >> 6][k] = 0.0;
         bz_m = cmulc(um[2], phi_m);
         __syncthreads();
         // F_xz, F_yz of the own column at plane z0-1
@@ -400,6 +411,10 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
     const int64_t pz0 = (int64_t)z0 * NN;
     R pr_c = ld_stream(f.pir + pz0 + ob), pi_c = ld_stream(f.pii + pz0 + ob);
     R e_c[3] = {ld_stream(f.e0 + pz0 + ob), ld_stream(f.e1 + pz0 + ob), ld_stream(f.e2 + pz0 + ob)};
+    if constexpr (GAUSS && !GLDS) {
+        ex_xm = at(f.e0, pz0, ob_xm);
+        ey_ym = at(f.e1, pz0, ob_ym);
+    }
 
     // Operands prefetched for iteration t: A of plane t+2 (own and halo), phi
     // of plane t+1 (halo) and t+2 (own), Pi and E of plane t+1 (own).  The
@@ -416,7 +431,8 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
         R a[3], ha[3];
         Cx<R> hphi, phi2;
         R pr, pi, e[3];
-        R he;  // GAUSS: the halo E of plane t+1
+        R he;          // GLDS: the halo E of plane t+1
+        R exm, eym;    // FP64 Gauss: E_x at x - kx, E_y at x - ky of plane t+1
     };
     auto prefetch = [&](int t, Pre& q) {
         const int64_t p2 = plane_of(t + 2), p1 = plane_of(t + 1);
@@ -429,8 +445,12 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             q.ha[2] = at(f.a2, p2, hb);
             q.hphi = {at(f.phr, p1, hb), at(f.phi, p1, hb)};
         }
-        if constexpr (GAUSS)
+        if constexpr (GLDS)
             if (halo_e) q.he = at(hE, p1, hb);
+        if constexpr (GAUSS && !GLDS) {
+            q.exm = at(f.e0, p1, ob_xm);
+            q.eym = at(f.e1, p1, ob_ym);
+        }
         q.phi2 = {at(f.phr, p2, ob), at(f.phi, p2, ob)};
         q.pr = ld_stream(f.pir + p1 + ob);
         q.pi = ld_stream(f.pii + p1 + ob);
@@ -485,6 +505,32 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                     Uc[d] = sU[cur][d][ro];
                     Up[d] = sU[nxt][d][ro];
                 }
+            if constexpr (GAUSS && !GLDS) {
+                // FP64: the Gauss residual of the site first, while few values
+                // are live, and the wave's sums of this plane added to its slot
+                double gs[4] = {0.0, 0.0, 0.0, 0.0};
+                if (active) {
+                    const double dv = (((double)e_c[0] - (double)ex_xm) * inv_dx64 +
+                                       ((double)e_c[1] - (double)ey_ym) * inv_dx64) +
+                                      ((double)e_c[2] - (double)ezm) * inv_dx64;
+                    const double crho = ma.gauss_c * ((double)phi_c.r * (double)pi_c -
+                                                      (double)phi_c.i * (double)pr_c);
+                    const double G = dv - crho;
+                    gs[0] = G * G;
+                    gs[1] = dv * dv;
+                    gs[2] = crho * crho;
+                    gs[3] = fabs(G);
+                }
+                const double v0 = wave_sum(gs[0]), v1 = wave_sum(gs[1]), v2 = wave_sum(gs[2]),
+                             v3 = wave_max(gs[3]);
+                if ((tid & 63) == 0) {
+                    double* ga = mx->gacc[tid >> 6];
+                    ga[0] += v0;
+                    ga[1] += v1;
+                    ga[2] += v2;
+                    ga[3] = fmax(ga[3], v3);
+                }
+            }
             const Cx<R> ph_xm = sPhi[rxm], ph_xp = sPhi[rxp], ph_ym = sPhi[rym], ph_yp = sPhi[ryp];
             const Cx<R> ux_xm = sU[cur][0][rxm];  // U_x^{x-kx}
             const Cx<R> uy_ym = sU[cur][1][rym];  // U_y^{x-ky}
@@ -609,7 +655,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                     const double rho = ((kin + grad) + pot_e) + (el + mag);
                     acc(M_PL) += pres * L;
                     acc(M_RHOL) += rho * L;
-                    if constexpr (GAUSS) {
+                    if constexpr (GLDS) {
                         // G = sum_i (E_i^x - E_i^{x-i}) / dx - c Im[conj(phi) Pi] of the
                         // snapshot, in FP64 from the exactly widened stored values
                         const double dv = (((double)e_c[0] - (double)mx->E[0][rxm]) * inv_dx64 +
@@ -660,7 +706,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                 sPhi[rh] = hphi;
             }
             sPhi[ro] = rphi;
-            if constexpr (GAUSS) {
+            if constexpr (GLDS) {
                 mx->E[0][ro] = q1.e[0];
                 mx->E[1][ro] = q1.e[1];
                 if (halo_e) mx->E[hEc][rh] = q1.he;
@@ -676,8 +722,9 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                 // own Y_x, Y_y of plane z1 complete the (x, z), (y, z) windings
                 // of the chunk's last plane
                 const Cx<R> px = sPhi[rxp], py = sPhi[ryp];
-                const float yx_n = phase(phi_p, Up[0], px, Ap[0]);
-                const float yy_n = phase(phi_p, Up[1], py, Ap[1]);
+                const Cx<R> ux_n = ULDS ? sU[nxt][0][ro] : Up[0], uy_n = ULDS ? sU[nxt][1][ro] : Up[1];
+                const float yx_n = phase(phi_p, ux_n, px, Ap[0]);
+                const float yy_n = phase(phi_p, uy_n, py, Ap[1]);
                 if (active) {
                     const auto& sYb = mx->Y[zs];
                     wabs += abs(winding_of(yx_b, sYb[2][rxp], yx_n, yz_b, thxz_b)) +
@@ -689,6 +736,10 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
 
         // ---- 5. rotate the own-column registers
         if constexpr (GAUSS) ezm = e_c[2];
+        if constexpr (GAUSS && !GLDS) {
+            ex_xm = q1.exm;
+            ey_ym = q1.eym;
+        }
         for (int d = 0; d < 3; ++d) {
             if constexpr (!ULDS) {
                 Uc[d] = Up[d];
@@ -721,7 +772,15 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             red[wv][M_NONFIN] = rn;
         }
         if constexpr (GAUSS) {
-            const double v[4] = {wave_sum(g2), wave_sum(d2), wave_sum(c2), wave_max(gmax)};
+            double v[4];
+            if constexpr (GLDS) {
+                v[0] = wave_sum(g2);
+                v[1] = wave_sum(d2);
+                v[2] = wave_sum(c2);
+                v[3] = wave_max(gmax);
+            } else {
+                for (int k = 0; k < 4; ++k) v[k] = mx->gacc[wv][k];  // lane 0's own slot
+            }
             if (lane == 0) {
                 red[wv][M_G2] = v[0];
                 red[wv][M_DIV2] = v[1];
@@ -823,8 +882,8 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(con
     a.oa0 = (R*)L.pp[cur ^ 1][2];
     a.oa1 = (R*)L.pp[cur ^ 1][3];
     a.oa2 = (R*)L.pp[cur ^ 1][4];
-    // Pi and E in place, but out of place for the FP32 measured march
-    const int om = (MEAS && sizeof(R) == 4) ? curm ^ 1 : curm;
+    // Pi and E in place, but out of place for the measured march
+    const int om = MEAS ? curm ^ 1 : curm;
     a.opr = (R*)L.mom[om][0];
     a.opi = (R*)L.mom[om][1];
     a.oe0 = (R*)L.mom[om][2];
@@ -862,103 +921,6 @@ __global__ void __launch_bounds__(TX* TY, (kMinWaves<R, MEAS>)) k_step_batch(con
 }
 
 
-// ------------------------------------------------------------ Gauss residual
-
-// Discrete Gauss law of the snapshot: G^x = sum_i (E_i^x - E_i^{x-i})/dx
-// - c Im[conj(phi^x) Pi^x] on the stored half-step fields, in FP64 from the
-// exactly widened stored values.  A workgroup of 256 threads owns a
-// kGaussTX x kGaussTY (x, y) tile and marches a chunk of gauss_zchunk(N)
-// planes of it (block = tile + tiles * chunk), carrying E_z of the plane
-// below in a register, so every field is read from memory once; it writes
-// one record (Gauss slots only).
-constexpr int kGaussTX = 64, kGaussTY = 4;
-static_assert(kGaussTX * kGaussTY == 256, "one site of a plane per thread");
-
-template <typename R>
-__device__ void gauss_block(const Fields<R>& f, int N, int P, double inv_dx, double gc, int block,
-                            double* __restrict__ record, double* red)
-{
-    const int tiles_x = (N + kGaussTX - 1) / kGaussTX, tiles_y = (N + kGaussTY - 1) / kGaussTY;
-    const int zc = gauss_zchunk(N);
-    const int t = block % (tiles_x * tiles_y), c = block / (tiles_x * tiles_y);
-    const int x = (t % tiles_x) * kGaussTX + (int)(threadIdx.x % kGaussTX);
-    const int y = (t / tiles_x) * kGaussTY + (int)(threadIdx.x / kGaussTX);
-    const int z0 = c * zc, z1 = min(z0 + zc, N);
-    double g2 = 0.0, d2 = 0.0, c2 = 0.0, gmax = 0.0;
-    if (x < N && y < N) {
-        const int64_t NP = (int64_t)N * P;
-        const int64_t xy = x + (int64_t)y * P;
-        const int64_t dxm = x == 0 ? N - 1 : -1;                      // to x - kx
-        const int64_t dym = y == 0 ? (int64_t)(N - 1) * P : -(int64_t)P;  // to x - ky
-        int64_t o = xy + (int64_t)z0 * NP;
-        double ezm = (double)f.e2[xy + (int64_t)(z0 == 0 ? N - 1 : z0 - 1) * NP];  // E_z below
-        for (int z = z0; z < z1; ++z, o += NP) {
-            const double ez = (double)f.e2[o];
-            const double dv = (((double)f.e0[o] - (double)f.e0[o + dxm]) * inv_dx +
-                               ((double)f.e1[o] - (double)f.e1[o + dym]) * inv_dx) +
-                              (ez - ezm) * inv_dx;
-            const double crho = gc * ((double)f.phr[o] * (double)f.pii[o] - (double)f.phi[o] * (double)f.pir[o]);
-            const double G = dv - crho;
-            g2 += G * G;
-            d2 += dv * dv;
-            c2 += crho * crho;
-            gmax = fmax(gmax, fabs(G));
-            ezm = ez;
-        }
-    }
-    // fixed-order block reduction
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const double v[4] = {wave_sum(g2), wave_sum(d2), wave_sum(c2), wave_max(gmax)};
-    if (lane == 0)
-        for (int k = 0; k < 4; ++k) red[wv * 4 + k] = v[k];
-    __syncthreads();
-    if (threadIdx.x < kMeasStride) {
-        const int k = threadIdx.x;
-        double r = 0.0;
-        const int slot = k == M_G2 ? 0 : k == M_DIV2 ? 1 : k == M_CRHO2 ? 2 : k == M_GMAX ? 3 : -1;
-        if (slot >= 0) {
-            r = red[slot];
-            for (int w = 1; w < 4; ++w) r = (slot == 3) ? fmax(r, red[w * 4 + slot]) : r + red[w * 4 + slot];
-        }
-        record[k] = r;
-    }
-    __syncthreads();
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_gauss(Fields<R> f, int N, int P, double inv_dx, double gc,
-                                               double* partials)
-{
-    __shared__ double red[16];
-    gauss_block<R>(f, N, P, inv_dx, gc, blockIdx.x, partials + (int64_t)blockIdx.x * kMeasStride, red);
-}
-
-// Gauss residual of every FP64 pool lattice whose snapshot is due, before
-// it is stepped (the work list holds items of FP64 lattices only).  An item is kGaussPerItem consecutive blocks of the lattice's
-// pass (records as the single-lattice pass writes them).
-template <typename R>
-__global__ void __launch_bounds__(256) k_gauss_batch(const PoolLattice* __restrict__ lat,
-                                                     const WorkItem* __restrict__ work, int nwork)
-{
-    __shared__ double red[16];
-    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-        const WorkItem it = work[w];
-        if (it.lattice < 0) continue;  // an empty item
-        const PoolLattice& L = lat[it.lattice];
-        const int64_t k = L.counter[0];
-        if (!measure_due(L, k)) continue;
-        const int cur = (int)L.counter[2], curm = (int)L.counter[3];
-        const Fields<R> f{(R*)L.pp[cur][0], (R*)L.pp[cur][1], (R*)L.mom[curm][0], (R*)L.mom[curm][1],
-                          (R*)L.pp[cur][2], (R*)L.pp[cur][3], (R*)L.pp[cur][4], (R*)L.mom[curm][2],
-                          (R*)L.mom[curm][3], (R*)L.mom[curm][4]};
-        const double* row = L.coef + k * kCoefStride;
-        const int b1 = min(it.tile + kGaussPerItem, L.gauss_blocks);
-        for (int b = it.tile; b < b1; ++b)
-            gauss_block<R>(f, L.N, L.P, 1.0 / L.dx, row[C_GAUSS], b,
-                           L.partials + (int64_t)(L.meas_blocks + b) * kMeasStride, red);
-    }
-}
-
 // Fold the records of every due lattice into its measurement series (one
 // block per lattice, the same fixed order as the single-lattice fold).
 __global__ void __launch_bounds__(256) k_fold_batch(const PoolLattice* __restrict__ lat, int nlat)
@@ -970,7 +932,7 @@ __global__ void __launch_bounds__(256) k_fold_batch(const PoolLattice* __restric
     const int64_t slot = L.counter[1];
     if (slot >= L.series_cap) return;
     double* out = L.series + slot * kSeriesStride;
-    fold_records(L.partials, L.meas_blocks + L.gauss_blocks, out, red);
+    fold_records(L.partials, L.meas_blocks, out, red);
     if (threadIdx.x == 0) {
         out[M_COUNT] = (double)k;
         L.counter[1] = slot + 1;
@@ -979,8 +941,8 @@ __global__ void __launch_bounds__(256) k_fold_batch(const PoolLattice* __restric
 
 // Advance the counter of every pool lattice that is not finished by what
 // this replay did to it: the final measurement one step; a single step one
-// step and the phi/A buffer, and the Pi/E buffer too if it was an FP32
-// measured step; a two-step pass two steps and both buffers.
+// step and the phi/A buffer, and the Pi/E buffer too if it was a measured
+// step; a two-step pass two steps and both buffers.
 __global__ void k_advance_batch(const PoolLattice* __restrict__ lat, int nlat)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -998,7 +960,7 @@ __global__ void k_advance_batch(const PoolLattice* __restrict__ lat, int nlat)
     } else {
         c[0] = k + 1;
         c[2] ^= 1;
-        if (gauss_in_march(L.precision) && measure_due(L, k)) c[3] ^= 1;
+        if (measure_due(L, k)) c[3] ^= 1;
     }
 }
 
@@ -1009,10 +971,10 @@ hipError_t launch_step_tile(const Fields<R>& in, const Fields<R>& out, const Lat
                             const TileConfig& tc, const MeasConst* mc, double* partials, bool write, hipStream_t s)
 {
     const int N = L.N;
-    // an FP32 measured step reads E of neighbours that other workgroups
-    // update: its Pi and E go to other buffers
-    if (sizeof(R) == 4 && mc && write && (out.pir == in.pir || out.pii == in.pii || out.e0 == in.e0 ||
-                                          out.e1 == in.e1 || out.e2 == in.e2))
+    // a measured step reads E of neighbours that other workgroups update:
+    // its Pi and E go to other buffers
+    if (mc && write && (out.pir == in.pir || out.pii == in.pii || out.e0 == in.e0 || out.e1 == in.e1 ||
+                        out.e2 == in.e2))
         return hipErrorInvalidValue;
     StepArgs<R> a;
     a.f = in;
@@ -1109,26 +1071,6 @@ hipError_t launch_step_batch(const PoolLattice* lat, const WorkItem* work, int n
     }
 #undef AH_BATCH_CASE
     return hipErrorInvalidValue;
-}
-
-int gauss_blocks(int N)
-{
-    const int64_t tiles = (int64_t)((N + 63) / 64) * ((N + 3) / 4);
-    const int zc = gauss_zchunk(N);
-    return (int)(tiles * ((N + zc - 1) / zc));
-}
-
-hipError_t launch_gauss(const Fields<double>& f, const LatticeConst& L, double gc, double* partials, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_gauss<double>, dim3(gauss_blocks(L.N)), dim3(256), 0, s, f, L.N, L.P, 1.0 / L.dx, gc,
-                       partials);
-    return hipGetLastError();
-}
-
-hipError_t launch_gauss_batch(const PoolLattice* lat, const WorkItem* work, int nwork, int grid, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_gauss_batch<double>, dim3(grid), dim3(256), 0, s, lat, work, nwork);
-    return hipGetLastError();
 }
 
 hipError_t launch_fold_batch(const PoolLattice* lat, int nlat, hipStream_t s)

@@ -149,7 +149,7 @@ def _counters(directory, counter):
 
 
 ALGO_PER_SITE = {  # algorithmic bytes per site of one launch
-    ("k_step_tile", "false"): 20, ("k_step2_tile", None): 40, ("k_step_tile", "true"): 10, ("k_gauss", None): 7,
+    ("k_step_tile", "false"): 20, ("k_step2_tile", None): 40, ("k_step_tile", "true"): 10,
 }
 
 

@@ -434,7 +434,7 @@ def test_short_chunks_diagnostics_vs_oracle(oracle_mod, ah, precision, zchunk):
             om = oracle_mod.measure(op, ref, n)
             assert m["winding_sum_abs"] == om["winding_sum_abs"], n
             assert abs(m["energy"] - om["energy"]) <= 1e-9 * om["energy"], n
-    assert max(field_scaled_error(got, ref).values()) <= (1e-12 if precision == "fp64" else 1e-4)
+    assert max(field_scaled_error(got, ref).values()) <= (1e-10 if precision == "fp64" else 1e-4)
 
 
 def test_default_kernel_choice(ah):
@@ -477,22 +477,28 @@ def test_fused_diagnostics_equal_separate_pass(ah, precision):
         assert [m["step"] for m in more] == [25]
 
 
-@pytest.mark.parametrize("kernel,zchunk", [("tile", 0), ("tile", 3), ("tile", 37), ("tile2", 5)])
-def test_fp32_gauss_in_measured_march(oracle_mod, ah, kernel, zchunk):
-    """FP32 lattices form the Gauss residual in the measured march: E_x, E_y of
-    the -x / -y neighbours pass through LDS (the -x column and -y row of the
-    halo included), E_z of the plane below is carried in a register and
-    loaded afresh at each z-chunk's first plane, and a measured step then
-    writes Pi and E into the other buffer.  N = 37 gives ragged x and y tiles;
-    the norms on a Gauss-violating random snapshot against the oracle, the
-    series of measured steps (every step, then every other) against the
-    oracle's norms of its own snapshots, and the fields after them (with a
-    two-step pass between the measured steps 9 and 12 for kernel tile2)."""
+@pytest.mark.parametrize("precision,kernel,tile,zchunk", [
+    ("fp32", "tile", (64, 8), 0), ("fp32", "tile", (64, 8), 3), ("fp32", "tile", (64, 8), 37),
+    ("fp32", "tile2", (64, 8), 5), ("fp64", "tile", (64, 8), 0), ("fp64", "tile", (32, 8), 3),
+    ("fp64", "tile2", (32, 8), 5)])
+def test_gauss_in_measured_march(oracle_mod, ah, precision, kernel, tile, zchunk):
+    """The measured march forms the Gauss residual: E_x, E_y of the -x / -y
+    neighbours (FP32 through LDS with the -x column and -y row of the halo,
+    FP64 loaded with the plane's Pi and E and summed per wave and plane), E_z
+    of the plane below carried in a register and loaded afresh at each
+    z-chunk's first plane; a measured step then writes Pi and E into the
+    other buffer.  N = 37 gives ragged x and y tiles; the norms on a
+    Gauss-violating random snapshot against the oracle, the series of
+    measured steps (every step, then every third) against the oracle's norms
+    of its own snapshots, and the fields after them (with a two-step pass
+    between the measured steps 9 and 12 for kernel tile2)."""
     N = 37
-    op, gp = both_params(oracle_mod, N, "fp32", m=2.0)
-    st = random_state(N, seed=91).astype(np.float32).astype(np.float64)
+    op, gp = both_params(oracle_mod, N, precision, m=2.0)
+    st = random_state(N, seed=91)
+    if precision == "fp32":
+        st = st.astype(np.float32).astype(np.float64)
     with ah.Lattice(gp) as lat:
-        lat.set_step_config(kernel, (64, 8), zchunk)
+        lat.set_step_config(kernel, tile, zchunk)
         lat.set_state(st, 5)
         gm = lat.measure()
         series = lat.step_measured(3, 1) + lat.step_measured(6, 3)
@@ -503,6 +509,9 @@ def test_fp32_gauss_in_measured_march(oracle_mod, ah, kernel, zchunk):
         assert abs(gm[k] - om[k]) <= 1e-11 * abs(om[k]), (k, gm[k], om[k])
     assert [m["step"] for m in series] == [5, 6, 7, 9, 12]
     assert all(series[0][k] == gm[k] for k in ("gauss_rms", "gauss_max", "gauss_rel", "energy"))
+    # FP32: the snapshots differ from the oracle's by FP32 rounding (relative
+    # ~1e-6 after these few steps) and the norms follow them
+    tol = 1e-10 if precision == "fp64" else 1e-4
     ref = st
     for m in series:
         n = m["step"]
@@ -510,9 +519,7 @@ def test_fp32_gauss_in_measured_march(oracle_mod, ah, kernel, zchunk):
             ref = oracle_mod.step(op, ref, prev, n - prev)
         prev = n
         on = oracle_mod.measure(op, ref, n)
-        # the snapshot itself differs from the oracle's by FP32 rounding
-        # (relative ~1e-6 after these few steps); the norms follow it
-        for k in ("gauss_rms", "gauss_rel"):
-            assert abs(m[k] - on[k]) <= 1e-4 * abs(on[k]), (n, k, m[k], on[k])
+        for k in ("gauss_rms", "gauss_max", "gauss_rel"):
+            assert abs(m[k] - on[k]) <= tol * abs(on[k]), (n, k, m[k], on[k])
     ref = oracle_mod.step(op, ref, prev, 14 - prev)
-    assert max(field_scaled_error(got, ref).values()) <= 1e-4
+    assert max(field_scaled_error(got, ref).values()) <= (1e-10 if precision == "fp64" else 1e-4)

@@ -20,12 +20,12 @@ def test_trace_statistics_and_busy_fraction(tmp_path):
         ('"void ah::(anonymous namespace)::k_step2_tile<float, 64, 8>(x)"', 704, 720896, 0, 4_000_000),
         ('"void ah::(anonymous namespace)::k_step2_tile<float, 64, 8>(x)"', 704, 720896, 4_000_000, 8_000_000),
         ('"void ah::(anonymous namespace)::k_step2_tile<float, 64, 8>(x)"', 704, 1408, 8_000_000, 8_500_000),
-        ('"k_gauss<float>(y)"', 256, 262144, 9_000_000, 10_000_000),
+        ('"k_fold_batch(y)"', 256, 16384, 9_000_000, 10_000_000),
     ]
     _write(str(d / "host" / "123" / "run_kernel_trace.csv"),
            ["Kernel_Name", "Workgroup_Size", "Grid_Size", "Start_Timestamp", "End_Timestamp"], rows)
     text = ps.trace(str(d), "note", window="k_step2_tile")
-    assert "k_step2_tile<float, 64, 8>" in text and "k_gauss<float>" in text
+    assert "k_step2_tile<float, 64, 8>" in text and "k_fold_batch" in text
     # one row per launch geometry: the two large launches, then the small one
     lines = [l.split() for l in text.splitlines() if l.startswith("k_step2_tile")]
     assert lines[0][-5:] == ["720896", "2", "4.0000", "4.0000", "4.0000"]
