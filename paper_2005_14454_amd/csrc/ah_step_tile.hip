@@ -85,8 +85,6 @@ struct MeasShared {
     // FP32 lattices: E_x, E_y of plane z (own sites, and the -x / -y halo)
     // for the Gauss residual
     R E[2][sizeof(R) == 4 ? RS : 1];
-    // FP64 lattices: each wave's Gauss sums, added plane by plane
-    double gacc[sizeof(R) == 8 ? TX * TY / 64 : 1][4];
     // FP64 lattices: each thread's running diagnostics sums (kept here rather
     // than in registers, which the FP64 measured march runs out of)
     double acc[kMarchSums][sizeof(R) == 8 ? TX * TY : 1];
@@ -221,8 +219,7 @@ __device__ inline double wave_max(double v)
 // march that steps writes Pi and E out of place (a.opr .. a.oe2).  E_z of the
 // plane below is carried in a register; FP32 passes E_x and E_y of each plane
 // through LDS, FP64 (whose LDS holds two workgroups per CU only without that
-// exchange) loads the two neighbours with the plane's Pi and E and adds each
-// wave's sums of a plane into an LDS slot of the wave.
+// exchange) loads the two neighbours with the plane's Pi and E.
 // All threads of the workgroup call this with the same arguments; it
 // synchronises the workgroup internally.
 template <typename R, int TX, int TY, bool MEAS>
@@ -380,9 +377,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             mx->E[1][ro] = at(f.e1, p0, ob);
             if (halo_e) mx->E[hEc][rh] = at(hE, p0, hb);
         }
-        if constexpr (GAUSS && !GLDS)
-            if ((tid & 63) == 0)
-                for (int k = 0; k < 4; ++k) mx->gacc[tid >> 6][k] = 0.0;
+
         bz_m = cmulc(um[2], phi_m);
         __syncthreads();
         // F_xz, F_yz of the own column at plane z0-1
@@ -507,7 +502,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                 }
             if constexpr (GAUSS && !GLDS) {
                 // FP64: the Gauss residual of the site first, while few values
-                // are live, and the wave's sums of this plane added to its slot
+                // are live
                 double gs[4] = {0.0, 0.0, 0.0, 0.0};
                 if (active) {
                     const double dv = (((double)e_c[0] - (double)ex_xm) * inv_dx64 +
@@ -521,15 +516,10 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                     gs[2] = crho * crho;
                     gs[3] = fabs(G);
                 }
-                const double v0 = wave_sum(gs[0]), v1 = wave_sum(gs[1]), v2 = wave_sum(gs[2]),
-                             v3 = wave_max(gs[3]);
-                if ((tid & 63) == 0) {
-                    double* ga = mx->gacc[tid >> 6];
-                    ga[0] += v0;
-                    ga[1] += v1;
-                    ga[2] += v2;
-                    ga[3] = fmax(ga[3], v3);
-                }
+                g2 += gs[0];
+                d2 += gs[1];
+                c2 += gs[2];
+                gmax = fmax(gmax, gs[3]);
             }
             const Cx<R> ph_xm = sPhi[rxm], ph_xp = sPhi[rxp], ph_ym = sPhi[rym], ph_yp = sPhi[ryp];
             const Cx<R> ux_xm = sU[cur][0][rxm];  // U_x^{x-kx}
@@ -772,15 +762,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
             red[wv][M_NONFIN] = rn;
         }
         if constexpr (GAUSS) {
-            double v[4];
-            if constexpr (GLDS) {
-                v[0] = wave_sum(g2);
-                v[1] = wave_sum(d2);
-                v[2] = wave_sum(c2);
-                v[3] = wave_max(gmax);
-            } else {
-                for (int k = 0; k < 4; ++k) v[k] = mx->gacc[wv][k];  // lane 0's own slot
-            }
+            const double v[4] = {wave_sum(g2), wave_sum(d2), wave_sum(c2), wave_max(gmax)};
             if (lane == 0) {
                 red[wv][M_G2] = v[0];
                 red[wv][M_DIV2] = v[1];
