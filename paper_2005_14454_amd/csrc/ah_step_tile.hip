@@ -212,8 +212,9 @@ __device__ inline double wave_max(double v)
 
 // Walk planes [z0, z1) of the tile whose lower corner is (x0, y0): kick and
 // drift every own site (if `write`), and with MEAS also form the diagnostics of
-// the snapshot being read (section 2 estimators, energy split, windings),
-// writing the workgroup's fixed-order sums to `record`.  The Gauss residual
+// the snapshot being read (section 2 estimators, energy split, windings, the
+// residual of the discrete Gauss law), writing the workgroup's fixed-order
+// sums to `record`.  The Gauss residual
 // reads E at the -x and -y neighbours, which a neighbouring workgroup of a
 // pass that updated E in place could already have overwritten, so a measured
 // march that steps writes Pi and E out of place (a.opr .. a.oe2).  E_z of the
@@ -502,8 +503,7 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                 }
             if constexpr (GAUSS && !GLDS) {
                 // FP64: the Gauss residual of the site first, while few values
-                // are live
-                double gs[4] = {0.0, 0.0, 0.0, 0.0};
+                // are live (FP32 forms it with the other diagnostics below)
                 if (active) {
                     const double dv = (((double)e_c[0] - (double)ex_xm) * inv_dx64 +
                                        ((double)e_c[1] - (double)ey_ym) * inv_dx64) +
@@ -511,15 +511,11 @@ __device__ void march_step(TileShared<R, TX, TY>& sh, MeasShared<R, TX, TY>* mx,
                     const double crho = ma.gauss_c * ((double)phi_c.r * (double)pi_c -
                                                       (double)phi_c.i * (double)pr_c);
                     const double G = dv - crho;
-                    gs[0] = G * G;
-                    gs[1] = dv * dv;
-                    gs[2] = crho * crho;
-                    gs[3] = fabs(G);
+                    g2 += G * G;
+                    d2 += dv * dv;
+                    c2 += crho * crho;
+                    gmax = fmax(gmax, fabs(G));
                 }
-                g2 += gs[0];
-                d2 += gs[1];
-                c2 += gs[2];
-                gmax = fmax(gmax, gs[3]);
             }
             const Cx<R> ph_xm = sPhi[rxm], ph_xp = sPhi[rxp], ph_ym = sPhi[rym], ph_yp = sPhi[ryp];
             const Cx<R> ux_xm = sU[cur][0][rxm];  // U_x^{x-kx}
