@@ -198,34 +198,49 @@ struct SiteOut {
     R fxz, fyz;      // F_xz, F_yz at x (the carry of the plane above)
 };
 
+// Plaquette fields of one site update (each F_ij = sin(Theta_ij) / dx^2):
+// those at x, and at x - kx and x - ky, which are the neighbours' own ones.
 template <typename R>
-__device__ __forceinline__ SiteOut<R> site_update(const SiteCoef<R>& k, const SiteNbr<R>& n, Cx<R> phi_m, Cx<R> phi_c,
-                                                  Cx<R> phi_p, const Cx<R> (&Uc)[3], Cx<R> ux_zp, Cx<R> uy_zp,
-                                                  Cx<R> uz_m, R fxz_m, R fyz_m, R pr_c, R pi_c, const R (&e_c)[3],
-                                                  const R (&a_c)[3])
+struct SiteF {
+    R xy, xz, yz;           // at x
+    R xy_xm, xz_xm;         // at x - kx
+    R xy_ym, yz_ym;         // at x - ky
+};
+
+// The plaquettes a site forms at itself (links of planes z and z+1).
+template <typename R>
+__device__ __forceinline__ void own_plaquettes(const Cx<R> (&Uc)[3], Cx<R> uy_xp, Cx<R> ux_yp, Cx<R> uz_xp,
+                                               Cx<R> uz_yp, Cx<R> ux_zp, Cx<R> uy_zp, R inv_dx2, R* fxy, R* fxz,
+                                               R* fyz)
+{
+    *fxy = plaq_sin(Uc[0], uy_xp, ux_yp, Uc[1]) * inv_dx2;
+    *fxz = plaq_sin(Uc[0], uz_xp, ux_zp, Uc[2]) * inv_dx2;
+    *fyz = plaq_sin(Uc[1], uz_yp, uy_zp, Uc[2]) * inv_dx2;
+}
+
+// Kick and drift of one site from its neighbourhood's phi, the links of the
+// Laplacian and the plaquette fields.
+template <typename R>
+__device__ __forceinline__ SiteOut<R> site_update_f(const SiteCoef<R>& k, Cx<R> ph_xm, Cx<R> ph_xp, Cx<R> ph_ym,
+                                                    Cx<R> ph_yp, Cx<R> ux_xm, Cx<R> uy_ym, Cx<R> phi_m, Cx<R> phi_c,
+                                                    Cx<R> phi_p, const Cx<R> (&Uc)[3], Cx<R> uz_m, const SiteF<R>& F,
+                                                    R fxz_m, R fyz_m, R pr_c, R pi_c, const R (&e_c)[3],
+                                                    const R (&a_c)[3])
 {
     const R inv_dx = k.inv_dx, inv_dx2 = k.inv_dx2;
     // covariant Laplacian: sum_j U_j^x phi^{x+j} + conj(U_j^{x-j}) phi^{x-j} - 2 phi^x
-    const Cx<R> fx = cmul(Uc[0], n.ph_xp), fy = cmul(Uc[1], n.ph_yp), fz = cmul(Uc[2], phi_p);
-    const Cx<R> bx = cmulc(n.ux_xm, n.ph_xm), by = cmulc(n.uy_ym, n.ph_ym), bz = cmulc(uz_m, phi_m);
+    const Cx<R> fx = cmul(Uc[0], ph_xp), fy = cmul(Uc[1], ph_yp), fz = cmul(Uc[2], phi_p);
+    const Cx<R> bx = cmulc(ux_xm, ph_xm), by = cmulc(uy_ym, ph_ym), bz = cmulc(uz_m, phi_m);
     const R lr = ((fx.r + bx.r) + (fy.r + by.r)) + fm(R(-6), phi_c.r, fz.r + bz.r);
     const R li = ((fx.i + bx.i) + (fy.i + by.i)) + fm(R(-6), phi_c.i, fz.i + bz.i);
     // currents J_i = Im[conj(phi) U_i phi^{x+i}] / dx
     const R jx = fm(phi_c.r, fx.i, -(phi_c.i * fx.r)) * inv_dx;
     const R jy = fm(phi_c.r, fy.i, -(phi_c.i * fy.r)) * inv_dx;
     const R jz = fm(phi_c.r, fz.i, -(phi_c.i * fz.r)) * inv_dx;
-    // plaquettes at x, x - kx and x - ky
-    const R fxy = plaq_sin(Uc[0], n.uy_xp, n.ux_yp, Uc[1]) * inv_dx2;
-    const R fxz = plaq_sin(Uc[0], n.uz_xp, ux_zp, Uc[2]) * inv_dx2;
-    const R fyz = plaq_sin(Uc[1], n.uz_yp, uy_zp, Uc[2]) * inv_dx2;
-    const R fxy_xm = plaq_sin(n.ux_xm, Uc[1], n.ux_xm_yp, n.uy_xm) * inv_dx2;
-    const R fxy_ym = plaq_sin(n.ux_ym, n.uy_xp_ym, Uc[0], n.uy_ym) * inv_dx2;
-    const R fxz_xm = plaq_sin(n.ux_xm, Uc[2], n.ux_xm_zp, n.uz_xm) * inv_dx2;
-    const R fyz_ym = plaq_sin(n.uy_ym, Uc[2], n.uy_ym_zp, n.uz_ym) * inv_dx2;
     // lattice curl C_i = sum_{j != i} (F_ij^x - F_ij^{x-j}) / dx, F_ji = -F_ij
-    const R cx = ((fxy - fxy_ym) + (fxz - fxz_m)) * inv_dx;
-    const R cy = ((fyz - fyz_m) - (fxy - fxy_xm)) * inv_dx;
-    const R cz = -((fxz - fxz_xm) + (fyz - fyz_ym)) * inv_dx;
+    const R cx = ((F.xy - F.xy_ym) + (F.xz - fxz_m)) * inv_dx;
+    const R cy = ((F.yz - fyz_m) - (F.xy - F.xy_xm)) * inv_dx;
+    const R cz = -((F.xz - F.xz_xm) + (F.yz - F.yz_ym)) * inv_dx;
     // Crank-Nicolson kick, drift
     const R m2 = fm(phi_c.r, phi_c.r, fm(phi_c.i, phi_c.i, -k.sigma2));
     const R pot = k.lamh * m2;
@@ -239,9 +254,27 @@ __device__ __forceinline__ SiteOut<R> site_update(const SiteCoef<R>& k, const Si
     o.a[0] = fm(k.deta, o.e[0], a_c[0]);
     o.a[1] = fm(k.deta, o.e[1], a_c[1]);
     o.a[2] = fm(k.deta, o.e[2], a_c[2]);
-    o.fxz = fxz;
-    o.fyz = fyz;
+    o.fxz = F.xz;
+    o.fyz = F.yz;
     return o;
+}
+
+// The same update forming all seven plaquettes from the neighbourhood's links.
+template <typename R>
+__device__ __forceinline__ SiteOut<R> site_update(const SiteCoef<R>& k, const SiteNbr<R>& n, Cx<R> phi_m, Cx<R> phi_c,
+                                                  Cx<R> phi_p, const Cx<R> (&Uc)[3], Cx<R> ux_zp, Cx<R> uy_zp,
+                                                  Cx<R> uz_m, R fxz_m, R fyz_m, R pr_c, R pi_c, const R (&e_c)[3],
+                                                  const R (&a_c)[3])
+{
+    const R inv_dx2 = k.inv_dx2;
+    SiteF<R> F;
+    own_plaquettes(Uc, n.uy_xp, n.ux_yp, n.uz_xp, n.uz_yp, ux_zp, uy_zp, inv_dx2, &F.xy, &F.xz, &F.yz);
+    F.xy_xm = plaq_sin(n.ux_xm, Uc[1], n.ux_xm_yp, n.uy_xm) * inv_dx2;
+    F.xy_ym = plaq_sin(n.ux_ym, n.uy_xp_ym, Uc[0], n.uy_ym) * inv_dx2;
+    F.xz_xm = plaq_sin(n.ux_xm, Uc[2], n.ux_xm_zp, n.uz_xm) * inv_dx2;
+    F.yz_ym = plaq_sin(n.uy_ym, Uc[2], n.uy_ym_zp, n.uz_ym) * inv_dx2;
+    return site_update_f(k, n.ph_xm, n.ph_xp, n.ph_ym, n.ph_yp, n.ux_xm, n.uy_ym, phi_m, phi_c, phi_p, Uc, uz_m, F,
+                         fxz_m, fyz_m, pr_c, pi_c, e_c, a_c);
 }
 
 }  // namespace

@@ -32,11 +32,12 @@ def test_pool_alone_vs_mix_bitwise(ah):
         (Params(N=64, precision="fp32", m=1.0), 14, 12, 4),
         (Params(N=20, precision="fp64", m=1.0), 15, 22, 0),
         (Params(N=24, precision="fp32", m=1.0, damp_gamma=3.0, eta_damp=2.05), 16, 28, 7),
-        # FP32 measured steps write Pi and E into the other buffer: every step
-        # measured (the buffer flips each replay), and measured steps between
-        # two-step passes
+        # measured steps write Pi and E into the other buffer: every step
+        # measured (the buffer flips each replay), and FP32 measured steps
+        # between two-step passes
         (Params(N=16, precision="fp32", m=2.0), 17, 9, 1),
         (Params(N=20, precision="fp32", m=1.0), 18, 14, 3),
+        (Params(N=24, precision="fp64", m=2.0), 19, 7, 1),
     ]
     with ah.Pool(hbm_budget=1 << 30, max_slots=16) as pool:
         ids = [pool.submit(p, seed, n, every) for p, seed, n, every in reqs]
