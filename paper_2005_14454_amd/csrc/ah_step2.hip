@@ -254,40 +254,15 @@ __device__ __forceinline__ void march2(Shared2<R, TX, TY>& sh, const Step2Args<R
         __syncthreads();
     }
 
-    // Operands of iteration p, used at its end: A of plane p+2 (stage-1 site
-    // and outer site), phi of plane p+2 (stage-1 site) and p+1 (outer site),
-    // Pi and E of plane p+1 (stage-1 site).  FP64 loads them at the start of
-    // iteration p; FP32, which has the registers, one iteration earlier (the
-    // second set), so that twice as many loads are in flight across the stages.
-    constexpr bool AHEAD = sizeof(R) == 4;
+    // Operands loaded one iteration ahead: A of plane p+2 (stage-1 site and
+    // outer site), phi of plane p+2 (stage-1 site) and p+1 (outer site), Pi
+    // and E of plane p+1 (stage-1 site).
     R na[3] = {0, 0, 0}, noa[3] = {0, 0, 0}, npr = 0, npi = 0, ne[3] = {0, 0, 0};
     Cx<R> nph = {}, noph = {};
-    R na2[3], noa2[3], npr2, npi2, ne2[3];
-    Cx<R> nph2, noph2;
-    auto load_ops = [&](int p, R (&a)[3], R (&oa)[3], R& rpr, R& rpi, R (&re)[3], Cx<R>& rph, Cx<R>& roph) {
-        const int64_t p2 = plane_of(p + 2), p1 = plane_of(p + 1);
-        if (has1) {
-            for (int d = 0; d < 3; ++d) a[d] = A[d][p2 + own_xy];
-            rph = Cx<R>{f.phr[p2 + own_xy], f.phi[p2 + own_xy]};
-            rpr = f.pir[p1 + own_xy];
-            rpi = f.pii[p1 + own_xy];
-            re[0] = f.e0[p1 + own_xy];
-            re[1] = f.e1[p1 + own_xy];
-            re[2] = f.e2[p1 + own_xy];
-        }
-        if (has_out) {
-            for (int d = 0; d < 3; ++d) oa[d] = A[d][p2 + xyo];
-            roph = Cx<R>{f.phr[p1 + xyo], f.phi[p1 + xyo]};
-        }
-    };
-    if constexpr (AHEAD)
-        if (z0 - 1 < z1) load_ops(z0 - 1, na, noa, npr, npi, ne, nph, noph);
 
     for (int p = z0 - 1; p <= z1; ++p) {
         const bool more = p < z1;
-        if constexpr (AHEAD) {
-            if (p + 1 < z1) load_ops(p + 1, na2, noa2, npr2, npi2, ne2, nph2, noph2);
-        } else if (more) {
+        if (more) {
             const int64_t p2 = plane_of(p + 2), p1 = plane_of(p + 1);
             if (has1) {
                 for (int d = 0; d < 3; ++d) na[d] = A[d][p2 + own_xy];
@@ -399,17 +374,6 @@ __device__ __forceinline__ void march2(Shared2<R, TX, TY>& sh, const Step2Args<R
             sh.u0x[sp][co] = link(dx, noa[0]);
             sh.u0y[sp][co] = link(dx, noa[1]);
             uo_z = link(dx, noa[2]);
-        }
-        if constexpr (AHEAD) {
-            for (int d = 0; d < 3; ++d) {
-                na[d] = na2[d];
-                noa[d] = noa2[d];
-                ne[d] = ne2[d];
-            }
-            npr = npr2;
-            npi = npi2;
-            nph = nph2;
-            noph = noph2;
         }
         __syncthreads();
     }
