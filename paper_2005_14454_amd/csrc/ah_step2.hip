@@ -96,10 +96,12 @@ __device__ __forceinline__ SiteNbr<R> gather_nbr(int c, const Cx<R>* ux, const C
 template <int TX, int TY>
 constexpr int kStep2Threads = Geom2<TX, TY>::NTH;
 // Waves per SIMD the register allocation leaves room for: FP64 two (its
-// stage state needs up to 256 registers), FP32 three (168 registers: two
-// 6-wave or one 11-wave workgroup per CU).
+// stage state needs up to 256 registers); FP32 three (168 registers: one
+// 11-wave 64 x 8 or two 7-wave 64 x 4 workgroups per CU), four for the
+// 6-wave 32 x 8 workgroup (128 registers; the pool's instance then spills
+// a few bytes and still runs faster).
 template <typename R, int TX, int TY>
-constexpr int kStep2MinWaves = sizeof(R) == 8 ? 2 : 3;
+constexpr int kStep2MinWaves = sizeof(R) == 8 ? 2 : (Geom2<TX, TY>::NTH <= 384 ? 4 : 3);
 
 // Two steps of planes [z0, z1) of the tile whose lower corner is (x0, y0).
 // All threads of the workgroup call this with the same arguments.
